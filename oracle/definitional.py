@@ -1,0 +1,346 @@
+"""Definitional multislice modularity in exact rational arithmetic (test infrastructure).
+
+This file belongs to the oracle: only tests, the smoke check and the benchmark's CPU
+baseline may use it.  Everything is written straight from the paper's definitions with
+``fractions.Fraction`` and plain loops, for tiny inputs only.
+
+* Supra-adjacency of Eq. 3 (Section 3.1): diagonal blocks A^(t), off-diagonal
+  coupling omega*I between consecutive snapshots (ordinal coupling).
+* Multislice modularity Q_MS of Eq. 6 (Section 3.2), evaluated three independent ways:
+  the literal quadruple sum over (i, j, s, r); the trace form Tr(C^T M C) / 2mu of the
+  supra-modularity matrix (Section 3.2, the paragraph after Eq. 6); and a per-slice
+  component form (intra weight inside communities, sum of squared community degrees,
+  coupled copies kept together).
+* Static Newman modularity (Eq. 5, undirected, so d_out = d_in = k) for T = 1.
+* Closed forms for the all-singleton and one-community partitions.
+* Brute-force maximum over all set partitions of the supra-nodes (n <= 10).
+
+Readings where the paper is silent (all listed with the design notes):
+* 2mu is the total weight of the supra-graph of Eq. 3: sum_s 2m_s + 2*omega*N*(T-1).
+* omega^(sr) = omega when |s - r| = 1 and 0 otherwise (ordinal coupling), omega^(ss) = 0.
+* A snapshot without edges (2m_s = 0) contributes no null-model term.
+* Supra-node (i, s) has index s*N + i (slice-major).
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+from itertools import product
+from math import lcm
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------- inputs
+
+def slice_matrices(g):
+    """Dense symmetric A^(s) (python ints) per slice; repeated pairs add their weights."""
+    n, t = g.n_nodes, g.n_slices
+    mats = []
+    for s in range(t):
+        a = [[0] * n for _ in range(n)]
+        u, x, w = g.slice_edges(s)
+        for e in range(u.size):
+            i, j = int(u[e]), int(x[e])
+            ww = 1 if w is None else int(w[e])
+            a[i][j] += ww
+            a[j][i] += ww
+        mats.append(a)
+    return mats
+
+
+def coupling(s, r, omega):
+    """Ordinal coupling omega^(sr)."""
+    return Fraction(omega) if abs(s - r) == 1 else Fraction(0)
+
+
+def supra_adjacency(g, omega):
+    """Dense A^supra of Eq. 3 as a list of lists of Fractions (order N*T, slice-major)."""
+    n, t = g.n_nodes, g.n_slices
+    mats = slice_matrices(g)
+    size = n * t
+    A = [[Fraction(0)] * size for _ in range(size)]
+    for s in range(t):
+        for i in range(n):
+            for j in range(n):
+                A[s * n + i][s * n + j] = Fraction(mats[s][i][j])
+    for s in range(t):
+        for r in range(t):
+            if s != r:
+                c = coupling(s, r, omega)
+                if c:
+                    for i in range(n):
+                        A[s * n + i][r * n + i] = c
+    return A
+
+
+def degrees(mats):
+    return [[sum(row) for row in a] for a in mats]
+
+
+def two_mu(g, omega):
+    mats = slice_matrices(g)
+    tot = sum(sum(sum(row) for row in a) for a in mats)
+    return Fraction(tot) + 2 * Fraction(omega) * g.n_nodes * (g.n_slices - 1)
+
+
+def _over_two_mu(num, g, omega):
+    """num / 2mu; an empty supra-graph (2mu = 0) has Q = 0 by convention."""
+    tm = two_mu(g, omega)
+    return num / tm if tm else Fraction(0)
+
+
+# --------------------------------------------------------------------------- Eq. 6, three ways
+
+def q_quadruple_sum(g, gamma, omega, membership):
+    """Eq. 6 literally: (1/2mu) sum_{ijsr} [(A_ij^s - gamma k_i^s k_j^s / 2m^s) delta_sr
+    + delta_ij omega^sr] delta(c_i^s, c_j^r)."""
+    n, t = g.n_nodes, g.n_slices
+    gamma, omega = Fraction(gamma), Fraction(omega)
+    mats = slice_matrices(g)
+    k = degrees(mats)
+    twom = [sum(ks) for ks in k]
+    c = np.asarray(membership).reshape(t, n)
+    total = Fraction(0)
+    for i, j, s, r in product(range(n), range(n), range(t), range(t)):
+        if c[s][i] != c[r][j]:
+            continue
+        term = Fraction(0)
+        if s == r:
+            term += mats[s][i][j]
+            if twom[s]:
+                term -= gamma * k[s][i] * k[s][j] / Fraction(twom[s])
+        if i == j:
+            term += coupling(s, r, omega)
+        total += term
+    return _over_two_mu(total, g, omega) 
+
+
+def modularity_matrix(g, gamma, omega):
+    """Supra-modularity matrix: per-slice A - gamma k k^T / 2m blocks, omega couplings off-block."""
+    n, t = g.n_nodes, g.n_slices
+    gamma, omega = Fraction(gamma), Fraction(omega)
+    mats = slice_matrices(g)
+    k = degrees(mats)
+    size = n * t
+    M = [[Fraction(0)] * size for _ in range(size)]
+    for s in range(t):
+        tm = sum(k[s])
+        for i in range(n):
+            for j in range(n):
+                v = Fraction(mats[s][i][j])
+                if tm:
+                    v -= gamma * k[s][i] * k[s][j] / Fraction(tm)
+                M[s * n + i][s * n + j] = v
+    for s in range(t):
+        for r in range(t):
+            if s != r:
+                for i in range(n):
+                    M[s * n + i][r * n + i] += coupling(s, r, omega)
+    return M
+
+
+def q_trace_form(g, gamma, omega, membership):
+    """Tr(C^T M C) / 2mu with C the one-hot community assignment matrix."""
+    M = modularity_matrix(g, gamma, omega)
+    labels = sorted(set(int(x) for x in np.asarray(membership).ravel()))
+    col = {lab: a for a, lab in enumerate(labels)}
+    size = len(M)
+    C = [[0] * len(labels) for _ in range(size)]
+    for u, lab in enumerate(np.asarray(membership).ravel()):
+        C[u][col[int(lab)]] = 1
+    # (C^T M C)_{aa}
+    tr = Fraction(0)
+    for a in range(len(labels)):
+        mc = [sum((M[u][v] for v in range(size) if C[v][a]), Fraction(0)) for u in range(size)]
+        tr += sum((mc[u] for u in range(size) if C[u][a]), Fraction(0))
+    return _over_two_mu(tr, g, omega) 
+
+
+def q_component_form(g, gamma, omega, membership):
+    """Per-slice form: (sum_s [W_s - gamma SS_s / 2m_s] + omega I) / 2mu, where W_s is the
+    intra weight inside communities (both directions), SS_s the sum over communities of
+    the squared slice-s community degree, and I the number of ordered consecutive-slice
+    pairs (i, s), (i, s+-1) that share a community.  Works on edge lists (no dense matrix)."""
+    n, t = g.n_nodes, g.n_slices
+    gamma, omega = Fraction(gamma), Fraction(omega)
+    c = np.asarray(membership).reshape(t, n)
+    num = Fraction(0)
+    for s in range(t):
+        u, x, w = g.slice_edges(s)
+        kdeg = [0] * n
+        W = 0
+        for e in range(u.size):
+            ww = 1 if w is None else int(w[e])
+            a, b = int(u[e]), int(x[e])
+            kdeg[a] += ww
+            kdeg[b] += ww
+            if c[s][a] == c[s][b]:
+                W += 2 * ww
+        tm = sum(kdeg)
+        sig = {}
+        for i in range(n):
+            sig[int(c[s][i])] = sig.get(int(c[s][i]), 0) + kdeg[i]
+        SS = sum(v * v for v in sig.values())
+        num += W
+        if tm:
+            num -= gamma * SS / Fraction(tm)
+    I = 0
+    for s in range(t - 1):
+        I += 2 * int(np.sum(c[s] == c[s + 1]))
+    num += omega * I
+    return _over_two_mu(num, g, omega)
+
+
+def q_newman_static(g, gamma, membership):
+    """Textbook undirected modularity for one snapshot: sum_c [L_c/m - gamma (d_c/2m)^2]."""
+    assert g.n_slices == 1
+    u, x, w = g.slice_edges(0)
+    m = Fraction(0)
+    inside, vol = {}, {}
+    c = np.asarray(membership).ravel()
+    for e in range(u.size):
+        ww = 1 if w is None else int(w[e])
+        a, b = int(u[e]), int(x[e])
+        m += ww
+        vol[int(c[a])] = vol.get(int(c[a]), 0) + ww
+        vol[int(c[b])] = vol.get(int(c[b]), 0) + ww
+        if c[a] == c[b]:
+            inside[int(c[a])] = inside.get(int(c[a]), 0) + ww
+    if m == 0:
+        return Fraction(0)
+    gamma = Fraction(gamma)
+    return sum((Fraction(inside.get(cl, 0)) / m - gamma * (Fraction(vol.get(cl, 0)) / (2 * m)) ** 2
+                for cl in set(int(v) for v in c)), Fraction(0))
+
+
+# --------------------------------------------------------------------------- closed forms
+
+def q_all_singletons(g, gamma, omega):
+    """Every supra-node alone: only the diagonal null terms survive."""
+    mats = slice_matrices(g)
+    k = degrees(mats)
+    num = Fraction(0)
+    for s in range(g.n_slices):
+        tm = sum(k[s])
+        if tm:
+            num -= Fraction(gamma) * sum(x * x for x in k[s]) / Fraction(tm)
+    return _over_two_mu(num, g, omega)
+
+
+def q_one_community(g, gamma, omega):
+    """All supra-nodes together: [(1 - gamma) sum_s 2m_s + 2 omega N (T-1)] / 2mu."""
+    mats = slice_matrices(g)
+    tot = sum(sum(sum(row) for row in a) for a in mats)
+    num = (1 - Fraction(gamma)) * tot + 2 * Fraction(omega) * g.n_nodes * (g.n_slices - 1)
+    return _over_two_mu(num, g, omega)
+
+
+# --------------------------------------------------------------------------- brute force
+
+def brute_force_max(g, gamma, omega):
+    """Maximum Q over every set partition of the N*T supra-nodes (restricted growth strings).
+
+    Returns (Q*, list of optimal memberships).  Sizes up to 10 supra-nodes (Bell(10) = 115975).
+    """
+    M = modularity_matrix(g, gamma, omega)
+    size = len(M)
+    assert size <= 10, "brute force is for tiny graphs only"
+    L = 1
+    for row in M:
+        for v in row:
+            L = lcm(L, v.denominator)
+    Mi = [[int(v * L) for v in row] for row in M]
+    best = [None, []]
+    assign = [0] * size
+    blocks: list[list[int]] = []
+
+    def rec(u, acc):
+        if u == size:
+            if best[0] is None or acc > best[0]:
+                best[0], best[1] = acc, [assign.copy()]
+            elif acc == best[0]:
+                best[1].append(assign.copy())
+            return
+        for b in range(len(blocks) + 1):
+            if b == len(blocks):
+                blocks.append([])
+            add = Mi[u][u] + 2 * sum(Mi[u][v] for v in blocks[b])
+            blocks[b].append(u)
+            assign[u] = b
+            rec(u + 1, acc + add)
+            blocks[b].pop()
+            if not blocks[b]:
+                blocks.pop()
+
+    rec(0, 0)
+    return _over_two_mu(Fraction(best[0], L), g, omega), best[1]
+
+
+# --------------------------------------------------------------------------- invariant helpers
+
+def supra_edges(g, omega):
+    """Undirected supra-edges (u, v, weight) of Eq. 3 with duplicates merged (omega > 0 adds
+    the coupling edges)."""
+    n, t = g.n_nodes, g.n_slices
+    acc = {}
+    for s in range(t):
+        u, x, w = g.slice_edges(s)
+        for e in range(u.size):
+            a, b = s * n + int(u[e]), s * n + int(x[e])
+            key = (min(a, b), max(a, b))
+            acc[key] = acc.get(key, 0) + (1 if w is None else int(w[e]))
+    out = [(a, b, Fraction(ww)) for (a, b), ww in acc.items()]
+    if Fraction(omega) != 0:
+        for s in range(t - 1):
+            for i in range(n):
+                out.append((s * n + i, (s + 1) * n + i, Fraction(omega)))
+    return out
+
+
+def communities_connected(g, omega, membership):
+    """True when every community induces a connected subgraph of the supra-graph."""
+    size = g.n_supra
+    c = np.asarray(membership).ravel()
+    adj = [[] for _ in range(size)]
+    for a, b, _ in supra_edges(g, omega):
+        if c[a] == c[b]:
+            adj[a].append(b)
+            adj[b].append(a)
+    seen = [False] * size
+    comps_per_label = {}
+    for v in range(size):
+        if seen[v]:
+            continue
+        comps_per_label[int(c[v])] = comps_per_label.get(int(c[v]), 0) + 1
+        stack = [v]
+        seen[v] = True
+        while stack:
+            x = stack.pop()
+            for y in adj[x]:
+                if not seen[y]:
+                    seen[y] = True
+                    stack.append(y)
+    return all(k == 1 for k in comps_per_label.values())
+
+
+def improving_single_moves(g, gamma, omega, membership):
+    """All (supra-node, target) pairs whose move raises Q strictly (targets: communities of
+    neighbours, and a fresh empty community).  Evaluated by recomputing Q exactly."""
+    c = np.asarray(membership).ravel().copy()
+    base = q_component_form(g, gamma, omega, c)
+    nbr = [set() for _ in range(g.n_supra)]
+    for a, b, _ in supra_edges(g, omega):
+        nbr[a].add(b)
+        nbr[b].add(a)
+    fresh = int(c.max()) + 1
+    found = []
+    for v in range(g.n_supra):
+        targets = {int(c[x]) for x in nbr[v]} | {fresh}
+        targets.discard(int(c[v]))
+        for tgt in sorted(targets):
+            old = c[v]
+            c[v] = tgt
+            if q_component_form(g, gamma, omega, c) > base:
+                found.append((v, tgt))
+            c[v] = old
+    return found
