@@ -1,0 +1,166 @@
+/*
+ * mslm — exact multislice-modularity Leiden on one AMD MI355X (gfx950).
+ *
+ * The operation: community detection in a snapshot temporal network by Leiden optimisation
+ * (local moving, refinement, aggregation) of the multislice modularity Q_MS of Eq. 6
+ * (Section 3.2) on the supra-graph of Eq. 3 (Section 3.1): T snapshots over the same N
+ * node ids, supra-node (i, s) numbered v = s*N + i, intra-snapshot edges on the diagonal
+ * blocks and an ordinal coupling omega between (i, s) and (i, s+1) for every node i.
+ * Resolution gamma and coupling omega are exact fractions; all arithmetic is integer or
+ * exact rational, so results are bit-for-bit reproducible and independent of batching.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: MSLM_OK or a negative mslm_status; mslm_last_error() gives the text.
+ *     On error outputs are left untouched and a valid handle stays valid.
+ *   - Host pointers unless a flag says device.  Inputs are copied; the caller keeps
+ *     ownership of everything it passes and may free it on return.
+ *   - Streams: device work runs on the hipStream_t given at creation (NULL = default
+ *     stream).  Calls return after their outputs are written.
+ *   - A handle is used by one thread at a time; distinct handles are independent.
+ */
+#ifndef MSLM_H
+#define MSLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MSLM_OK = 0,
+  MSLM_EINVAL = -1,       /* invalid argument or malformed graph                        */
+  MSLM_ENOMEM = -2,       /* device or host allocation failed                           */
+  MSLM_EOVERFLOW = -3,    /* exact integer head-room precondition violated              */
+  MSLM_EUNSUPPORTED = -4, /* outside this version's limits (T > 64, N*T >= 2^27 * 0.97) */
+  MSLM_EHIP = -5,         /* HIP runtime error                                          */
+  MSLM_EBUSY = -6         /* server: result not ready before the timeout                */
+} mslm_status;
+
+typedef struct mslm_graph mslm_graph;   /* owns the device supra-CSR of one temporal graph */
+typedef struct mslm_server mslm_server; /* continuous-batching request loop               */
+
+enum { MSLM_INPUT_ON_DEVICE = 1u, MSLM_OUTPUT_ON_DEVICE = 2u, MSLM_PROFILE = 4u };
+
+/* One temporal graph.  Slice s holds edges [slice_offsets[s], slice_offsets[s+1]) of
+ * src/dst/weight: undirected, each edge listed once in either orientation, ids in [0, N),
+ * no self-loops, weight >= 1 (NULL = unit weights).  Repeated pairs inside a slice add
+ * their weights.  slice_offsets is always host memory; src/dst/weight are device
+ * pointers when flags has MSLM_INPUT_ON_DEVICE.  Limits: 1 <= T <= 64, N >= 1,
+ * N*T*33 < 2^32, every slice's total degree 2m_s < 2^31. */
+typedef struct {
+  int32_t n_nodes;
+  int32_t n_slices;
+  const int64_t *slice_offsets;
+  const int32_t *src;
+  const int32_t *dst;
+  const int32_t *weight;
+  int64_t omega_num, omega_den;   /* default coupling omega = num/den, num >= 0, den >= 1 */
+  uint32_t flags;
+} mslm_graph_desc;
+
+/* One solve.  gamma = gamma_num/gamma_den (num >= 0, den >= 1).  omega_den == 0 keeps the
+ * graph's default coupling.  max_levels >= 1 bounds the aggregation levels of one Leiden
+ * iteration; max_iterations <= 0 runs iterations until the partition is stable (at most
+ * 32); max_sweeps <= 0 means 32 local-moving sweeps per level.  The seed only changes the
+ * hash priorities of the schedule.  Numerators and denominators must be below 2^31. */
+typedef struct {
+  int64_t gamma_num, gamma_den;
+  int64_t omega_num, omega_den;
+  int32_t max_levels;
+  int32_t max_iterations;
+  int32_t max_sweeps;
+  int32_t reserved0;
+  uint64_t seed;
+  uint32_t flags;                 /* MSLM_OUTPUT_ON_DEVICE: membership is a device pointer;
+                                     MSLM_PROFILE: time every local-moving decision kernel */
+  uint32_t reserved1;
+} mslm_params;
+
+/* Per-solve outcome.  q_components (3T+1 int64) are the exact integer pieces of Q:
+ * W_s (weight inside communities in slice s, both directions), SS_s (sum over communities
+ * of the squared slice-s degree), 2m_s, and I (ordered coupled copy pairs sharing a
+ * community); mslm_q_exact turns them into the reduced fraction Q. */
+typedef struct {
+  double q;                       /* Q rounded to double                                    */
+  int32_t n_communities, levels_run, iterations_run, colours_level0;
+  int64_t sweeps, moves, sweep_cap_hits, refine_rounds, merges, splits, exact_fallbacks;
+  double ms_total;                /* host wall clock of the call                            */
+  double ms_colour, ms_local_move, ms_refine, ms_aggregate, ms_finish;   /* device, by phase */
+  double lm_kernel_ms;            /* summed durations of the local-moving decision kernels,
+                                     measured only with MSLM_PROFILE                        */
+  int64_t lm_launches;            /* number of those kernel launches (MSLM_PROFILE)          */
+  int64_t lm_units, lm_entries, lm_candidates;   /* work of those kernels: units decided,
+                                     adjacency entries scanned, candidate communities (PROFILE) */
+  int64_t q_components[3 * 64 + 1];
+} mslm_result;
+
+/* Build the device supra-CSR (Eq. 3) of a temporal graph: both directions of every intra
+ * edge with repeated pairs summed, plus the coupling entries (i,s)<->(i,s+1) for all i.
+ * *out is NULL on failure.  Errors: EINVAL (ids, self-loops, weights, sizes), EOVERFLOW
+ * (2m_s >= 2^31), EUNSUPPORTED (T > 64 or N*T too large), ENOMEM, EHIP. */
+mslm_status mslm_create(const mslm_graph_desc *desc, void *hip_stream, mslm_graph **out);
+
+/* Run the deterministic Leiden schedule on a resident graph (Section 3.2, Eq. 6).
+ * membership[T*N] receives the community of supra-node v = s*N + i, labelled 0..K-1 in
+ * order of first appearance; every community is connected.  res may be NULL.
+ * Errors: EINVAL (parameters), EOVERFLOW (int64 gain head-room: q*2m_s*w and p*b*k*Sigma
+ * must stay below 2^62), ENOMEM, EHIP. */
+mslm_status mslm_leiden(mslm_graph *g, const mslm_params *params, int32_t *membership,
+                        mslm_result *res);
+
+/* Release a graph handle and its device memory.  NULL is allowed. */
+void mslm_destroy(mslm_graph *g);
+
+/* Exact Q of Eq. 6 from the 3T+1 components, as a reduced fraction written in decimal
+ * into num/den (NUL-terminated).  Errors: EINVAL (buffers too small, den <= 0). */
+mslm_status mslm_q_exact(const int64_t *q_components, int32_t n_slices, int32_t n_nodes,
+                         int64_t gamma_num, int64_t gamma_den, int64_t omega_num,
+                         int64_t omega_den, char *num, size_t num_cap, char *den, size_t den_cap);
+
+/* Device bytes a graph and one solve on it need (admission estimate). */
+size_t mslm_footprint_bytes(const mslm_graph_desc *desc);
+
+/* Graph sizes: supra-nodes, directed CSR entries (coupling entries included). */
+mslm_status mslm_graph_info(const mslm_graph *g, int64_t *n_supra, int64_t *nnz, int64_t *two_m);
+
+/* Text of the last error on this thread (valid until the next call on this thread). */
+const char *mslm_last_error(void);
+
+/* ------------------------------------------------------------------ batching */
+/* Many solves (graph x gamma x omega) run as one disjoint-union solve: every kernel launch
+ * covers all solves that are still active, and each solve's result is bit-identical to a
+ * plain mslm_leiden call with the same graph and parameters (the schedule only ever
+ * compares units of the same solve, and priorities use solve-local ids). */
+typedef struct {
+  int32_t graph;                  /* index into graphs[]                                    */
+  int32_t reserved;
+  mslm_params params;
+  int32_t *membership;            /* host [T*N] of that graph                               */
+  mslm_result *result;            /* may be NULL                                            */
+} mslm_solve;
+
+mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs,
+                              const mslm_solve *solves, int32_t n_solves, void *hip_stream);
+
+/* ------------------------------------------------------------------ serving */
+/* A request loop that admits clustering requests while the device-memory footprint of
+ * admitted work stays within hbm_budget_bytes and at most max_slots requests are in
+ * flight.  Requests that arrive while others run are admitted as room frees up and run
+ * concurrently on their own streams.  Results equal plain mslm_create + mslm_leiden. */
+mslm_status mslm_server_create(size_t hbm_budget_bytes, int32_t max_slots, mslm_server **out);
+/* Copies the graph (host pointers only) and queues it.  EINVAL if the request alone exceeds
+ * the budget. */
+mslm_status mslm_server_submit(mslm_server *s, const mslm_graph_desc *desc,
+                               const mslm_params *params, uint64_t *ticket);
+/* Waits up to timeout_ms (< 0: forever) for a ticket; EBUSY on timeout.  latency_s is the
+ * time from submit to completion. */
+mslm_status mslm_server_wait(mslm_server *s, uint64_t ticket, int32_t timeout_ms,
+                             int32_t *membership, mslm_result *res, double *latency_s);
+void mslm_server_destroy(mslm_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSLM_H */

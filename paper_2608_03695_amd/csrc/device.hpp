@@ -1,0 +1,272 @@
+// Device building blocks of the multislice Leiden path for gfx950 (CDNA4, wave64).
+//
+//  * priority hash (SplitMix64 output function, Steele-Lea-Flood 2014) for colouring and
+//    refinement eligibility;
+//  * the slice-partitioned community-degree table Sigma[(C, s)] (Eq. 6's per-slice null
+//    model needs the total slice-s degree of every community): one open-addressing
+//    sub-table per slice so that a colour batch, processed in slice-major order, touches
+//    one slice's sub-table at a time (it stays resident in L2 / Infinity Cache);
+//  * per-wave LDS accumulation tables for neighbour-community weights;
+//  * exact comparison of multi-slice gains: a double filter with a rigorous error bound,
+//    then fixed-width two's-complement big integers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mslm {
+
+constexpr uint32_t kNone = 0xffffffffu;   // "no label" / the empty-community sentinel
+constexpr int kMaxSlices = 64;
+
+// ------------------------------------------------------------------ hashing
+
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// seedmix = mix64(seed); key packs the solve-local unit id, phase, level and iteration.
+__host__ __device__ inline uint64_t priority(uint64_t seedmix, int it, int lvl, int phase,
+                                            uint32_t local) {
+  uint64_t key = (uint64_t)local | ((uint64_t)phase << 32) | ((uint64_t)lvl << 40) |
+                 ((uint64_t)it << 48);
+  return mix64(key ^ seedmix);
+}
+
+// (h_u, u) > (h_v, v) lexicographically
+__device__ inline bool outranks(uint64_t hu, uint32_t u, uint64_t hv, uint32_t v) {
+  return hu > hv || (hu == hv && u > v);
+}
+
+__host__ __device__ inline uint32_t fib_hash(uint32_t x, int shift) {
+  return (uint32_t)((x * 2654435769u) >> shift);
+}
+
+// ------------------------------------------------------------------ wave helpers
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline int64_t shfl_xor64(int64_t v, int m) { return __shfl_xor(v, m, 64); }
+__device__ inline uint32_t shfl_xor32(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m, 64); }
+
+__device__ inline int64_t wave_sum64(int64_t v) {
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
+  return v;
+}
+
+// ------------------------------------------------------------------ Sigma table
+// Slot layout: 64-bit word, low half = key (label + 1, 0 = empty), high half = value.
+// Values are slice degrees (< 2^31 by the create-time precondition).
+
+struct SliceTable {
+  uint64_t *slots;
+  const int64_t *base;     // [slices] first slot of the slice's sub-table
+  const int32_t *shift;    // [slices] 32 - log2(capacity)
+  uint32_t *used;          // [slices] keys claimed (for the rebuild rule)
+};
+
+__device__ inline int32_t tab_get(const SliceTable &t, int s, uint32_t label) {
+  const int sh = t.shift[s];
+  const uint32_t mask = 0xffffffffu >> sh;
+  const uint64_t *sub = t.slots + t.base[s];
+  const uint32_t key = label + 1;
+  uint32_t h = fib_hash(label, sh);
+  for (;;) {
+    uint64_t e = sub[h];
+    uint32_t k = (uint32_t)e;
+    if (k == key) return (int32_t)(e >> 32);
+    if (k == 0) return 0;
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ inline void tab_add(const SliceTable &t, int s, uint32_t label, int32_t delta) {
+  const int sh = t.shift[s];
+  const uint32_t mask = 0xffffffffu >> sh;
+  uint64_t *sub = t.slots + t.base[s];
+  const uint32_t key = label + 1;
+  uint32_t h = fib_hash(label, sh);
+  for (;;) {
+    uint32_t *kp = reinterpret_cast<uint32_t *>(sub + h);
+    uint32_t k = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k == 0) {
+      uint32_t prev = atomicCAS(kp, 0u, key);
+      if (prev == 0) {
+        atomicAdd(t.used + s, 1u);
+        k = key;
+      } else {
+        k = prev;
+      }
+    }
+    if (k == key) {
+      atomicAdd(reinterpret_cast<int32_t *>(kp) + 1, delta);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+// ------------------------------------------------------------------ LDS accumulation
+// Open addressing over a power-of-two table in LDS; keys are label + 1.
+
+__device__ inline void lds_add(uint32_t *K, int64_t *V, int lg, uint32_t label, int64_t w) {
+  const uint32_t key = label + 1, mask = (1u << lg) - 1;
+  uint32_t h = fib_hash(label, 32 - lg);
+  for (;;) {
+    uint32_t prev = atomicCAS(&K[h], 0u, key);
+    if (prev == 0 || prev == key) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(&V[h]), (unsigned long long)w);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ inline int64_t lds_get(const uint32_t *K, const int64_t *V, int lg, uint32_t label) {
+  const uint32_t key = label + 1, mask = (1u << lg) - 1;
+  uint32_t h = fib_hash(label, 32 - lg);
+  for (;;) {
+    uint32_t k = K[h];
+    if (k == key) return V[h];
+    if (k == 0) return 0;
+    h = (h + 1) & mask;
+  }
+}
+
+// global-memory version for units whose neighbourhood exceeds the LDS table
+__device__ inline void gtab_add(uint32_t *K, int64_t *V, uint32_t mask, int shift, uint32_t label,
+                                int64_t w) {
+  const uint32_t key = label + 1;
+  uint32_t h = fib_hash(label, shift);
+  for (;;) {
+    uint32_t prev = atomicCAS(&K[h], 0u, key);
+    if (prev == 0 || prev == key) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(&V[h]), (unsigned long long)w);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ inline int64_t gtab_get(const uint32_t *K, const int64_t *V, uint32_t mask, int shift,
+                                   uint32_t label) {
+  const uint32_t key = label + 1;
+  uint32_t h = fib_hash(label, shift);
+  for (;;) {
+    uint32_t k = K[h];
+    if (k == key) return V[h];
+    if (k == 0) return 0;
+    h = (h + 1) & mask;
+  }
+}
+
+// ------------------------------------------------------------------ solve coefficients
+// gamma = p/q, omega = a/b reduced; scaled weights: intra b*w, coupling a.
+// Gains are ordered through   q*W - p*b * sum_s k_s * y_s / S_s   (S_s = 2m_s or 1).
+struct Coef {
+  int64_t p, q, a, b, pb;
+  const int64_t *S;        // [slices] device
+};
+
+// ------------------------------------------------------------------ exact comparison
+// Fixed-width two's-complement integers of kLimbs 32-bit limbs (2304 bits): enough for
+// q*W*prod(S) with 64 slice denominators below 2^31 plus the summed null terms.
+constexpr int kLimbs = 72;
+
+struct Big {
+  uint32_t d[kLimbs];
+};
+
+__device__ inline void big_set(Big &x, int64_t v) {
+  uint32_t ext = v < 0 ? 0xffffffffu : 0u;
+  x.d[0] = (uint32_t)v;
+  x.d[1] = (uint32_t)((uint64_t)v >> 32);
+  for (int i = 2; i < kLimbs; i++) x.d[i] = ext;
+}
+__device__ inline void big_mul_u32(Big &x, uint32_t m) {
+  uint64_t c = 0;
+  for (int i = 0; i < kLimbs; i++) {
+    uint64_t t = (uint64_t)x.d[i] * m + c;
+    x.d[i] = (uint32_t)t;
+    c = t >> 32;
+  }
+}
+__device__ inline void big_add(Big &x, const Big &y) {
+  uint64_t c = 0;
+  for (int i = 0; i < kLimbs; i++) {
+    uint64_t t = (uint64_t)x.d[i] + y.d[i] + c;
+    x.d[i] = (uint32_t)t;
+    c = t >> 32;
+  }
+}
+__device__ inline void big_neg(Big &x) {
+  uint64_t c = 1;
+  for (int i = 0; i < kLimbs; i++) {
+    uint64_t t = (uint64_t)(~x.d[i]) + c;
+    x.d[i] = (uint32_t)t;
+    c = t >> 32;
+  }
+}
+// x *= m for any int64 m (the product is taken modulo 2^2304; callers stay in range)
+__device__ inline void big_mul_i64(Big &x, int64_t m) {
+  bool neg = m < 0;
+  uint64_t u = neg ? (uint64_t)0 - (uint64_t)m : (uint64_t)m;
+  Big hi = x;
+  big_mul_u32(x, (uint32_t)u);
+  big_mul_u32(hi, (uint32_t)(u >> 32));
+  // x += hi << 32
+  uint64_t c = 0;
+  for (int i = 1; i < kLimbs; i++) {
+    uint64_t t = (uint64_t)x.d[i] + hi.d[i - 1] + c;
+    x.d[i] = (uint32_t)t;
+    c = t >> 32;
+  }
+  if (neg) big_neg(x);
+}
+__device__ inline int big_sign(const Big &x) {
+  if (x.d[kLimbs - 1] >> 31) return -1;
+  for (int i = 0; i < kLimbs; i++)
+    if (x.d[i]) return 1;
+  return 0;
+}
+
+// Streaming evaluator of  q*Wd*Pi - pb*sum_j c_j/S_j * Pi  where Pi is the product of the
+// denominators of the terms fed in (terms with c_j == 0 are skipped entirely).
+struct ExactAcc {
+  Big num, den;
+  __device__ void init() {
+    big_set(num, 0);
+    big_set(den, 1);
+  }
+  __device__ void term(int64_t c, int64_t S) {
+    if (c == 0) return;
+    // num/den + c/S = (num*S + c*den) / (den*S)
+    Big t = den;
+    big_mul_i64(t, c);
+    big_mul_i64(num, S);
+    big_add(num, t);
+    big_mul_i64(den, S);
+  }
+  __device__ int sign(int64_t q, int64_t Wd, int64_t pb) {
+    Big lhs = den;
+    big_mul_i64(lhs, q);
+    big_mul_i64(lhs, Wd);
+    big_mul_i64(num, pb);
+    big_neg(num);
+    big_add(lhs, num);
+    return big_sign(lhs);
+  }
+};
+
+// Double-precision estimate of  q*W - pb * sum_j c_j / S_j  with a rigorous bound on its
+// error: every int64 -> double conversion, division, product and addition contributes at
+// most one half-ulp, so (m + 8) * 2^-50 * (|q*W| + pb * sum |c_j| / S_j) is a safe cover.
+struct Approx {
+  double val, err;
+};
+
+}  // namespace mslm

@@ -1,0 +1,280 @@
+// Host driver of the deterministic multislice Leiden schedule (Section 3.2, Eq. 6).
+//
+// One call runs one or more solves as a disjoint union: every kernel launch covers all
+// solves that are still active, and per-solve control (sweep convergence, level breaks,
+// iteration stability) is applied from per-solve counters, so each solve follows exactly
+// the schedule it would follow alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "engine.hpp"
+#include "kernels.hpp"
+#include "prims.hpp"
+
+namespace mslm {
+
+namespace {
+
+constexpr int kBS = 256;
+
+inline unsigned nblk(int64_t n, int bs = kBS) {
+  int64_t b = (n + bs - 1) / bs;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 0x7fffffff));
+}
+inline unsigned nblk_cap(int64_t n, int64_t cap, int bs = kBS) {
+  int64_t b = (n + bs - 1) / bs;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+inline unsigned wblk(int64_t units) { return nblk(units, 4); }
+
+int bits_for(uint64_t x) {
+  int b = 1;
+  while (b < 64 && (1ull << b) <= x) b++;
+  return b;
+}
+
+template <class T>
+void fill(T *p, T val, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill<T><<<nblk_cap(n, 65536), kBS, 0, st>>>(p, val, n);
+}
+
+template <class T>
+void h2d(T *dst, const T *src, int64_t n, hipStream_t st) {
+  if (n > 0) MSLM_HIP(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyHostToDevice, st));
+}
+template <class T>
+void d2h(T *dst, const T *src, int64_t n, hipStream_t st) {
+  if (n > 0) MSLM_HIP(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyDeviceToHost, st));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ workspace
+struct LevelBufs {
+  Buf rp, col, w, pp, ps, pk, usolve;
+};
+
+struct Workspace {
+  Buf temp;
+  // union level 0
+  Buf u_rp, u_col, u_w, u_k, u_uslice, u_usolve, u_sstart;
+  // per solve / per slice
+  Buf s_p, s_q, s_pb, s_a, s_b, s_seed, s_uoff, s_sfirst, s_slast, s_S, s_frozen, s_cnt, s_cnt2;
+  Buf fallbacks;
+  // state
+  Buf pcur, pnew, comm, comm2, map0, pflat, parent, isroot, rank0;
+  Buf colour, work0, work1, nwork, bkeys, bvals, bkeys2, bvals2, hist, target;
+  Buf gk, gv, goff, glg;
+  Buf sig_slots, sig_base, sig_shift, sig_used, sig_limit, sr_slots, sr_used, flag;
+  Buf R, ext, mask, active, wcT, elig, changed, clist, ccount, prop, propw;
+  Buf r, minm, flag8, rank, akeys, avals, akeys2, avals2, nuniq, rowcnt, pkeys, pvals, pkeys2,
+      pvals2, pnext;
+  Buf ckeys, cvals, ckeys2, cvals2, head, ismin, segx, minof, crank;
+  Buf qW, qSS, qI, ranges_lo, ranges_hi, ranges_off;
+  LevelBufs lvA, lvB;
+  std::vector<hipEvent_t> evpool;
+};
+
+Workspace *workspace_new() { return new Workspace(); }
+void workspace_free(Workspace *ws) {
+  if (!ws) return;
+  for (auto e : ws->evpool) (void)hipEventDestroy(e);
+  delete ws;
+}
+
+static void *temp_get(void *ctx, size_t bytes) {
+  return static_cast<Workspace *>(ctx)->temp.ensure(bytes);
+}
+
+static TempAlloc temp_alloc(Workspace *ws) { return TempAlloc{temp_get, ws}; }
+
+#define MSLM_PRIM(call) MSLM_HIP(call)
+
+// ------------------------------------------------------------------ graph build (Eq. 3)
+namespace {
+
+__global__ void k_build_validate(const int32_t *src, const int32_t *dst, const int32_t *w,
+                                 int64_t E, int32_t N, int *bad) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  int32_t u = src[e], x = dst[e];
+  if (u < 0 || u >= N || x < 0 || x >= N || u == x || (w && w[e] < 1)) atomicOr(bad, 1);
+}
+
+// every intra edge in both directions, keyed (row, col); the slice comes from the offsets
+__global__ void k_build_intra(const int32_t *src, const int32_t *dst, const int32_t *w,
+                              const int64_t *off, int32_t T, int32_t N, int64_t E,
+                              uint64_t *keys, int64_t *vals) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  int lo = 0, hi = T;   // off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid;
+  }
+  int64_t base = (int64_t)lo * N;
+  uint64_t u = (uint64_t)(base + src[e]), x = (uint64_t)(base + dst[e]);
+  int64_t ww = w ? w[e] : 1;
+  keys[2 * e] = (u << 32) | x;
+  vals[2 * e] = ww;
+  keys[2 * e + 1] = (x << 32) | u;
+  vals[2 * e + 1] = ww;
+}
+
+// coupling entries (i,s)<->(i,s+1) for every node i, raw weight 0 (scaled by a at use)
+__global__ void k_build_inter(int32_t N, int32_t T, uint64_t *keys, int64_t *vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t m = (int64_t)N * (T - 1);
+  if (i >= m) return;
+  uint64_t v = (uint64_t)i, x = (uint64_t)(i + N);
+  keys[2 * i] = (v << 32) | x;
+  vals[2 * i] = 0;
+  keys[2 * i + 1] = (x << 32) | v;
+  vals[2 * i + 1] = 0;
+}
+
+__global__ void k_build_csr(const uint64_t *keys, const int64_t *vals, int64_t m, int32_t *col,
+                            int32_t *w, int64_t *rowcnt, int *nonunit) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint64_t k = keys[i];
+  col[i] = (int32_t)(uint32_t)k;
+  int64_t v = vals[i];
+  w[i] = (int32_t)v;
+  if (v > 1) atomicOr(nonunit, 1);
+  atomicAdd(reinterpret_cast<unsigned long long *>(rowcnt + (k >> 32)), 1ull);
+}
+
+__global__ void k_build_degree(const int64_t *rp, const int32_t *col, const int32_t *w, int64_t n,
+                               int32_t N, int32_t *kdeg, int64_t *twom, int64_t *nz) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int64_t s = v / N, lo = s * N, hi = lo + N;
+  int64_t d = 0;
+  for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+    int32_t x = col[e];
+    if (x >= lo && x < hi) d += w[e];
+  }
+  kdeg[v] = (int32_t)(d < 0x7fffffff ? d : 0x7fffffff);
+  if (d) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(twom + s), (unsigned long long)d);
+    atomicAdd(reinterpret_cast<unsigned long long *>(nz + s), 1ull);
+  }
+}
+
+__global__ void k_max_degree(const int64_t *rp, int64_t n, int *mx) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicMax(mx, (int)std::min<int64_t>(rp[v + 1] - rp[v], 0x7fffffff));
+}
+
+}  // namespace
+
+void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspace *ws) {
+  const int32_t N = d.n_nodes, T = d.n_slices;
+  const int64_t E = d.slice_offsets[T];
+  const int64_t n = (int64_t)N * T;
+  const int64_t ninter = (int64_t)N * (T - 1);
+  const int64_t mraw = 2 * E + 2 * ninter;
+  const bool on_dev = d.flags & MSLM_INPUT_ON_DEVICE;
+  g.N = N;
+  g.T = T;
+  g.n = n;
+  // edge lists on the device
+  Buf dsrc, ddst, dw, doff;
+  const int32_t *src = d.src, *dst = d.dst, *w = d.weight;
+  if (!on_dev) {
+    src = dsrc.get<int32_t>(E);
+    dst = ddst.get<int32_t>(E);
+    h2d(const_cast<int32_t *>(src), d.src, E, st);
+    h2d(const_cast<int32_t *>(dst), d.dst, E, st);
+    if (d.weight) {
+      w = dw.get<int32_t>(E);
+      h2d(const_cast<int32_t *>(w), d.weight, E, st);
+    }
+  }
+  int64_t *off = doff.get<int64_t>(T + 1);
+  h2d(off, d.slice_offsets, T + 1, st);
+  if (on_dev && E > 0) {   // host validation covers host inputs; device inputs are checked here
+    int *bad = ws->flag.get<int>(1);
+    MSLM_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    k_build_validate<<<nblk(E), kBS, 0, st>>>(src, dst, w, E, N, bad);
+    int hbad = 0;
+    d2h(&hbad, bad, 1, st);
+    MSLM_HIP(hipStreamSynchronize(st));
+    if (hbad) throw Error(MSLM_EINVAL, "edge list has an id out of range, a self-loop or a weight < 1");
+  }
+  Buf keys, vals, keys2, vals2, nun;
+  uint64_t *k1 = keys.get<uint64_t>(mraw);
+  int64_t *v1 = vals.get<int64_t>(mraw);
+  if (E > 0) k_build_intra<<<nblk(E), kBS, 0, st>>>(src, dst, w, off, T, N, E, k1, v1);
+  if (ninter > 0) k_build_inter<<<nblk(ninter), kBS, 0, st>>>(N, T, k1 + 2 * E, v1 + 2 * E);
+  uint64_t *k2 = keys2.get<uint64_t>(mraw);
+  int64_t *v2 = vals2.get<int64_t>(mraw);
+  int endbit = 32 + bits_for((uint64_t)n);
+  MSLM_PRIM(sort_pairs_u64_i64(k1, k2, v1, v2, mraw, endbit, st, temp_alloc(ws)));
+  int64_t *dn = nun.get<int64_t>(1);
+  MSLM_PRIM(reduce_by_key_u64_i64(k2, k1, v2, v1, dn, mraw, st, temp_alloc(ws)));
+  int64_t m = 0;
+  d2h(&m, dn, 1, st);
+  MSLM_HIP(hipStreamSynchronize(st));
+  g.nnz = m;
+  int32_t *col = g.col.get<int32_t>(m);
+  int32_t *wv = g.w.get<int32_t>(m);
+  int64_t *cnt = ws->rowcnt.get<int64_t>(n + 1);
+  int *flags = ws->flag.get<int>(2);
+  MSLM_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (n + 1), st));
+  MSLM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 2, st));
+  if (m > 0) k_build_csr<<<nblk(m), kBS, 0, st>>>(k1, v1, m, col, wv, cnt, flags);
+  int64_t *rp = g.rp.get<int64_t>(n + 1);
+  MSLM_PRIM(exclusive_sum_i64(cnt, rp, n + 1, st, temp_alloc(ws)));
+  int32_t *kd = g.k.get<int32_t>(n);
+  Buf tw;
+  int64_t *twom = tw.get<int64_t>(2 * T);
+  MSLM_HIP(hipMemsetAsync(twom, 0, sizeof(int64_t) * 2 * T, st));
+  k_build_degree<<<nblk(n), kBS, 0, st>>>(rp, col, wv, n, N, kd, twom, twom + T);
+  k_max_degree<<<nblk(n), kBS, 0, st>>>(rp, n, flags + 1);
+  std::vector<int64_t> h(2 * T);
+  int hf[2] = {0, 0};
+  d2h(h.data(), twom, 2 * T, st);
+  d2h(hf, flags, 2, st);
+  MSLM_HIP(hipStreamSynchronize(st));
+  g.twom.assign(h.begin(), h.begin() + T);
+  g.nzslice.assign(h.begin() + T, h.end());
+  for (int s = 0; s < T; s++)
+    if (g.twom[s] >= (int64_t)1 << 31)
+      throw Error(MSLM_EOVERFLOW, "a slice's total degree 2m_s reaches 2^31");
+  g.unit = hf[0] == 0;
+  g.maxdeg = hf[1];
+  if (g.unit) g.w.release();
+}
+
+namespace {
+__global__ void k_iota_i64_ranges(int64_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+__global__ void k_union_rows(const int64_t *rp, int64_t n, int64_t eoff, int64_t *out, int) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) out[i] = rp[i] + eoff;
+}
+__global__ void k_union_cols(const int32_t *col, int64_t m, int32_t u0, int32_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = col[i] + u0;
+}
+__global__ void k_unit_ids(int32_t *uslice, int32_t *usolve, int64_t n, int32_t N, int32_t sfirst,
+                           int32_t j) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uslice[i] = sfirst + (int32_t)(i / N);
+  usolve[i] = j;
+}
+}  // namespace
+
+#include "engine_solve.inc"
+
+}  // namespace mslm

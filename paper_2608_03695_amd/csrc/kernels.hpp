@@ -1,0 +1,1141 @@
+// Hand-written HIP kernels of the multislice Leiden path (gfx950, wave64, no MFMA: every
+// step is a scan, a gather or a hash update, bounded by HBM bandwidth).
+//
+// Units are supra-nodes at level 0 and super-nodes at later levels.  Several independent
+// solves can share one launch as a disjoint union: each unit knows its solve (coefficients,
+// priority seed, local id offset) and its slices are global slice ids, so nothing here
+// ever compares quantities of two different solves.
+#pragma once
+#include <math.h>
+
+#include "device.hpp"
+
+namespace mslm {
+
+typedef __int128 i128;
+
+// ------------------------------------------------------------------ per-solve constants
+struct SolveDev {
+  const int64_t *p, *q, *pb, *a, *b;   // gamma = p/q, omega = a/b (reduced), pb = p*b
+  const uint64_t *seedmix;             // mix64(seed)
+  const int64_t *uoff;                 // first unit of the solve at the current level
+  const int32_t *sfirst;               // first global slice of the solve
+  const int64_t *S;                    // per global slice: 2m_s, or 1 for an empty slice
+  int64_t *fallbacks;                  // exact-comparison counter
+};
+
+// ------------------------------------------------------------------ level views
+// Level 0: the supra-CSR of Eq. 3 with raw intra weights; an entry whose column lies
+// outside the unit's slice is a coupling entry of scaled weight a (absent when a == 0).
+struct View0 {
+  const int64_t *rp;
+  const int32_t *col;
+  const int32_t *w;        // raw intra weight per entry, or nullptr for unit weights
+  const int32_t *k;        // intra degree per unit
+  const int32_t *uslice;   // global slice of each unit
+  const int64_t *sstart;   // [slices + 1] first unit of each global slice
+  const int32_t *usolve;   // solve of each unit
+  struct Row {
+    int64_t lo, hi, slo, shi, a, b;
+  };
+  __device__ Row row(int64_t v, const SolveDev &sd) const {
+    int gs = uslice[v];
+    int j = usolve[v];
+    return Row{rp[v], rp[v + 1], sstart[gs], sstart[gs + 1], sd.a[j], sd.b[j]};
+  }
+  __device__ int64_t wt(const Row &r, int64_t e, int32_t x) const {
+    return (x >= r.slo && x < r.shi) ? r.b * (w ? (int64_t)w[e] : 1) : r.a;
+  }
+  __device__ int plen(int64_t v) const { return k[v] > 0 ? 1 : 0; }
+  __device__ void pent(int64_t v, int, int &gs, int64_t &kk) const {
+    gs = uslice[v];
+    kk = k[v];
+  }
+  __device__ int64_t degree(int64_t v) const { return rp[v + 1] - rp[v]; }
+};
+
+// Aggregated levels: scaled int64 weights, per-unit slice profiles (global slice, degree).
+struct ViewK {
+  const int64_t *rp;
+  const int32_t *col;
+  const int64_t *w;
+  const int64_t *pp;
+  const int32_t *ps;
+  const int32_t *pk;
+  const int32_t *usolve;
+  struct Row {
+    int64_t lo, hi;
+  };
+  __device__ Row row(int64_t v, const SolveDev &) const { return Row{rp[v], rp[v + 1]}; }
+  __device__ int64_t wt(const Row &, int64_t e, int32_t) const { return w[e]; }
+  __device__ int plen(int64_t v) const { return (int)(pp[v + 1] - pp[v]); }
+  __device__ void pent(int64_t v, int j, int &gs, int64_t &kk) const {
+    gs = ps[pp[v] + j];
+    kk = pk[pp[v] + j];
+  }
+  __device__ int64_t degree(int64_t v) const { return rp[v + 1] - rp[v]; }
+};
+
+// ------------------------------------------------------------------ gains
+// Targets: a community label, the empty community (label kNone, gain 0), or "stay" (the
+// unit's own community without itself).  The value compared for unit v and target X is
+//     q*W_X - p*b * sum_s k_{v,s} * y_{X,s} / S_s
+// (W_X the scaled edge weight from v to X, y_{X,s} the slice-s degree of X), which orders
+// targets exactly as the change of Q in Eq. 6 does (a positive multiple of it).
+enum { kTarget = 0, kEmpty = 1, kStay = 2 };
+
+struct UnitCtx {
+  int64_t v;
+  int j;
+  uint32_t D;
+  int m;          // profile length
+  int gs0;        // first profile slice
+  int64_t k0;     // first profile degree
+  int64_t p, q, pb, S0;
+};
+
+template <class V>
+__device__ inline UnitCtx unit_ctx(const V &g, const SolveDev &sd, int64_t v, uint32_t D) {
+  UnitCtx u;
+  u.v = v;
+  u.j = g.usolve[v];
+  u.D = D;
+  u.m = g.plen(v);
+  u.gs0 = 0;
+  u.k0 = 0;
+  if (u.m > 0) g.pent(v, 0, u.gs0, u.k0);
+  u.p = sd.p[u.j];
+  u.q = sd.q[u.j];
+  u.pb = sd.pb[u.j];
+  u.S0 = u.m > 0 ? sd.S[u.gs0] : 1;
+  return u;
+}
+
+__device__ inline int64_t target_y(const SliceTable &tab, int gs, int64_t k, uint32_t lab, int kind) {
+  if (kind == kEmpty) return 0;
+  int64_t y = tab_get(tab, gs, lab);
+  return kind == kStay ? y - k : y;
+}
+
+// Level 0: one slice per unit; exact in int64 under the checked head-room precondition.
+struct Score0 {
+  int64_t g;
+  uint32_t lab;
+};
+
+struct Policy0 {
+  typedef Score0 Score;
+  template <class V>
+  __device__ static Score make(const V &, const UnitCtx &u, const SolveDev &, const SliceTable &tab,
+                               uint32_t lab, int64_t W, int kind) {
+    Score s;
+    s.lab = kind == kEmpty ? kNone : lab;
+    if (u.m == 0) {
+      s.g = u.q * W;
+    } else {
+      int64_t y = target_y(tab, u.gs0, u.k0, lab, kind);
+      s.g = u.q * u.S0 * W - u.pb * (u.k0 * y);
+    }
+    return s;
+  }
+  template <class V>
+  __device__ static int cmp(const V &, const UnitCtx &, const SolveDev &, const SliceTable &,
+                            const Score &a, const Score &b) {
+    return a.g < b.g ? -1 : (a.g > b.g ? 1 : 0);
+  }
+  __device__ static Score shfl(const Score &s, int m) {
+    Score o;
+    o.g = shfl_xor64(s.g, m);
+    o.lab = shfl_xor32(s.lab, m);
+    return o;
+  }
+};
+
+// Aggregated levels: int128 when the unit lies in one slice, otherwise a double estimate
+// with a rigorous error bound and an exact big-integer evaluation when the estimates of
+// two targets are too close to order.
+struct ScoreK {
+  i128 ex;
+  double ap, er;
+  int64_t W;
+  uint32_t lab;
+  int kind;
+};
+
+template <class V>
+__device__ __noinline__ int exact_cmp(const V &g, const UnitCtx &u, const SolveDev &sd,
+                                      const SliceTable &tab, uint32_t la, int ka, int64_t Wa,
+                                      uint32_t lb, int kb, int64_t Wb) {
+  ExactAcc acc;
+  acc.init();
+  for (int jj = 0; jj < u.m; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(u.v, jj, gs, k);
+    int64_t ya = target_y(tab, gs, k, la, ka);
+    int64_t yb = target_y(tab, gs, k, lb, kb);
+    acc.term(k * (ya - yb), sd.S[gs]);
+  }
+  return acc.sign(u.q, Wa - Wb, u.pb);
+}
+
+struct PolicyK {
+  typedef ScoreK Score;
+  template <class V>
+  __device__ static Score make(const V &g, const UnitCtx &u, const SolveDev &sd,
+                               const SliceTable &tab, uint32_t lab, int64_t W, int kind) {
+    Score s;
+    s.lab = kind == kEmpty ? kNone : lab;
+    s.kind = kind;
+    s.W = W;
+    s.ex = 0;
+    s.ap = 0;
+    s.er = 0;
+    if (u.m <= 1) {
+      i128 val = (i128)u.q * W;
+      if (u.m == 1) {
+        int64_t y = target_y(tab, u.gs0, u.k0, lab, kind);
+        val = val * u.S0 - (i128)u.pb * (i128)(u.k0 * y);
+      }
+      s.ex = val;
+    } else {
+      double acc = 0.0, mag = 0.0;
+      for (int jj = 0; jj < u.m; jj++) {
+        int gs;
+        int64_t k;
+        g.pent(u.v, jj, gs, k);
+        int64_t y = target_y(tab, gs, k, lab, kind);
+        double t = (double)(k * y) / (double)sd.S[gs];
+        acc += t;
+        mag += fabs(t);
+      }
+      double qw = (double)u.q * (double)W;
+      s.ap = qw - (double)u.pb * acc;
+      s.er = (double)(u.m + 8) * 0x1p-50 * (fabs(qw) + (double)u.pb * mag);
+    }
+    return s;
+  }
+  template <class V>
+  __device__ static int cmp(const V &g, const UnitCtx &u, const SolveDev &sd, const SliceTable &tab,
+                            const Score &a, const Score &b) {
+    if (u.m <= 1) return a.ex < b.ex ? -1 : (a.ex > b.ex ? 1 : 0);
+    double d = a.ap - b.ap;
+    if (fabs(d) > 2.0 * (a.er + b.er)) return d > 0 ? 1 : -1;
+    atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
+    return exact_cmp(g, u, sd, tab, a.lab, a.kind, a.W, b.lab, b.kind, b.W);
+  }
+  __device__ static Score shfl(const Score &s, int m) {
+    Score o;
+    uint64_t lo = (uint64_t)s.ex, hi = (uint64_t)(s.ex >> 64);
+    lo = (uint64_t)shfl_xor64((int64_t)lo, m);
+    hi = (uint64_t)shfl_xor64((int64_t)hi, m);
+    o.ex = (i128)(((unsigned __int128)hi << 64) | lo);
+    o.ap = __shfl_xor(s.ap, m, 64);
+    o.er = __shfl_xor(s.er, m, 64);
+    o.W = shfl_xor64(s.W, m);
+    o.lab = shfl_xor32(s.lab, m);
+    o.kind = __shfl_xor(s.kind, m, 64);
+    return o;
+  }
+};
+
+template <class P, class V>
+__device__ inline bool better(const V &g, const UnitCtx &u, const SolveDev &sd, const SliceTable &tab,
+                              const typename P::Score &a, const typename P::Score &b) {
+  int c = P::cmp(g, u, sd, tab, a, b);
+  return c > 0 || (c == 0 && a.lab < b.lab);
+}
+
+template <class P, class V>
+__device__ inline typename P::Score wave_best(const V &g, const UnitCtx &u, const SolveDev &sd,
+                                              const SliceTable &tab, typename P::Score s) {
+  for (int m = 32; m >= 1; m >>= 1) {
+    typename P::Score o = P::shfl(s, m);
+    if (better<P>(g, u, sd, tab, o, s)) s = o;
+  }
+  return s;
+}
+
+// ------------------------------------------------------------------ accumulation tables
+struct LdsTab {
+  uint32_t *K;
+  int64_t *V;
+  int lg;
+  __device__ int size() const { return 1 << lg; }
+  __device__ void add(uint32_t lab, int64_t w) const { lds_add(K, V, lg, lab, w); }
+  __device__ int64_t get(uint32_t lab) const { return lds_get(K, V, lg, lab); }
+};
+struct GTab {
+  uint32_t *K;
+  int64_t *V;
+  int lg;
+  __device__ int size() const { return 1 << lg; }
+  __device__ void add(uint32_t lab, int64_t w) const {
+    gtab_add(K, V, (1u << lg) - 1, 32 - lg, lab, w);
+  }
+  __device__ int64_t get(uint32_t lab) const {
+    return gtab_get(K, V, (1u << lg) - 1, 32 - lg, lab);
+  }
+};
+
+// Group = the threads cooperating on one unit: one wave, or a whole block.
+struct WaveGrp {
+  __device__ int rank() const { return threadIdx.x & 63; }
+  __device__ int size() const { return 64; }
+  __device__ void sync() const { wave_sync(); }
+};
+struct BlockGrp {
+  __device__ int rank() const { return threadIdx.x; }
+  __device__ int size() const { return blockDim.x; }
+  __device__ void sync() const { __syncthreads(); }
+};
+
+// Reduce a score over the group; every thread gets the result.
+template <class P, class V>
+__device__ inline typename P::Score group_best(WaveGrp, const V &g, const UnitCtx &u,
+                                               const SolveDev &sd, const SliceTable &tab,
+                                               typename P::Score s, typename P::Score *) {
+  return wave_best<P>(g, u, sd, tab, s);
+}
+template <class P, class V>
+__device__ inline typename P::Score group_best(BlockGrp grp, const V &g, const UnitCtx &u,
+                                               const SolveDev &sd, const SliceTable &tab,
+                                               typename P::Score s, typename P::Score *red) {
+  s = wave_best<P>(g, u, sd, tab, s);
+  int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wv] = s;
+  grp.sync();
+  typename P::Score b = red[0];
+  for (int i = 1; i < nw; i++)
+    if (better<P>(g, u, sd, tab, red[i], b)) b = red[i];
+  grp.sync();
+  return b;
+}
+
+// ------------------------------------------------------------------ local moving
+// One unit: accumulate neighbour-community weights in the table, evaluate every candidate
+// community (strictly better gain wins, ties to the lower label, the empty community has
+// gain 0 and label +inf), and decide a move only when it beats staying strictly.
+// Profiling counters of the decision kernels (filled only when profiling is requested):
+// [0] units decided, [1] entries scanned, [2] candidate communities evaluated.
+struct LmCounters {
+  unsigned long long *c;
+};
+
+template <class P, class V, class Grp, class Tab>
+__device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd, int64_t v,
+                                   const uint32_t *comm, const SliceTable &sig, uint32_t fresh_base,
+                                   typename P::Score *red, LmCounters pc) {
+  const int r = grp.rank(), gsz = grp.size();
+  for (int i = r; i < tab.size(); i += gsz) {
+    tab.K[i] = 0;
+    tab.V[i] = 0;
+  }
+  grp.sync();
+  const uint32_t D = comm[v];
+  typename V::Row row = g.row(v, sd);
+  for (int64_t e = row.lo + r; e < row.hi; e += gsz) {
+    int32_t x = g.col[e];
+    int64_t w = g.wt(row, e, x);
+    if (w == 0) continue;
+    tab.add(comm[x], w);
+  }
+  grp.sync();
+  UnitCtx u = unit_ctx(g, sd, v, D);
+  typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
+  int ncand = 0;
+  for (int i = r; i < tab.size(); i += gsz) {
+    uint32_t key = tab.K[i];
+    if (key == 0 || key - 1 == D) continue;
+    ncand++;
+    typename P::Score s = P::make(g, u, sd, sig, key - 1, tab.V[i], kTarget);
+    if (better<P>(g, u, sd, sig, s, best)) best = s;
+  }
+  if (pc.c) {
+    if (ncand) atomicAdd(pc.c + 2, (unsigned long long)ncand);
+    if (r == 0) {
+      atomicAdd(pc.c + 0, 1ull);
+      atomicAdd(pc.c + 1, (unsigned long long)(row.hi - row.lo));
+    }
+  }
+  best = group_best<P>(grp, g, u, sd, sig, best, red);
+  int64_t wD = tab.get(D);
+  typename P::Score stay = P::make(g, u, sd, sig, D, wD, kStay);
+  uint32_t out = kNone;
+  if (P::cmp(g, u, sd, sig, best, stay) > 0) out = best.lab == kNone ? fresh_base + (uint32_t)v : best.lab;
+  grp.sync();
+  return out;
+}
+
+constexpr int kWaveLg = 9;        // 512-slot LDS table per wave: units of degree <= 256
+constexpr int kBlockLg = 13;      // 8192-slot LDS table per block: degree <= 4096
+constexpr int kWaveMaxDeg = 256;
+constexpr int kBlockMaxDeg = 4096;
+
+template <class P, class V>
+__global__ __launch_bounds__(256) void k_lm_wave(V g, SolveDev sd, const int32_t *units,
+                                                 int64_t count, const uint32_t *comm,
+                                                 SliceTable sig, uint32_t *target,
+                                                 uint32_t fresh_base, LmCounters pc) {
+  __shared__ uint32_t sk[4][1 << kWaveLg];
+  __shared__ int64_t sv[4][1 << kWaveLg];
+  const int wv = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + wv;
+  if (idx >= count) return;
+  LdsTab tab{sk[wv], sv[wv], kWaveLg};
+  uint32_t t = lm_unit<P>(WaveGrp(), tab, g, sd, units[idx], comm, sig, fresh_base,
+                          (typename P::Score *)nullptr, pc);
+  if ((threadIdx.x & 63) == 0) target[idx] = t;
+}
+
+template <class P, class V>
+__global__ __launch_bounds__(1024) void k_lm_block(V g, SolveDev sd, const int32_t *units,
+                                                   int64_t count, const uint32_t *comm,
+                                                   SliceTable sig, uint32_t *target,
+                                                   uint32_t fresh_base, LmCounters pc) {
+  __shared__ uint32_t sk[1 << kBlockLg];
+  __shared__ int64_t sv[1 << kBlockLg];
+  __shared__ typename P::Score red[16];
+  LdsTab tab{sk, sv, kBlockLg};
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, units[idx], comm, sig, fresh_base, red, pc);
+    if (threadIdx.x == 0) target[idx] = t;
+  }
+}
+
+// Units of very high degree: a global-memory table per unit, slot offsets from a scan.
+template <class P, class V>
+__global__ __launch_bounds__(256) void k_lm_gtab(V g, SolveDev sd, const int32_t *units,
+                                                 int64_t count, const uint32_t *comm,
+                                                 SliceTable sig, uint32_t *target,
+                                                 uint32_t fresh_base, uint32_t *gk, int64_t *gv,
+                                                 const int64_t *goff, const int32_t *glg,
+                                                 LmCounters pc) {
+  __shared__ typename P::Score red[4];
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int64_t v = units[idx];
+    GTab tab{gk + goff[v], gv + goff[v], glg[v]};
+    uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, v, comm, sig, fresh_base, red, pc);
+    if (threadIdx.x == 0) target[idx] = t;
+  }
+}
+
+// Apply the decided moves of one colour batch: new label, Sigma delta for every profile slice.
+template <class V>
+__global__ void k_lm_apply(V g, const int32_t *units, int64_t count, const uint32_t *target,
+                           uint32_t *comm, SliceTable sig, uint32_t *moved,
+                           const uint8_t *frozen) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint32_t C = target[i];
+  if (C == kNone) return;
+  int64_t v = units[i];
+  int j = g.usolve[v];
+  if (frozen[j]) return;
+  uint32_t D = comm[v];
+  int m = g.plen(v);
+  for (int jj = 0; jj < m; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(v, jj, gs, k);
+    tab_add(sig, gs, D, -(int32_t)k);
+    tab_add(sig, gs, C, (int32_t)k);
+  }
+  comm[v] = C;
+  atomicAdd(moved + j, 1u);
+}
+
+template <class V>
+__global__ void k_sigma_build(V g, int64_t n, const uint32_t *comm, SliceTable sig) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int m = g.plen(v);
+  for (int jj = 0; jj < m; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(v, jj, gs, k);
+    tab_add(sig, gs, comm[v], (int32_t)k);
+  }
+}
+
+__global__ void k_rebuild_check(const uint32_t *used, const uint32_t *limit, int nslices, int *flag) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nslices && used[s] > limit[s]) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------------ colouring
+// First-fit colouring in decreasing priority (Jones-Plassmann rounds): a unit takes the
+// smallest colour unused by its higher-priority neighbours once all of them are coloured.
+// The result equals the sequential greedy colouring in priority order.
+template <class V>
+__global__ __launch_bounds__(256) void k_jp(V g, SolveDev sd, const int32_t *work, int64_t nwork,
+                                            int32_t *colour, int32_t *next, uint32_t *nnext,
+                                            int it, int lvl) {
+  const int lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= nwork) return;
+  const int64_t v = work[idx];
+  const int j = g.usolve[v];
+  const uint64_t sm = sd.seedmix[j];
+  const int64_t off = sd.uoff[j];
+  const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+  typename V::Row row = g.row(v, sd);
+  int blocked = 0;
+  int base = 0;
+  int result = -1;
+  for (;;) {
+    uint64_t used = 0;
+    for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+      int32_t x = g.col[e];
+      if (g.wt(row, e, x) == 0) continue;
+      uint64_t hx = priority(sm, it, lvl, 0, (uint32_t)(x - off));
+      if (!outranks(hx, (uint32_t)x, hv, (uint32_t)v)) continue;
+      int cx = __hip_atomic_load(colour + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cx < 0) {
+        blocked = 1;
+      } else if (cx >= base && cx < base + 64) {
+        used |= 1ull << (cx - base);
+      }
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+      used |= (uint64_t)shfl_xor64((int64_t)used, m);
+      blocked |= __shfl_xor(blocked, m, 64);
+    }
+    if (blocked) break;
+    if (~used) {
+      result = base + __builtin_ctzll(~used);
+      break;
+    }
+    base += 64;
+  }
+  if (lane == 0) {
+    if (blocked) {
+      uint32_t pos = atomicAdd(nnext, 1u);
+      next[pos] = (int32_t)v;
+    } else {
+      __hip_atomic_store(colour + v, result, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// sort key of a unit for batching: colour, then degree bin (wave / block-LDS / global table)
+constexpr uint32_t kInactiveKey = 0xfffffffcu;
+
+template <class V>
+__global__ void k_batch_keys(V g, int64_t n, const int32_t *colour, const uint8_t *sactive,
+                             uint32_t *keys, uint32_t *vals, uint32_t *hist) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  vals[v] = (uint32_t)v;
+  if (!sactive[g.usolve[v]]) {
+    keys[v] = kInactiveKey;
+    return;
+  }
+  int64_t d = g.degree(v);
+  uint32_t bin = d <= kWaveMaxDeg ? 0u : (d <= kBlockMaxDeg ? 1u : 2u);
+  uint32_t key = ((uint32_t)colour[v] << 2) | bin;
+  keys[v] = key;
+  atomicAdd(hist + key, 1u);
+}
+
+template <class V>
+__global__ void k_bin_keys(V g, int64_t n, const uint8_t *sactive, uint32_t *keys, uint32_t *vals,
+                           uint32_t *hist) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  vals[v] = (uint32_t)v;
+  uint32_t bin = 3;
+  if (sactive[g.usolve[v]]) {
+    int64_t d = g.degree(v);
+    bin = d <= kWaveMaxDeg ? 0u : (d <= kBlockMaxDeg ? 1u : 2u);
+  }
+  keys[v] = bin;
+  atomicAdd(hist + bin, 1u);
+}
+
+// per unit of the global-table bin: table size (power of two >= 2*degree), by unit id
+template <class V>
+__global__ void k_gtab_sizes(V g, const int32_t *units, int64_t count, int64_t *sz, int32_t *lg) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int64_t v = units[i];
+  int64_t d = g.degree(v);
+  int l = 4;
+  while ((1ll << l) < 2 * d) l++;
+  lg[v] = l;
+  sz[i] = 1ll << l;
+}
+__global__ void k_gtab_assign(const int32_t *units, int64_t count, const int64_t *off,
+                              int64_t *goff) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) goff[units[i]] = off[i];
+}
+
+// ------------------------------------------------------------------ refinement
+// Leiden refinement inside each community (Section 3.2 citing Traag et al.): singletons
+// that are well connected to their community merge into well-connected sub-communities
+// of positive gain; a proposer merges only if it outranks every proposing neighbour of
+// its community, so each merge joins a frozen sub-community along an edge and
+// sub-communities stay connected.
+
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_init(V g, SolveDev sd, int64_t n, const uint32_t *comm,
+                                                  uint32_t *R, int64_t *ext, uint64_t *mask,
+                                                  SliceTable sr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const uint32_t D = comm[v];
+  typename V::Row row = g.row(v, sd);
+  int64_t s = 0;
+  for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+    int32_t x = g.col[e];
+    if (comm[x] == D) s += g.wt(row, e, x);
+  }
+  s = wave_sum64(s);
+  const int m = g.plen(v);
+  const int j = g.usolve[v];
+  uint64_t mk = 0;
+  for (int jj = 0; jj < m; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(v, jj, gs, k);
+    mk |= 1ull << (gs - sd.sfirst[j]);
+    if (jj % 64 == lane) tab_add(sr, gs, (uint32_t)v, (int32_t)k);
+  }
+  if (lane == 0) {
+    R[v] = (uint32_t)v;
+    ext[v] = s;
+    mask[v] = mk;
+  }
+}
+
+// Well-connectedness of sub-community T within its community K:
+//   q*ext(T) - p*b * sum_s x_s (K_s - x_s) / S_s >= 0,  x_s = Sigma_R(T, s), K_s = Sigma(K, s).
+template <class V>
+__global__ void k_ref_wc(V g, SolveDev sd, const int32_t *list, int64_t count, const uint32_t *comm,
+                         const int64_t *ext, const uint64_t *mask, SliceTable sr, SliceTable sig,
+                         uint8_t *wcT, uint8_t *active, uint8_t *only) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t T = list ? list[i] : i;
+  if (only) {
+    if (!only[T]) return;
+    only[T] = 0;
+  }
+  const int j = g.usolve[T];
+  const int64_t q = sd.q[j], pb = sd.pb[j];
+  const uint32_t K = comm[T];
+  const int base = sd.sfirst[j];
+  uint64_t mk = mask[T];
+  int m = 0;
+  int gs0 = 0;
+  int64_t c0 = 0;
+  double acc = 0, mag = 0;
+  for (uint64_t b = mk; b; b &= b - 1) {
+    int gs = base + __builtin_ctzll(b);
+    int64_t x = tab_get(sr, gs, (uint32_t)T);
+    if (x == 0) continue;
+    int64_t c = x * ((int64_t)tab_get(sig, gs, K) - x);
+    if (m == 0) {
+      gs0 = gs;
+      c0 = c;
+    }
+    m++;
+    double t = (double)c / (double)sd.S[gs];
+    acc += t;
+    mag += fabs(t);
+  }
+  int sign;
+  if (m <= 1) {
+    i128 val = (i128)q * ext[T] * (m ? sd.S[gs0] : 1) - (i128)pb * c0;
+    sign = val < 0 ? -1 : (val > 0 ? 1 : 0);
+  } else {
+    double qw = (double)q * (double)ext[T];
+    double ap = qw - (double)pb * acc;
+    double er = (double)(m + 8) * 0x1p-50 * (fabs(qw) + (double)pb * mag);
+    if (fabs(ap) > er) {
+      sign = ap > 0 ? 1 : -1;
+    } else {
+      atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
+      ExactAcc ea;
+      ea.init();
+      for (uint64_t b = mk; b; b &= b - 1) {
+        int gs = base + __builtin_ctzll(b);
+        int64_t x = tab_get(sr, gs, (uint32_t)T);
+        if (x == 0) continue;
+        ea.term(x * ((int64_t)tab_get(sig, gs, K) - x), sd.S[gs]);
+      }
+      sign = ea.sign(q, ext[T], pb);
+    }
+  }
+  wcT[T] = sign >= 0;
+  if (active) active[T] = sign >= 0;
+}
+
+// Proposal of one active singleton: best well-connected sub-community of positive gain.
+template <class P, class V, class Grp, class Tab>
+__device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd, int64_t v,
+                                const uint32_t *comm, const uint32_t *R, const uint8_t *wcT,
+                                const SliceTable &sr, uint32_t *prop, int64_t *propw,
+                                uint8_t *active, typename P::Score *red) {
+  const int r = grp.rank(), gsz = grp.size();
+  for (int i = r; i < tab.size(); i += gsz) {
+    tab.K[i] = 0;
+    tab.V[i] = 0;
+  }
+  grp.sync();
+  const uint32_t D = comm[v];
+  typename V::Row row = g.row(v, sd);
+  for (int64_t e = row.lo + r; e < row.hi; e += gsz) {
+    int32_t x = g.col[e];
+    if (comm[x] != D) continue;
+    int64_t w = g.wt(row, e, x);
+    if (w == 0) continue;
+    tab.add(R[x], w);
+  }
+  grp.sync();
+  UnitCtx u = unit_ctx(g, sd, v, D);
+  const typename P::Score zero = P::make(g, u, sd, sr, kNone, 0, kEmpty);
+  typename P::Score best = zero;
+  for (int i = r; i < tab.size(); i += gsz) {
+    uint32_t key = tab.K[i];
+    if (key == 0) continue;
+    uint32_t T = key - 1;
+    if (!wcT[T]) continue;
+    typename P::Score s = P::make(g, u, sd, sr, T, tab.V[i], kTarget);
+    if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
+    if (better<P>(g, u, sd, sr, s, best)) best = s;
+  }
+  best = group_best<P>(grp, g, u, sd, sr, best, red);
+  int64_t w = best.lab == kNone ? 0 : tab.get(best.lab);
+  grp.sync();
+  if (r == 0) {
+    prop[v] = best.lab;
+    propw[v] = w;
+    if (best.lab == kNone) active[v] = 0;
+  }
+}
+
+template <class P, class V>
+__global__ __launch_bounds__(256) void k_ref_prop_wave(V g, SolveDev sd, const int32_t *units,
+                                                       int64_t count, const uint32_t *comm,
+                                                       const uint32_t *R, const uint8_t *wcT,
+                                                       SliceTable sr, uint32_t *prop, int64_t *propw,
+                                                       uint8_t *active) {
+  __shared__ uint32_t sk[4][1 << kWaveLg];
+  __shared__ int64_t sv[4][1 << kWaveLg];
+  const int wv = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + wv;
+  if (idx >= count) return;
+  const int64_t v = units[idx];
+  if (!active[v]) {
+    if ((threadIdx.x & 63) == 0) prop[v] = kNone;
+    return;
+  }
+  LdsTab tab{sk[wv], sv[wv], kWaveLg};
+  ref_unit<P>(WaveGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propw, active,
+              (typename P::Score *)nullptr);
+}
+
+template <class P, class V>
+__global__ __launch_bounds__(1024) void k_ref_prop_block(V g, SolveDev sd, const int32_t *units,
+                                                         int64_t count, const uint32_t *comm,
+                                                         const uint32_t *R, const uint8_t *wcT,
+                                                         SliceTable sr, uint32_t *prop,
+                                                         int64_t *propw, uint8_t *active) {
+  __shared__ uint32_t sk[1 << kBlockLg];
+  __shared__ int64_t sv[1 << kBlockLg];
+  __shared__ typename P::Score red[16];
+  LdsTab tab{sk, sv, kBlockLg};
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int64_t v = units[idx];
+    if (!active[v]) {
+      if (threadIdx.x == 0) prop[v] = kNone;
+      continue;
+    }
+    ref_unit<P>(BlockGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propw, active, red);
+  }
+}
+
+template <class P, class V>
+__global__ __launch_bounds__(256) void k_ref_prop_gtab(V g, SolveDev sd, const int32_t *units,
+                                                       int64_t count, const uint32_t *comm,
+                                                       const uint32_t *R, const uint8_t *wcT,
+                                                       SliceTable sr, uint32_t *prop, int64_t *propw,
+                                                       uint8_t *active, uint32_t *gk, int64_t *gv,
+                                                       const int64_t *goff, const int32_t *glg) {
+  __shared__ typename P::Score red[4];
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int64_t v = units[idx];
+    if (!active[v]) {
+      if (threadIdx.x == 0) prop[v] = kNone;
+      continue;
+    }
+    GTab tab{gk + goff[v], gv + goff[v], glg[v]};
+    ref_unit<P>(BlockGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propw, active, red);
+  }
+}
+
+// A proposer merges when no proposing neighbour of its community outranks it.
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, int64_t n,
+                                                      const uint32_t *comm, const uint32_t *prop,
+                                                      uint8_t *elig, uint32_t *nelig, int it,
+                                                      int lvl) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  if (prop[v] == kNone) {
+    if (lane == 0) elig[v] = 0;
+    return;
+  }
+  const int j = g.usolve[v];
+  const uint64_t sm = sd.seedmix[j];
+  const int64_t off = sd.uoff[j];
+  const uint64_t hv = priority(sm, it, lvl, 1, (uint32_t)(v - off));
+  const uint32_t D = comm[v];
+  typename V::Row row = g.row(v, sd);
+  int beaten = 0;
+  for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+    int32_t x = g.col[e];
+    if (comm[x] != D || prop[x] == kNone) continue;
+    if (g.wt(row, e, x) == 0) continue;
+    uint64_t hx = priority(sm, it, lvl, 1, (uint32_t)(x - off));
+    if (outranks(hx, (uint32_t)x, hv, (uint32_t)v)) beaten = 1;
+  }
+  for (int m = 32; m >= 1; m >>= 1) beaten |= __shfl_xor(beaten, m, 64);
+  if (lane == 0) {
+    elig[v] = !beaten;
+    if (!beaten) atomicAdd(nelig + j, 1u);
+  }
+}
+
+template <class V>
+__global__ void k_ref_apply(V g, SolveDev sd, int64_t n, const uint32_t *prop, const int64_t *propw,
+                            const uint8_t *elig, uint32_t *R, int64_t *ext, uint64_t *mask,
+                            uint8_t *active, uint8_t *changed, SliceTable sr) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || !elig[v]) return;
+  const uint32_t T = prop[v];
+  R[v] = T;
+  active[v] = 0;
+  active[T] = 0;
+  atomicAdd(reinterpret_cast<unsigned long long *>(ext + T),
+            (unsigned long long)(ext[v] - 2 * propw[v]));
+  int m = g.plen(v);
+  for (int jj = 0; jj < m; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(v, jj, gs, k);
+    tab_add(sr, gs, T, (int32_t)k);
+  }
+  atomicOr(reinterpret_cast<unsigned long long *>(mask + T), (unsigned long long)mask[v]);
+  changed[T] = 1;
+}
+
+// ------------------------------------------------------------------ aggregation helpers
+__global__ void k_minmember(const uint32_t *R, int64_t n, const int32_t *usolve,
+                            const uint8_t *cont, uint32_t *minm) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n && cont[usolve[u]]) atomicMin(minm + R[u], (uint32_t)u);
+}
+__global__ void k_flag_minm(const uint32_t *R, const uint32_t *minm, int64_t n, uint8_t *flag) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) flag[u] = minm[R[u]] == (uint32_t)u;
+}
+// super-node id of each unit of a continuing solve (kNone for units of finished solves)
+__global__ void k_rank_gather(const uint32_t *R, const uint32_t *minm, const int64_t *rank,
+                              int64_t n, uint32_t *r) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  uint32_t m = minm[R[u]];
+  r[u] = m == kNone ? kNone : (uint32_t)rank[m];
+}
+
+// emit (r[u], r[x]) keys for every entry between different super-nodes
+template <class V>
+__global__ __launch_bounds__(256) void k_agg_keys(V g, SolveDev sd, int64_t n, const uint32_t *r,
+                                                  uint64_t *keys, int64_t *vals,
+                                                  unsigned long long *counter) {
+  const int lane = threadIdx.x & 63;
+  const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (u >= n) return;
+  const uint32_t ru = r[u];
+  if (ru == kNone) return;
+  typename V::Row row = g.row(u, sd);
+  for (int64_t e0 = row.lo; e0 < row.hi; e0 += 64) {
+    int64_t e = e0 + lane;
+    bool emit = false;
+    uint32_t rx = 0;
+    int64_t w = 0;
+    if (e < row.hi) {
+      int32_t x = g.col[e];
+      w = g.wt(row, e, x);
+      rx = r[x];
+      emit = w != 0 && rx != ru;
+    }
+    uint64_t bal = __ballot(emit);
+    if (!bal) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(counter, (unsigned long long)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (emit) {
+      uint64_t below = lane ? (bal & ((1ull << lane) - 1)) : 0;
+      unsigned long long pos = base + __popcll(below);
+      keys[pos] = ((uint64_t)ru << 32) | rx;
+      vals[pos] = w;
+    }
+  }
+}
+
+template <class V>
+__global__ void k_agg_prof_keys(V g, int64_t n, const uint32_t *r, uint64_t *keys, int32_t *vals,
+                                unsigned long long *counter) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n || r[u] == kNone) return;
+  int m = g.plen(u);
+  if (m == 0) return;
+  unsigned long long pos = atomicAdd(counter, (unsigned long long)m);
+  for (int jj = 0; jj < m; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(u, jj, gs, k);
+    keys[pos + jj] = ((uint64_t)r[u] << 32) | (uint32_t)gs;
+    vals[pos + jj] = (int32_t)k;
+  }
+}
+
+__global__ void k_row_counts(const uint64_t *keys, int64_t m, int64_t *cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) atomicAdd(reinterpret_cast<unsigned long long *>(cnt + (keys[i] >> 32)), 1ull);
+}
+__global__ void k_low32(const uint64_t *keys, int64_t m, int32_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = (int32_t)(uint32_t)keys[i];
+}
+
+template <class V>
+__global__ void k_scatter_next(V g, int64_t n, const uint32_t *r, const uint32_t *P,
+                               uint32_t *Pnext, int32_t *usolve_next) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n || r[u] == kNone) return;
+  Pnext[r[u]] = P[u];
+  usolve_next[r[u]] = g.usolve[u];
+}
+
+__global__ void k_map_compose(int64_t *map0, const int64_t *lo, const int64_t *hi, int nr,
+                              const uint32_t *r) {
+  // ranges [lo[k], hi[k]) of level-0 units; grid-stride over their union
+  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < nr; k++)
+    for (int64_t i = lo[k] + tid; i < hi[k]; i += stride) map0[i] = r[map0[i]];
+}
+
+// ------------------------------------------------------------------ canonical labels by sort
+__global__ void k_seg_heads(const uint32_t *sk, const uint32_t *sv, int64_t n, uint8_t *head,
+                            uint8_t *ismin) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint8_t h = (i == 0 || sk[i] != sk[i - 1]) ? 1 : 0;
+  head[i] = h;
+  ismin[sv[i]] = h;
+}
+// segid = inclusive index of the segment (exclusive scan of heads at heads), minOf[seg] = unit
+__global__ void k_seg_min(const uint32_t *sv, const uint8_t *head, const int64_t *segx, int64_t n,
+                          uint32_t *minof) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && head[i]) minof[segx[i]] = sv[i];
+}
+__global__ void k_seg_label(const uint32_t *sv, const uint8_t *head, const int64_t *segx,
+                            const uint32_t *minof, const int64_t *rank, int64_t n, uint32_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t seg = segx[i] + head[i] - 1;
+  out[sv[i]] = (uint32_t)rank[minof[seg]];
+}
+__global__ void k_count_heads(const uint32_t *sv, const uint8_t *head, const int32_t *usolve,
+                              int64_t n, uint32_t *cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && head[i]) atomicAdd(cnt + usolve[sv[i]], 1u);
+}
+__global__ void k_count_roots_R(const uint32_t *R, const int32_t *usolve, int64_t n, uint32_t *cnt) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n && R[u] == (uint32_t)u) atomicAdd(cnt + usolve[u], 1u);
+}
+
+// ------------------------------------------------------------------ split into connected parts
+__device__ inline int32_t uf_find(int32_t *parent, int32_t x) {
+  for (;;) {
+    int32_t p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p == x) return x;
+    int32_t gp = __hip_atomic_load(parent + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gp != p) __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = p;
+  }
+}
+__device__ inline void uf_unite(int32_t *parent, int32_t a, int32_t b) {
+  for (;;) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a < b) {
+      int32_t t = a;
+      a = b;
+      b = t;
+    }
+    // link the larger root under the smaller one: roots stay component minima
+    if (atomicCAS(parent + a, a, b) == a) return;
+  }
+}
+
+__global__ void k_uf_init(int32_t *parent, const int64_t *lo, const int64_t *hi, int nr) {
+  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < nr; k++)
+    for (int64_t i = lo[k] + tid; i < hi[k]; i += stride) parent[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_uf_link(View0 g, SolveDev sd, const int64_t *lo,
+                                                 const int64_t *hi, int nr, const uint32_t *lab,
+                                                 int32_t *parent) {
+  const int lane = threadIdx.x & 63;
+  int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int k = 0; k < nr; k++)
+    for (int64_t v = lo[k] + wid; v < hi[k]; v += nw) {
+      View0::Row row = g.row(v, sd);
+      const uint32_t L = lab[v];
+      for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+        int32_t x = g.col[e];
+        if (x <= v || lab[x] != L || g.wt(row, e, x) == 0) continue;
+        uf_unite(parent, (int32_t)v, x);
+      }
+    }
+}
+
+__global__ void k_uf_roots(int32_t *parent, const int64_t *lo, const int64_t *hi, int nr,
+                           uint8_t *isroot) {
+  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < nr; k++)
+    for (int64_t i = lo[k] + tid; i < hi[k]; i += stride) {
+      int32_t r = uf_find(parent, (int32_t)i);
+      parent[i] = r;
+      isroot[i] = r == (int32_t)i;
+    }
+}
+
+__global__ void k_label_out(const int32_t *parent, const int64_t *rank, const int64_t *lo,
+                            const int64_t *hi, const int64_t *roff, int nr, int32_t *memb) {
+  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < nr; k++)
+    for (int64_t i = lo[k] + tid; i < hi[k]; i += stride)
+      memb[i] = (int32_t)(rank[parent[i]] - roff[k]);
+}
+
+__global__ void k_flatten(const int64_t *map0, const uint32_t *P, const int64_t *lo,
+                          const int64_t *hi, int nr, uint32_t *flat) {
+  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < nr; k++)
+    for (int64_t i = lo[k] + tid; i < hi[k]; i += stride) flat[i] = P[map0[i]];
+}
+
+__global__ void k_count_diff(const int32_t *a, const int32_t *b, const int32_t *usolve,
+                             const int64_t *lo, const int64_t *hi, int nr, uint32_t *diff) {
+  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < nr; k++)
+    for (int64_t i = lo[k] + tid; i < hi[k]; i += stride)
+      if (a[i] != b[i]) atomicAdd(diff + usolve[i], 1u);
+}
+
+// ------------------------------------------------------------------ Q components
+// W_s: intra weight inside communities (both directions, unscaled) per global slice.
+__global__ __launch_bounds__(256) void k_q_w(View0 g, int64_t n, const int32_t *memb, int64_t *W) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const int gs = g.uslice[v];
+  const int64_t slo = g.sstart[gs], shi = g.sstart[gs + 1];
+  const int32_t L = memb[v];
+  int64_t s = 0;
+  for (int64_t e = g.rp[v] + lane; e < g.rp[v + 1]; e += 64) {
+    int32_t x = g.col[e];
+    if (x >= slo && x < shi && memb[x] == L) s += g.w ? g.w[e] : 1;
+  }
+  s = wave_sum64(s);
+  if (lane == 0 && s) atomicAdd(reinterpret_cast<unsigned long long *>(W + gs), (unsigned long long)s);
+}
+
+__global__ void k_sigma_build_memb(View0 g, int64_t n, const int32_t *memb, SliceTable t) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int k = g.k[v];
+  if (k > 0) tab_add(t, g.uslice[v], (uint32_t)memb[v], k);
+}
+
+// SS_s: sum over the slice's sub-table of value^2
+__global__ void k_q_ss(const uint64_t *slots, const int64_t *base, int nslices, int64_t total,
+                       int64_t *SS) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  uint64_t e = slots[i];
+  if ((uint32_t)e == 0) return;
+  int64_t val = (int32_t)(e >> 32);
+  if (val == 0) return;
+  int lo = 0, hi = nslices;   // base[lo] <= i < base[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (base[mid] <= i) lo = mid; else hi = mid;
+  }
+  atomicAdd(reinterpret_cast<unsigned long long *>(SS + lo), (unsigned long long)(val * val));
+}
+
+// I: ordered coupled copy pairs (i,s),(i,s+1) sharing a community, per solve
+__global__ void k_q_inter(View0 g, int64_t n, const int32_t *memb, const int32_t *slast,
+                          int64_t *I) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int gs = g.uslice[v];
+  int j = g.usolve[v];
+  if (gs >= slast[j]) return;   // last slice of its solve
+  int64_t N = g.sstart[gs + 1] - g.sstart[gs];
+  if (memb[v] == memb[v + N]) atomicAdd(reinterpret_cast<unsigned long long *>(I + j), 2ull);
+}
+
+// ------------------------------------------------------------------ small utilities
+template <class T>
+__global__ void k_fill(T *p, T val, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = val;
+}
+__global__ void k_iota_i32(int32_t *p, int64_t n, int64_t off) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)(i + off);
+}
+__global__ void k_iota_u32(uint32_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+__global__ void k_fill_ranges(int32_t *out, const int64_t *lo, const int64_t *hi,
+                              const int64_t *outoff, int nr) {
+  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < nr; k++)
+    for (int64_t i = tid; i < hi[k] - lo[k]; i += stride) out[outoff[k] + i] = (int32_t)(lo[k] + i);
+}
+__global__ void k_gather_i64(const int64_t *src, const int64_t *idx, int n, int64_t *dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+__global__ void k_compact_flag(const uint8_t *flag, int64_t n, int32_t *out, uint32_t *cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) out[atomicAdd(cnt, 1u)] = (int32_t)i;
+}
+
+}  // namespace mslm

@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libmslm.so (argument marshalling only; all work runs in HIP).
+
+Names follow the C ABI in include/mslm.h.  The library must have been built in-tree
+(``paper_2608_03695_amd/build.py``); importing this module on a machine without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from fractions import Fraction
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmslm.so")
+
+MSLM_OK, MSLM_EINVAL, MSLM_ENOMEM, MSLM_EOVERFLOW, MSLM_EUNSUPPORTED, MSLM_EHIP, MSLM_EBUSY = \
+    0, -1, -2, -3, -4, -5, -6
+MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE = 1, 2, 4
+
+EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_footprint_bytes",
+            "mslm_graph_info", "mslm_last_error", "mslm_batch_leiden", "mslm_server_create",
+            "mslm_server_submit", "mslm_server_wait", "mslm_server_destroy"]
+
+
+class MslmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mslm status {status}: {msg}")
+        self.status = status
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_slices", C.c_int32),
+                ("slice_offsets", C.c_void_p), ("src", C.c_void_p), ("dst", C.c_void_p),
+                ("weight", C.c_void_p), ("omega_num", C.c_int64), ("omega_den", C.c_int64),
+                ("flags", C.c_uint32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma_num", C.c_int64), ("gamma_den", C.c_int64),
+                ("omega_num", C.c_int64), ("omega_den", C.c_int64),
+                ("max_levels", C.c_int32), ("max_iterations", C.c_int32),
+                ("max_sweeps", C.c_int32), ("reserved0", C.c_int32),
+                ("seed", C.c_uint64), ("flags", C.c_uint32), ("reserved1", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("q", C.c_double), ("n_communities", C.c_int32), ("levels_run", C.c_int32),
+                ("iterations_run", C.c_int32), ("colours_level0", C.c_int32),
+                ("sweeps", C.c_int64), ("moves", C.c_int64), ("sweep_cap_hits", C.c_int64),
+                ("refine_rounds", C.c_int64), ("merges", C.c_int64), ("splits", C.c_int64),
+                ("exact_fallbacks", C.c_int64), ("ms_total", C.c_double),
+                ("ms_colour", C.c_double), ("ms_local_move", C.c_double),
+                ("ms_refine", C.c_double), ("ms_aggregate", C.c_double),
+                ("ms_finish", C.c_double), ("lm_kernel_ms", C.c_double),
+                ("lm_launches", C.c_int64), ("lm_units", C.c_int64), ("lm_entries", C.c_int64),
+                ("lm_candidates", C.c_int64), ("q_components", C.c_int64 * (3 * 64 + 1))]
+
+    def as_dict(self, n_slices):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "q_components"}
+        d["q_components"] = np.array(self.q_components[:3 * n_slices + 1], dtype=np.int64)
+        return d
+
+
+class Solve(C.Structure):
+    _fields_ = [("graph", C.c_int32), ("reserved", C.c_int32), ("params", Params),
+                ("membership", C.c_void_p), ("result", C.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree HIP library; raise when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2608_03695_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.mslm_create.argtypes = [C.POINTER(GraphDesc), P, C.POINTER(C.c_void_p)]
+    lib.mslm_create.restype = C.c_int
+    lib.mslm_leiden.argtypes = [P, C.POINTER(Params), P, C.POINTER(Result)]
+    lib.mslm_leiden.restype = C.c_int
+    lib.mslm_destroy.argtypes = [P]
+    lib.mslm_destroy.restype = None
+    lib.mslm_q_exact.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
+                                 C.c_int64, C.c_char_p, C.c_size_t, C.c_char_p, C.c_size_t]
+    lib.mslm_q_exact.restype = C.c_int
+    lib.mslm_footprint_bytes.argtypes = [C.POINTER(GraphDesc)]
+    lib.mslm_footprint_bytes.restype = C.c_size_t
+    lib.mslm_graph_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64)]
+    lib.mslm_graph_info.restype = C.c_int
+    lib.mslm_last_error.restype = C.c_char_p
+    lib.mslm_batch_leiden.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Solve),
+                                      C.c_int32, P]
+    lib.mslm_batch_leiden.restype = C.c_int
+    lib.mslm_server_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]
+    lib.mslm_server_create.restype = C.c_int
+    lib.mslm_server_submit.argtypes = [P, C.POINTER(GraphDesc), C.POINTER(Params),
+                                       C.POINTER(C.c_uint64)]
+    lib.mslm_server_submit.restype = C.c_int
+    lib.mslm_server_wait.argtypes = [P, C.c_uint64, C.c_int32, P, C.POINTER(Result),
+                                     C.POINTER(C.c_double)]
+    lib.mslm_server_wait.restype = C.c_int
+    lib.mslm_server_destroy.argtypes = [P]
+    lib.mslm_server_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != MSLM_OK:
+        raise MslmError(rc, load().mslm_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _desc(tg, omega):
+    omega = Fraction(omega)
+    keep = [np.ascontiguousarray(tg.offsets, dtype=np.int64),
+            np.ascontiguousarray(tg.src, dtype=np.int32),
+            np.ascontiguousarray(tg.dst, dtype=np.int32),
+            None if tg.weight is None else np.ascontiguousarray(tg.weight, dtype=np.int32)]
+    d = GraphDesc(tg.n_nodes, tg.n_slices, keep[0].ctypes.data, keep[1].ctypes.data,
+                  keep[2].ctypes.data, None if keep[3] is None else keep[3].ctypes.data,
+                  omega.numerator, omega.denominator, 0)
+    return d, keep
+
+
+def params(gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
+           flags=0) -> Params:
+    gamma = Fraction(gamma)
+    if omega is None:
+        on, od = 0, 0
+    else:
+        omega = Fraction(omega)
+        on, od = omega.numerator, omega.denominator
+    return Params(gamma.numerator, gamma.denominator, on, od, max_levels, max_iterations,
+                  max_sweeps, 0, seed, flags, 0)
+
+
+def stream_handle(stream=None):
+    """hipStream_t of a torch stream (torch.cuda.Stream on ROCm), or None for the default."""
+    if stream is None:
+        return None
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+class Graph:
+    """A temporal graph resident on the device (mslm_create / mslm_destroy)."""
+
+    def __init__(self, tg, omega=Fraction(1), stream=None):
+        lib = load()
+        self.n_nodes, self.n_slices = tg.n_nodes, tg.n_slices
+        self.omega = Fraction(omega)
+        d, keep = _desc(tg, omega)
+        h = C.c_void_p()
+        _check(lib.mslm_create(C.byref(d), stream_handle(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mslm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n, m, t = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().mslm_graph_info(self._h, C.byref(n), C.byref(m), C.byref(t)))
+        return dict(n_supra=n.value, nnz=m.value, two_m=t.value)
+
+    def leiden(self, gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0,
+               seed=0, profile=False, out=None):
+        """Returns (membership int32[T*N], result dict).  `out` may be a device tensor
+        (torch, int32, T*N elements) to receive the membership on the device."""
+        lib = load()
+        flags = MSLM_PROFILE if profile else 0
+        if out is not None:
+            flags |= MSLM_OUTPUT_ON_DEVICE
+            dest = C.c_void_p(int(out.data_ptr()))
+            memb = None
+        else:
+            memb = np.empty(self.n_nodes * self.n_slices, dtype=np.int32)
+            dest = _ptr(memb)
+        p = params(gamma, omega, max_levels, max_iterations, max_sweeps, seed, flags)
+        res = Result()
+        _check(lib.mslm_leiden(self._h, C.byref(p), dest, C.byref(res)))
+        return memb, res.as_dict(self.n_slices)
+
+
+def q_exact(components, n_slices, n_nodes, gamma, omega) -> Fraction:
+    """Exact Q (Eq. 6) from the 3T+1 integer components, via the library's reduction."""
+    lib = load()
+    gamma, omega = Fraction(gamma), Fraction(omega)
+    comps = np.ascontiguousarray(components, dtype=np.int64)
+    num = C.create_string_buffer(4096)
+    den = C.create_string_buffer(4096)
+    _check(lib.mslm_q_exact(_ptr(comps), n_slices, n_nodes, gamma.numerator, gamma.denominator,
+                            omega.numerator, omega.denominator, num, 4096, den, 4096))
+    return Fraction(int(num.value.decode()), int(den.value.decode()))
+
+
+def footprint_bytes(tg, omega=Fraction(1)) -> int:
+    d, keep = _desc(tg, omega)
+    return int(load().mslm_footprint_bytes(C.byref(d)))
+
+
+def batch_leiden(graphs: Sequence[Graph], solves, stream=None):
+    """solves: list of (graph index, gamma, omega, max_levels, max_iterations, seed).
+    Returns a list of (membership, result dict), bit-identical to plain calls."""
+    lib = load()
+    arr = (C.c_void_p * len(graphs))(*[g._h for g in graphs])
+    cs = (Solve * len(solves))()
+    outs = []
+    for i, (gi, gamma, omega, levels, iters, seed) in enumerate(solves):
+        g = graphs[gi]
+        memb = np.empty(g.n_nodes * g.n_slices, dtype=np.int32)
+        res = Result()
+        outs.append((memb, res, g.n_slices))
+        cs[i].graph = gi
+        cs[i].params = params(gamma, omega, levels, iters, 0, seed, 0)
+        cs[i].membership = memb.ctypes.data
+        cs[i].result = C.addressof(res)
+    _check(lib.mslm_batch_leiden(arr, len(graphs), cs, len(solves), stream_handle(stream)))
+    return [(m, r.as_dict(t)) for m, r, t in outs]

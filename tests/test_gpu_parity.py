@@ -1,0 +1,111 @@
+"""GPU parity: the HIP path (through the C ABI) against the C oracle, element by element.
+
+Memberships must be identical int32 arrays and the Q components identical integers (so Q
+is the same reduced fraction); the deterministic schedule statistics must agree too.
+"""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_03695_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+STAT_KEYS = ["sweeps", "moves", "sweep_cap_hits", "refine_rounds", "merges", "splits",
+             "levels_run", "iterations_run", "n_communities"]
+
+
+def _mslm():
+    from paper_2608_03695_amd import mslm
+    return mslm
+
+
+def run_both(tg, gamma, omega, **kw):
+    mslm = _mslm()
+    om, oc, ost = oracle.OracleGraph(tg, omega).leiden(gamma, **kw)
+    g = mslm.Graph(tg, omega)
+    gm, gr = g.leiden(gamma, **kw)
+    g.close()
+    return om, oc, ost, gm, gr
+
+
+def assert_same(tg, gamma, omega, **kw):
+    om, oc, ost, gm, gr = run_both(tg, gamma, omega, **kw)
+    case = f"{tg.name} N={tg.n_nodes} T={tg.n_slices} gamma={gamma} omega={omega} {kw}"
+    assert gm.shape == om.shape, case
+    bad = np.nonzero(gm != om)[0]
+    assert bad.size == 0, f"{case}: {bad.size} memberships differ, first at {bad[:5]}"
+    assert np.array_equal(gr["q_components"], oc), case
+    for k in STAT_KEYS:
+        assert gr[k] == ost[k], f"{case}: {k} gpu={gr[k]} oracle={ost[k]}"
+    mslm = _mslm()
+    q = mslm.q_exact(gr["q_components"], tg.n_slices, tg.n_nodes, gamma, omega)
+    assert q == oracle.q_from_components(oc, tg.n_nodes, tg.n_slices, gamma, omega), case
+    return gm, gr
+
+
+def test_config1_full_parity():
+    tg = gen.config1()
+    spec = gen.CONFIG_SOLVE[1]
+    assert_same(tg, spec.gamma, spec.omega, max_levels=32, max_iterations=2, seed=0)
+
+
+SMALL = [
+    ("er_sparse", lambda: gen.erdos_renyi(300, 3, 0.01, seed=1), F(1), F(1)),
+    ("er_weighted", lambda: gen.erdos_renyi(200, 4, 0.03, seed=2, weights_max=8), F(1), F(1, 2)),
+    ("planted_T5", lambda: gen.planted_partition(400, 5, 8, 0.08, 0.004, 0.1, seed=3), F(1), F(1, 10)),
+    ("planted_gamma2", lambda: gen.planted_partition(300, 3, 6, 0.1, 0.01, 0.2, seed=4), F(2), F(10)),
+    ("planted_gamma_half", lambda: gen.planted_partition(300, 3, 6, 0.1, 0.01, 0.2, seed=5), F(1, 2), F(1)),
+    ("static_T1", lambda: gen.planted_partition(500, 1, 5, 0.05, 0.005, 0.0, seed=6), F(1), F(1)),
+    ("omega_zero", lambda: gen.planted_partition(200, 4, 4, 0.1, 0.01, 0.1, seed=7), F(1), F(0)),
+    ("dcsbm_small", lambda: gen.dcsbm(2000, 6, 8, 20, 0.3, 2.5, 0.05, weights_max=8, seed=8), F(1), F(1)),
+    ("dcsbm_hubs", lambda: gen.dcsbm(3000, 3, 12, 10, 0.4, 2.1, 0.02, seed=9), F(1), F(1, 2)),
+]
+
+
+@pytest.mark.parametrize("name,make,gamma,omega", SMALL, ids=[s[0] for s in SMALL])
+def test_small_graphs_full_parity(name, make, gamma, omega):
+    assert_same(make(), gamma, omega, max_levels=32, max_iterations=2, seed=0)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(max_levels=1, max_iterations=1, max_sweeps=1),
+    dict(max_levels=1, max_iterations=1, max_sweeps=3),
+    dict(max_levels=2, max_iterations=1),
+    dict(max_levels=32, max_iterations=0),
+    dict(max_levels=32, max_iterations=3, seed=12345),
+])
+def test_schedule_knobs(kw):
+    tg = gen.planted_partition(500, 4, 10, 0.06, 0.004, 0.1, seed=11)
+    assert_same(tg, F(1), F(1), **kw)
+
+
+def test_degenerate_graphs():
+    assert_same(gen.from_edge_lists(3, [[], [], []]), F(1), F(1), max_iterations=0)
+    assert_same(gen.from_edge_lists(4, [[]]), F(1), F(1))
+    assert_same(gen.from_edge_lists(1, [[]] * 5), F(2), F(1, 3))
+    assert_same(gen.from_edge_lists(2, [[(0, 1)], [(0, 1)]]), F(1), F(1), max_iterations=0)
+    # repeated pairs inside a slice add up
+    assert_same(gen.from_edge_lists(4, [[(0, 1, 2), (1, 0, 3), (2, 3, 1)], [(0, 2, 5)]], weighted=True),
+                F(1), F(1))
+
+
+def test_hand_example_reaches_optimum():
+    mslm = _mslm()
+    tg = gen.from_edge_lists(2, [[(0, 1)], [(0, 1)]])
+    g = mslm.Graph(tg, 1)
+    m, r = g.leiden(1, max_iterations=0)
+    assert list(m) == [0, 0, 0, 0]
+    assert mslm.q_exact(r["q_components"], 2, 2, 1, 1) == F(1, 2)
+
+
+def test_repeat_runs_bit_identical():
+    mslm = _mslm()
+    tg = gen.dcsbm(5000, 8, 10, 30, 0.3, 2.5, 0.05, weights_max=4, seed=21)
+    g = mslm.Graph(tg, F(1, 2))
+    a, ra = g.leiden(1)
+    b, rb = g.leiden(1)
+    assert np.array_equal(a, b)
+    assert np.array_equal(ra["q_components"], rb["q_components"])
