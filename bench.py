@@ -1,0 +1,153 @@
+"""Benchmark of the multislice Leiden path on one MI355X.
+
+One step = one complete solve (mslm_leiden: every Leiden iteration, level, sweep,
+refinement round, aggregation, split and the Q components) on a supra-graph that is
+already resident in HBM.  Prints one JSON line (see the keys below).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg1]
+                    [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from fractions import Fraction
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+METRIC = "Leiden supra-edge TEPS + %HBM peak; batched solves/s vs plain; p99 latency"
+
+# algorithmic bytes of the level-0 decision kernels (see the design notes):
+#   per unit decided: batch id 4 + row pointers 8 + own label 4 + degree 4 + decision 4
+#   per adjacency entry scanned: column 4 + neighbour label 4 (+ weight 4 when weighted)
+#   per candidate community: one Sigma(C, s) slot probe 8
+BYTES_UNIT, BYTES_ENTRY, BYTES_WEIGHT, BYTES_CAND = 24, 8, 4, 8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2608_03695_amd import gen
+    if name == "cfg1":
+        return gen.config1(), gen.CONFIG_SOLVE[1]
+    if name == "cfg2":
+        return gen.config2(), gen.CONFIG_SOLVE[2]
+    if name == "cfg3":
+        return gen.config3(), gen.CONFIG_SOLVE[3]
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(args):
+    """The oracle, as it stands, on a bounded sample of the same workload family: the
+    config-2 generator restricted to its first 4 snapshots (same N, degree law, churn)."""
+    import oracle
+    from paper_2608_03695_amd import gen
+    tg = gen.dcsbm(100_000, 4, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=2,
+                   name="cfg2_first4_slices")
+    og = oracle.OracleGraph(tg, 1)
+    rp, col, w, raw, twom = og.csr()
+    m_supra = int(rp[-1]) // 2
+    t0 = time.perf_counter()
+    og.leiden(1, max_levels=32, max_iterations=2, seed=0)
+    dt = time.perf_counter() - t0
+    return {"value": m_supra / dt, "unit": "supra-edges/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{tg.name}: N=100k x T=4 snapshots of the config-2 generator, "
+                      f"{m_supra} supra-edges, one full solve (2 iterations) in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-count", action="store_true",
+                    help="skip the extra counting solve (keeps profiler traces to the timed steps)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              f"multi-GPU path", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    from paper_2608_03695_amd import mslm
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    log(f"generating {args.workload}")
+    tg, spec = workload(args.workload)
+    log(f"N={tg.n_nodes} T={tg.n_slices} E={tg.n_edges}; uploading")
+    stream = torch.cuda.current_stream()
+    g = mslm.Graph(tg, spec.omega, stream=stream)
+    info = g.info()
+    m_supra = info["nnz"] // 2
+    kw = dict(gamma=spec.gamma, max_levels=spec.max_levels, max_iterations=spec.max_iterations,
+              seed=spec.seed)
+    for i in range(args.warmup):
+        g.leiden(**kw)
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        _, r = g.leiden(profile=True, **kw)
+        results.append(r)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log("timed steps done")
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    # the schedule is deterministic: one counting run gives the exact work of every step
+    if args.no_count:
+        rc = {"lm_units": 0, "lm_entries": 0, "lm_candidates": 0}
+    else:
+        _, rc = g.leiden(count=True, **kw)
+    weighted = tg.weight is not None
+    per_step_bytes = (rc["lm_units"] * BYTES_UNIT
+                      + rc["lm_entries"] * (BYTES_ENTRY + (BYTES_WEIGHT if weighted else 0))
+                      + rc["lm_candidates"] * BYTES_CAND)
+    lm_ms = sum(r["lm_kernel_ms"] for r in results) / len(results)
+    launches = results[0]["lm_launches"]
+    achieved = per_step_bytes / (lm_ms * 1e-3) / 1e9 if lm_ms > 0 else 0.0
+    q = mslm.q_exact(results[-1]["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
+    out = {
+        "metric": METRIC,
+        "value": m_supra / (ms_step * 1e-3),
+        "unit": "supra-edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": tg.name, "n_nodes": tg.n_nodes, "n_slices": tg.n_slices,
+                   "supra_nodes": info["n_supra"], "supra_edges": m_supra,
+                   "gamma": str(spec.gamma), "omega": str(spec.omega),
+                   "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_lm_wave/k_lm_block/k_lm_gtab (local-moving decisions)",
+                     "bytes_per_step": per_step_bytes, "kernel_ms_per_step": lm_ms,
+                     "launches_per_step": launches,
+                     "avg_launch_us": lm_ms * 1e3 / max(launches, 1)},
+        "phases_ms": {k: results[-1][k] for k in ("ms_colour", "ms_local_move", "ms_refine",
+                                                  "ms_aggregate", "ms_finish")},
+        "solve": {"Q": float(q), "n_communities": results[-1]["n_communities"],
+                  "sweeps": results[-1]["sweeps"], "levels": results[-1]["levels_run"],
+                  "iterations": results[-1]["iterations_run"],
+                  "exact_fallbacks": results[-1]["exact_fallbacks"]},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -41,7 +41,7 @@ typedef enum {
 typedef struct mslm_graph mslm_graph;   /* owns the device supra-CSR of one temporal graph */
 typedef struct mslm_server mslm_server; /* continuous-batching request loop               */
 
-enum { MSLM_INPUT_ON_DEVICE = 1u, MSLM_OUTPUT_ON_DEVICE = 2u, MSLM_PROFILE = 4u };
+enum { MSLM_INPUT_ON_DEVICE = 1u, MSLM_OUTPUT_ON_DEVICE = 2u, MSLM_PROFILE = 4u, MSLM_COUNT = 8u };
 
 /* One temporal graph.  Slice s holds edges [slice_offsets[s], slice_offsets[s+1]) of
  * src/dst/weight: undirected, each edge listed once in either orientation, ids in [0, N),
@@ -74,7 +74,9 @@ typedef struct {
   int32_t reserved0;
   uint64_t seed;
   uint32_t flags;                 /* MSLM_OUTPUT_ON_DEVICE: membership is a device pointer;
-                                     MSLM_PROFILE: time every local-moving decision kernel */
+                                     MSLM_PROFILE: time every local-moving decision kernel
+                                     with HIP events on the graph's stream;
+                                     MSLM_COUNT: count the work of those kernels            */
   uint32_t reserved1;
 } mslm_params;
 
@@ -92,7 +94,7 @@ typedef struct {
                                      measured only with MSLM_PROFILE                        */
   int64_t lm_launches;            /* number of those kernel launches (MSLM_PROFILE)          */
   int64_t lm_units, lm_entries, lm_candidates;   /* work of those kernels: units decided,
-                                     adjacency entries scanned, candidate communities (PROFILE) */
+                                     adjacency entries scanned, candidate communities (COUNT) */
   int64_t q_components[3 * 64 + 1];
 } mslm_result;
 

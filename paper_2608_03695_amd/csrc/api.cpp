@@ -431,7 +431,8 @@ mslm_status mslm_leiden(mslm_graph *g, const mslm_params *params, int32_t *membe
   std::vector<SolveOut> outs(1);
   if (params->flags & MSLM_OUTPUT_ON_DEVICE) outs[0].dev_membership = membership;
   try {
-    run_solves({&g->g}, {sp}, outs, g->st, g->ws, (params->flags & MSLM_PROFILE) != 0);
+    run_solves({&g->g}, {sp}, outs, g->st, g->ws, (params->flags & MSLM_PROFILE) != 0,
+               (params->flags & MSLM_COUNT) != 0);
   } catch (const Error &e) {
     return fail(e.status, e.what());
   } catch (const std::exception &e) {

@@ -58,6 +58,44 @@ __device__ inline int64_t wave_sum64(int64_t v) {
   return v;
 }
 
+// Keyed counters with one atomic per distinct key present in the wave.  Every lane of the
+// wave must call these together (no lane may have left the kernel).
+__device__ inline void wave_count(uint32_t *ctr, int key, bool inc) {
+  const int lane = threadIdx.x & 63;
+  uint64_t m = __ballot(inc);
+  while (m) {
+    int leader = __builtin_ctzll(m);
+    int k = __shfl(key, leader, 64);
+    uint64_t same = __ballot(inc && key == k);
+    if (lane == leader) atomicAdd(ctr + k, (uint32_t)__popcll(same));
+    m &= ~same;
+  }
+}
+__device__ inline void wave_add64(int64_t *ctr, int key, int64_t val) {
+  const int lane = threadIdx.x & 63;
+  uint64_t m = __ballot(val != 0);
+  while (m) {
+    int leader = __builtin_ctzll(m);
+    int k = __shfl(key, leader, 64);
+    bool mine = val != 0 && key == k;
+    int64_t v = wave_sum64(mine ? val : 0);
+    if (lane == leader) atomicAdd(reinterpret_cast<unsigned long long *>(ctr + k), (unsigned long long)v);
+    m &= ~__ballot(mine);
+  }
+}
+
+// Append val to out[] for every lane with flag set: one atomic per wave (convergent code).
+__device__ inline void wave_append(int32_t *out, uint32_t *ctr, bool flag, int32_t val) {
+  const int lane = threadIdx.x & 63;
+  uint64_t bal = __ballot(flag);
+  if (!bal) return;
+  const int leader = __builtin_ctzll(bal);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(bal));
+  base = (uint32_t)__shfl((int)base, leader, 64);
+  if (flag) out[base + __popcll(bal & ((1ull << lane) - 1))] = val;
+}
+
 // ------------------------------------------------------------------ Sigma table
 // Slot layout: 64-bit word, low half = key (label + 1, 0 = empty), high half = value.
 // Values are slice degrees (< 2^31 by the create-time precondition).
@@ -84,7 +122,10 @@ __device__ inline int32_t tab_get(const SliceTable &t, int s, uint32_t label) {
   }
 }
 
-__device__ inline void tab_add(const SliceTable &t, int s, uint32_t label, int32_t delta) {
+// count_new: bump the slice's key counter when a new key is claimed (only the sweeps need
+// it, for the rebuild rule; full builds set the counters from known bounds instead)
+__device__ inline void tab_add(const SliceTable &t, int s, uint32_t label, int32_t delta,
+                               bool count_new = true) {
   const int sh = t.shift[s];
   const uint32_t mask = 0xffffffffu >> sh;
   uint64_t *sub = t.slots + t.base[s];
@@ -96,7 +137,7 @@ __device__ inline void tab_add(const SliceTable &t, int s, uint32_t label, int32
     if (k == 0) {
       uint32_t prev = atomicCAS(kp, 0u, key);
       if (prev == 0) {
-        atomicAdd(t.used + s, 1u);
+        if (count_new) atomicAdd(t.used + s, 1u);
         k = key;
       } else {
         k = prev;

@@ -93,6 +93,7 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
 // Run the schedule for one or more solves (each solve names a graph); results are
 // bit-identical to running every solve alone.
 void run_solves(const std::vector<const GraphDev *> &graphs, const std::vector<SolveSpec> &specs,
-                std::vector<SolveOut> &outs, hipStream_t st, Workspace *ws, bool profile);
+                std::vector<SolveOut> &outs, hipStream_t st, Workspace *ws, bool profile,
+                bool count = false);
 
 }  // namespace mslm

@@ -28,6 +28,7 @@ struct SolveDev {
 // Level 0: the supra-CSR of Eq. 3 with raw intra weights; an entry whose column lies
 // outside the unit's slice is a coupling entry of scaled weight a (absent when a == 0).
 struct View0 {
+  static constexpr bool kLevel0 = true;
   const int64_t *rp;
   const int32_t *col;
   const int32_t *w;        // raw intra weight per entry, or nullptr for unit weights
@@ -56,6 +57,7 @@ struct View0 {
 
 // Aggregated levels: scaled int64 weights, per-unit slice profiles (global slice, degree).
 struct ViewK {
+  static constexpr bool kLevel0 = false;
   const int64_t *rp;
   const int32_t *col;
   const int64_t *w;
@@ -159,7 +161,7 @@ struct ScoreK {
   double ap, er;
   int64_t W;
   uint32_t lab;
-  int kind;
+  int kind;   // kTarget / kEmpty / kStay; +4 when the value has no null term (it is q*W)
 };
 
 template <class V>
@@ -212,6 +214,7 @@ struct PolicyK {
       double qw = (double)u.q * (double)W;
       s.ap = qw - (double)u.pb * acc;
       s.er = (double)(u.m + 8) * 0x1p-50 * (fabs(qw) + (double)u.pb * mag);
+      if (mag == 0.0 || u.pb == 0) s.kind |= 4;
     }
     return s;
   }
@@ -219,10 +222,12 @@ struct PolicyK {
   __device__ static int cmp(const V &g, const UnitCtx &u, const SolveDev &sd, const SliceTable &tab,
                             const Score &a, const Score &b) {
     if (u.m <= 1) return a.ex < b.ex ? -1 : (a.ex > b.ex ? 1 : 0);
+    if (a.lab == b.lab && a.kind == b.kind && a.W == b.W) return 0;   // the same target
+    if ((a.kind & 4) && (b.kind & 4)) return a.W < b.W ? -1 : (a.W > b.W ? 1 : 0);   // both q*W
     double d = a.ap - b.ap;
     if (fabs(d) > 2.0 * (a.er + b.er)) return d > 0 ? 1 : -1;
     atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
-    return exact_cmp(g, u, sd, tab, a.lab, a.kind, a.W, b.lab, b.kind, b.W);
+    return exact_cmp(g, u, sd, tab, a.lab, a.kind & 3, a.W, b.lab, b.kind & 3, b.W);
   }
   __device__ static Score shfl(const Score &s, int m) {
     Score o;
@@ -372,6 +377,78 @@ constexpr int kBlockLg = 13;      // 8192-slot LDS table per block: degree <= 40
 constexpr int kWaveMaxDeg = 256;
 constexpr int kBlockMaxDeg = 4096;
 
+// Degree bins of the decision kernels: 0..3 lane groups of 4/8/16/32 lanes per unit (one
+// adjacency entry per lane, equal labels merged with shuffles), 4 a wave with an LDS
+// table, 5 a block with an LDS table, 6 a block with a global-memory table.
+constexpr int kNumBins = 7;
+__host__ __device__ inline uint32_t degree_bin(int64_t d) {
+  return d <= 4 ? 0u : d <= 8 ? 1u : d <= 16 ? 2u : d <= 32 ? 3u
+       : d <= kWaveMaxDeg ? 4u : d <= kBlockMaxDeg ? 5u : 6u;
+}
+
+// Units of degree <= G: G lanes per unit, one adjacency entry per lane; the group merges
+// equal community labels with shuffles (the first lane holding a label leads it), every
+// leader evaluates its community, and the group reduces to the best.
+template <class P, class V, int G>
+__global__ __launch_bounds__(256) void k_lm_group(V g, SolveDev sd, const int32_t *units,
+                                                  int64_t count, const uint32_t *comm,
+                                                  SliceTable sig, uint32_t *target,
+                                                  uint32_t fresh_base, LmCounters pc) {
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G - 1);
+  const int gbase = lane & ~(G - 1);
+  const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  if (idx >= count) return;   // whole groups leave together; shuffles stay inside a group
+  const int64_t v = units[idx];
+  const uint32_t D = comm[v];
+  typename V::Row row = g.row(v, sd);
+  const int64_t e = row.lo + gl;
+  uint32_t c = kNone;
+  int64_t w = 0;
+  if (e < row.hi) {
+    int32_t x = g.col[e];
+    w = g.wt(row, e, x);
+    if (w != 0) c = comm[x];
+  }
+  int64_t wsum = 0, wD = 0;
+  bool leader = c != kNone;
+  for (int j = 0; j < G; j++) {
+    uint32_t cj = (uint32_t)__shfl((int)c, gbase + j, 64);
+    int64_t wj = __shfl(w, gbase + j, 64);
+    if (cj == c) {
+      wsum += wj;
+      if (j < gl) leader = false;
+    }
+    if (cj == D) wD += wj;
+  }
+  UnitCtx u = unit_ctx(g, sd, v, D);
+  typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
+  const bool cand = leader && c != D;
+  if (cand) {
+    typename P::Score s = P::make(g, u, sd, sig, c, wsum, kTarget);
+    if (better<P>(g, u, sd, sig, s, best)) best = s;
+  }
+  for (int m = G / 2; m >= 1; m >>= 1) {
+    typename P::Score o = P::shfl(best, m);
+    if (better<P>(g, u, sd, sig, o, best)) best = o;
+  }
+  if (pc.c) {
+    unsigned long long nc = __popcll(__ballot(cand) & (((G == 64) ? ~0ull : ((1ull << G) - 1)) << gbase));
+    if (gl == 0) {
+      atomicAdd(pc.c + 0, 1ull);
+      atomicAdd(pc.c + 1, (unsigned long long)(row.hi - row.lo));
+      if (nc) atomicAdd(pc.c + 2, nc);
+    }
+  }
+  if (gl == 0) {
+    typename P::Score stay = P::make(g, u, sd, sig, D, wD, kStay);
+    uint32_t out = kNone;
+    if (P::cmp(g, u, sd, sig, best, stay) > 0)
+      out = best.lab == kNone ? fresh_base + (uint32_t)v : best.lab;
+    target[idx] = out;
+  }
+}
+
 template <class P, class V>
 __global__ __launch_bounds__(256) void k_lm_wave(V g, SolveDev sd, const int32_t *units,
                                                  int64_t count, const uint32_t *comm,
@@ -425,24 +502,28 @@ template <class V>
 __global__ void k_lm_apply(V g, const int32_t *units, int64_t count, const uint32_t *target,
                            uint32_t *comm, SliceTable sig, uint32_t *moved,
                            const uint8_t *frozen) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  uint32_t C = target[i];
-  if (C == kNone) return;
-  int64_t v = units[i];
-  int j = g.usolve[v];
-  if (frozen[j]) return;
-  uint32_t D = comm[v];
-  int m = g.plen(v);
-  for (int jj = 0; jj < m; jj++) {
-    int gs;
-    int64_t k;
-    g.pent(v, jj, gs, k);
-    tab_add(sig, gs, D, -(int32_t)k);
-    tab_add(sig, gs, C, (int32_t)k);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool mv = false;
+  int j = 0;
+  if (i < count) {
+    const uint32_t C = target[i];
+    const int64_t v = units[i];
+    j = g.usolve[v];
+    if (C != kNone && !frozen[j]) {
+      const uint32_t D = comm[v];
+      const int m = g.plen(v);
+      for (int jj = 0; jj < m; jj++) {
+        int gs;
+        int64_t k;
+        g.pent(v, jj, gs, k);
+        tab_add(sig, gs, D, -(int32_t)k);
+        tab_add(sig, gs, C, (int32_t)k);
+      }
+      comm[v] = C;
+      mv = true;
+    }
   }
-  comm[v] = C;
-  atomicAdd(moved + j, 1u);
+  wave_count(moved, j, mv);
 }
 
 template <class V>
@@ -454,7 +535,7 @@ __global__ void k_sigma_build(V g, int64_t n, const uint32_t *comm, SliceTable s
     int gs;
     int64_t k;
     g.pent(v, jj, gs, k);
-    tab_add(sig, gs, comm[v], (int32_t)k);
+    tab_add(sig, gs, comm[v], (int32_t)k, false);
   }
 }
 
@@ -464,66 +545,94 @@ __global__ void k_rebuild_check(const uint32_t *used, const uint32_t *limit, int
 }
 
 // ------------------------------------------------------------------ colouring
-// First-fit colouring in decreasing priority (Jones-Plassmann rounds): a unit takes the
-// smallest colour unused by its higher-priority neighbours once all of them are coloured.
-// The result equals the sequential greedy colouring in priority order.
+// First-fit colouring in decreasing priority (Jones-Plassmann): a unit takes the smallest
+// colour unused by its higher-priority neighbours once all of them are coloured.  The
+// result equals the sequential greedy colouring in priority order.  Each unit counts its
+// higher-priority neighbours once; a round colours the ready frontier and releases the
+// lower-priority neighbours, so every row is scanned a constant number of times.
 template <class V>
-__global__ __launch_bounds__(256) void k_jp(V g, SolveDev sd, const int32_t *work, int64_t nwork,
-                                            int32_t *colour, int32_t *next, uint32_t *nnext,
-                                            int it, int lvl) {
+__global__ __launch_bounds__(256) void k_jp_count(V g, SolveDev sd, const int32_t *work,
+                                                  int64_t nwork, uint32_t *cnt, int32_t *front,
+                                                  uint32_t *nfront, int it, int lvl) {
+  // one thread per unit; ready units are appended once per wave
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ready = false;
+  int64_t v = 0;
+  if (idx < nwork) {
+    v = work[idx];
+    const int j = g.usolve[v];
+    const uint64_t sm = sd.seedmix[j];
+    const int64_t off = sd.uoff[j];
+    const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+    typename V::Row row = g.row(v, sd);
+    uint32_t c = 0;
+    for (int64_t e = row.lo; e < row.hi; e++) {
+      int32_t x = g.col[e];
+      if (g.wt(row, e, x) == 0) continue;
+      uint64_t hx = priority(sm, it, lvl, 0, (uint32_t)(x - off));
+      if (outranks(hx, (uint32_t)x, hv, (uint32_t)v)) c++;
+    }
+    cnt[v] = c;
+    ready = c == 0;
+  }
+  wave_append(front, nfront, ready, (int32_t)v);
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_jp_front(V g, SolveDev sd, const int32_t *front, int64_t nf,
+                                                  int32_t *colour, uint32_t *cnt, int32_t *next,
+                                                  uint32_t *nnext, int it, int lvl) {
   const int lane = threadIdx.x & 63;
   const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= nwork) return;
-  const int64_t v = work[idx];
+  if (idx >= nf) return;
+  const int64_t v = front[idx];
   const int j = g.usolve[v];
   const uint64_t sm = sd.seedmix[j];
   const int64_t off = sd.uoff[j];
   const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
   typename V::Row row = g.row(v, sd);
-  int blocked = 0;
-  int base = 0;
   int result = -1;
-  for (;;) {
+  for (int base = 0; result < 0; base += 64) {
     uint64_t used = 0;
     for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
       int32_t x = g.col[e];
       if (g.wt(row, e, x) == 0) continue;
       uint64_t hx = priority(sm, it, lvl, 0, (uint32_t)(x - off));
       if (!outranks(hx, (uint32_t)x, hv, (uint32_t)v)) continue;
-      int cx = __hip_atomic_load(colour + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (cx < 0) {
-        blocked = 1;
-      } else if (cx >= base && cx < base + 64) {
-        used |= 1ull << (cx - base);
+      int cx = colour[x];
+      if (cx >= base && cx < base + 64) used |= 1ull << (cx - base);
+    }
+    for (int m = 32; m >= 1; m >>= 1) used |= (uint64_t)shfl_xor64((int64_t)used, m);
+    if (~used) result = base + __builtin_ctzll(~used);
+  }
+  if (lane == 0) colour[v] = result;
+  // release the lower-priority neighbours; the last one to be released joins the next round
+  for (int64_t e0 = row.lo; e0 < row.hi; e0 += 64) {
+    int64_t e = e0 + lane;
+    bool ready = false;
+    int32_t x = 0;
+    if (e < row.hi) {
+      x = g.col[e];
+      if (g.wt(row, e, x) != 0) {
+        uint64_t hx = priority(sm, it, lvl, 0, (uint32_t)(x - off));
+        if (!outranks(hx, (uint32_t)x, hv, (uint32_t)v)) ready = atomicSub(cnt + x, 1u) == 1u;
       }
     }
-    for (int m = 32; m >= 1; m >>= 1) {
-      used |= (uint64_t)shfl_xor64((int64_t)used, m);
-      blocked |= __shfl_xor(blocked, m, 64);
-    }
-    if (blocked) break;
-    if (~used) {
-      result = base + __builtin_ctzll(~used);
-      break;
-    }
-    base += 64;
-  }
-  if (lane == 0) {
-    if (blocked) {
-      uint32_t pos = atomicAdd(nnext, 1u);
-      next[pos] = (int32_t)v;
-    } else {
-      __hip_atomic_store(colour + v, result, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    uint64_t bal = __ballot(ready);
+    if (!bal) continue;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(nnext, (uint32_t)__popcll(bal));
+    base = (uint32_t)__shfl((int)base, 0, 64);
+    if (ready) next[base + __popcll(bal & ((1ull << lane) - 1))] = x;
   }
 }
 
-// sort key of a unit for batching: colour, then degree bin (wave / block-LDS / global table)
+// sort key of a unit for batching: colour, then degree bin
 constexpr uint32_t kInactiveKey = 0xfffffffcu;
 
 template <class V>
 __global__ void k_batch_keys(V g, int64_t n, const int32_t *colour, const uint8_t *sactive,
-                             uint32_t *keys, uint32_t *vals, uint32_t *hist) {
+                             uint32_t *keys, uint32_t *vals) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   vals[v] = (uint32_t)v;
@@ -531,26 +640,24 @@ __global__ void k_batch_keys(V g, int64_t n, const int32_t *colour, const uint8_
     keys[v] = kInactiveKey;
     return;
   }
-  int64_t d = g.degree(v);
-  uint32_t bin = d <= kWaveMaxDeg ? 0u : (d <= kBlockMaxDeg ? 1u : 2u);
-  uint32_t key = ((uint32_t)colour[v] << 2) | bin;
-  keys[v] = key;
-  atomicAdd(hist + key, 1u);
+  keys[v] = ((uint32_t)colour[v] << 3) | degree_bin(g.degree(v));
 }
 
 template <class V>
-__global__ void k_bin_keys(V g, int64_t n, const uint8_t *sactive, uint32_t *keys, uint32_t *vals,
-                           uint32_t *hist) {
+__global__ void k_bin_keys(V g, int64_t n, const uint8_t *sactive, uint32_t *keys, uint32_t *vals) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   vals[v] = (uint32_t)v;
-  uint32_t bin = 3;
-  if (sactive[g.usolve[v]]) {
-    int64_t d = g.degree(v);
-    bin = d <= kWaveMaxDeg ? 0u : (d <= kBlockMaxDeg ? 1u : 2u);
-  }
+  uint32_t bin = kNumBins;
+  if (sactive[g.usolve[v]]) bin = degree_bin(g.degree(v));
   keys[v] = bin;
-  atomicAdd(hist + bin, 1u);
+}
+// first[key] = first position of key in a sorted key array (keys below nkeys only)
+__global__ void k_key_bounds(const uint32_t *sk, int64_t n, uint32_t nkeys, int64_t *first) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t k = sk[i];
+  if (k < nkeys && (i == 0 || sk[i - 1] != k)) first[k] = i;
 }
 
 // per unit of the global-table bin: table size (power of two >= 2*degree), by unit id
@@ -601,7 +708,7 @@ __global__ __launch_bounds__(256) void k_ref_init(V g, SolveDev sd, int64_t n, c
     int64_t k;
     g.pent(v, jj, gs, k);
     mk |= 1ull << (gs - sd.sfirst[j]);
-    if (jj % 64 == lane) tab_add(sr, gs, (uint32_t)v, (int32_t)k);
+    if (jj % 64 == lane) tab_add(sr, gs, (uint32_t)v, (int32_t)k, false);
   }
   if (lane == 0) {
     R[v] = (uint32_t)v;
@@ -650,6 +757,8 @@ __global__ void k_ref_wc(V g, SolveDev sd, const int32_t *list, int64_t count, c
   if (m <= 1) {
     i128 val = (i128)q * ext[T] * (m ? sd.S[gs0] : 1) - (i128)pb * c0;
     sign = val < 0 ? -1 : (val > 0 ? 1 : 0);
+  } else if (mag == 0.0 || pb == 0) {
+    sign = ext[T] > 0 ? 1 : (ext[T] < 0 ? -1 : 0);
   } else {
     double qw = (double)q * (double)ext[T];
     double ap = qw - (double)pb * acc;
@@ -805,10 +914,9 @@ __global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, int64_t 
     if (outranks(hx, (uint32_t)x, hv, (uint32_t)v)) beaten = 1;
   }
   for (int m = 32; m >= 1; m >>= 1) beaten |= __shfl_xor(beaten, m, 64);
-  if (lane == 0) {
-    elig[v] = !beaten;
-    if (!beaten) atomicAdd(nelig + j, 1u);
-  }
+  if (lane == 0) elig[v] = !beaten;
+  (void)nelig;
+  (void)j;
 }
 
 template <class V>
@@ -828,7 +936,7 @@ __global__ void k_ref_apply(V g, SolveDev sd, int64_t n, const uint32_t *prop, c
     int gs;
     int64_t k;
     g.pent(v, jj, gs, k);
-    tab_add(sr, gs, T, (int32_t)k);
+    tab_add(sr, gs, T, (int32_t)k, false);
   }
   atomicOr(reinterpret_cast<unsigned long long *>(mask + T), (unsigned long long)mask[v]);
   changed[T] = 1;
@@ -853,62 +961,62 @@ __global__ void k_rank_gather(const uint32_t *R, const uint32_t *minm, const int
   r[u] = m == kNone ? kNone : (uint32_t)rank[m];
 }
 
-// emit (r[u], r[x]) keys for every entry between different super-nodes
+// key (r[u], r[x]) of every entry between different super-nodes, written at the entry's own
+// position; dropped entries get the all-ones key, which sorts last
+constexpr uint64_t kDropKey = ~0ull;
 template <class V>
 __global__ __launch_bounds__(256) void k_agg_keys(V g, SolveDev sd, int64_t n, const uint32_t *r,
-                                                  uint64_t *keys, int64_t *vals,
-                                                  unsigned long long *counter) {
+                                                  uint64_t *keys, int64_t *vals) {
   const int lane = threadIdx.x & 63;
   const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (u >= n) return;
   const uint32_t ru = r[u];
-  if (ru == kNone) return;
   typename V::Row row = g.row(u, sd);
-  for (int64_t e0 = row.lo; e0 < row.hi; e0 += 64) {
-    int64_t e = e0 + lane;
-    bool emit = false;
-    uint32_t rx = 0;
-    int64_t w = 0;
-    if (e < row.hi) {
-      int32_t x = g.col[e];
-      w = g.wt(row, e, x);
-      rx = r[x];
-      emit = w != 0 && rx != ru;
-    }
-    uint64_t bal = __ballot(emit);
-    if (!bal) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(counter, (unsigned long long)__popcll(bal));
-    base = __shfl(base, 0, 64);
-    if (emit) {
-      uint64_t below = lane ? (bal & ((1ull << lane) - 1)) : 0;
-      unsigned long long pos = base + __popcll(below);
-      keys[pos] = ((uint64_t)ru << 32) | rx;
-      vals[pos] = w;
-    }
+  for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+    int32_t x = g.col[e];
+    int64_t w = g.wt(row, e, x);
+    uint32_t rx = ru == kNone ? kNone : r[x];
+    bool emit = ru != kNone && w != 0 && rx != ru;
+    keys[e] = emit ? (((uint64_t)ru << 32) | rx) : kDropKey;
+    vals[e] = emit ? w : 0;
   }
 }
 
+// profile entries (r[u], slice) at fixed positions: level 0 one per unit, later pp[u] + j
+__device__ inline int64_t prof_pos(const View0 &, int64_t u, int) { return u; }
+__device__ inline int64_t prof_pos(const ViewK &g, int64_t u, int j) { return g.pp[u] + j; }
 template <class V>
-__global__ void k_agg_prof_keys(V g, int64_t n, const uint32_t *r, uint64_t *keys, int32_t *vals,
-                                unsigned long long *counter) {
+__global__ void k_agg_prof_keys(V g, int64_t n, const uint32_t *r, uint64_t *keys, int32_t *vals) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n || r[u] == kNone) return;
+  if (u >= n) return;
   int m = g.plen(u);
-  if (m == 0) return;
-  unsigned long long pos = atomicAdd(counter, (unsigned long long)m);
+  if (V::kLevel0 && m == 0) {
+    keys[u] = kDropKey;
+    vals[u] = 0;
+    return;
+  }
   for (int jj = 0; jj < m; jj++) {
     int gs;
     int64_t k;
     g.pent(u, jj, gs, k);
-    keys[pos + jj] = ((uint64_t)r[u] << 32) | (uint32_t)gs;
-    vals[pos + jj] = (int32_t)k;
+    int64_t pos = prof_pos(g, u, jj);
+    bool keep = r[u] != kNone;
+    keys[pos] = keep ? (((uint64_t)r[u] << 32) | (uint32_t)gs) : kDropKey;
+    vals[pos] = keep ? (int32_t)k : 0;
   }
 }
 
-__global__ void k_row_counts(const uint64_t *keys, int64_t m, int64_t *cnt) {
+// row bounds of a sorted key array (row = high 32 bits): rs[row] = first, re[row] = last + 1
+__global__ void k_row_bounds(const uint64_t *keys, int64_t m, int64_t *rs, int64_t *re) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) atomicAdd(reinterpret_cast<unsigned long long *>(cnt + (keys[i] >> 32)), 1ull);
+  if (i >= m) return;
+  uint64_t row = keys[i] >> 32;
+  if (i == 0 || (keys[i - 1] >> 32) != row) rs[row] = i;
+  if (i == m - 1 || (keys[i + 1] >> 32) != row) re[row] = i + 1;
+}
+__global__ void k_row_cnt(const int64_t *rs, const int64_t *re, int64_t n, int64_t *cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = re[i] - rs[i];
 }
 __global__ void k_low32(const uint64_t *keys, int64_t m, int32_t *out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -958,11 +1066,18 @@ __global__ void k_seg_label(const uint32_t *sv, const uint8_t *head, const int64
 __global__ void k_count_heads(const uint32_t *sv, const uint8_t *head, const int32_t *usolve,
                               int64_t n, uint32_t *cnt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && head[i]) atomicAdd(cnt + usolve[sv[i]], 1u);
+  bool h = i < n && head[i];
+  wave_count(cnt, h ? usolve[sv[i]] : 0, h);
 }
 __global__ void k_count_roots_R(const uint32_t *R, const int32_t *usolve, int64_t n, uint32_t *cnt) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u < n && R[u] == (uint32_t)u) atomicAdd(cnt + usolve[u], 1u);
+  bool h = u < n && R[u] == (uint32_t)u;
+  wave_count(cnt, h ? usolve[u] : 0, h);
+}
+__global__ void k_count_flags(const uint8_t *flag, const int32_t *usolve, int64_t n, uint32_t *cnt) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool h = u < n && flag[u];
+  wave_count(cnt, h ? usolve[u] : 0, h);
 }
 
 // ------------------------------------------------------------------ split into connected parts
@@ -1046,65 +1161,78 @@ __global__ void k_flatten(const int64_t *map0, const uint32_t *P, const int64_t 
 
 __global__ void k_count_diff(const int32_t *a, const int32_t *b, const int32_t *usolve,
                              const int64_t *lo, const int64_t *hi, int nr, uint32_t *diff) {
-  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // convergent loops: every lane of a wave runs the same iterations
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ll;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int k = 0; k < nr; k++)
-    for (int64_t i = lo[k] + tid; i < hi[k]; i += stride)
-      if (a[i] != b[i]) atomicAdd(diff + usolve[i], 1u);
+    for (int64_t b0 = lo[k] + wave0; b0 < hi[k]; b0 += stride) {
+      int64_t i = b0 + lane;
+      bool d = i < hi[k] && a[i] != b[i];
+      wave_count(diff, d ? usolve[i] : 0, d);
+    }
 }
 
 // ------------------------------------------------------------------ Q components
-// W_s: intra weight inside communities (both directions, unscaled) per global slice.
-__global__ __launch_bounds__(256) void k_q_w(View0 g, int64_t n, const int32_t *memb, int64_t *W) {
-  const int lane = threadIdx.x & 63;
-  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (v >= n) return;
-  const int gs = g.uslice[v];
-  const int64_t slo = g.sstart[gs], shi = g.sstart[gs + 1];
-  const int32_t L = memb[v];
+// W_s: intra weight inside communities (both directions, unscaled) per global slice; one
+// thread per unit, sums merged per wave by slice
+__global__ void k_q_w(View0 g, int64_t n, const int32_t *memb, int64_t *W) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t s = 0;
-  for (int64_t e = g.rp[v] + lane; e < g.rp[v + 1]; e += 64) {
-    int32_t x = g.col[e];
-    if (x >= slo && x < shi && memb[x] == L) s += g.w ? g.w[e] : 1;
+  int gs = 0;
+  if (v < n) {
+    gs = g.uslice[v];
+    const int64_t slo = g.sstart[gs], shi = g.sstart[gs + 1];
+    const int32_t L = memb[v];
+    for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
+      int32_t x = g.col[e];
+      if (x >= slo && x < shi && memb[x] == L) s += g.w ? g.w[e] : 1;
+    }
   }
-  s = wave_sum64(s);
-  if (lane == 0 && s) atomicAdd(reinterpret_cast<unsigned long long *>(W + gs), (unsigned long long)s);
+  wave_add64(W, gs, s);
 }
 
 __global__ void k_sigma_build_memb(View0 g, int64_t n, const int32_t *memb, SliceTable t) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int k = g.k[v];
-  if (k > 0) tab_add(t, g.uslice[v], (uint32_t)memb[v], k);
+  if (k > 0) tab_add(t, g.uslice[v], (uint32_t)memb[v], k, false);
 }
 
 // SS_s: sum over the slice's sub-table of value^2
 __global__ void k_q_ss(const uint64_t *slots, const int64_t *base, int nslices, int64_t total,
                        int64_t *SS) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  uint64_t e = slots[i];
-  if ((uint32_t)e == 0) return;
-  int64_t val = (int32_t)(e >> 32);
-  if (val == 0) return;
-  int lo = 0, hi = nslices;   // base[lo] <= i < base[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (base[mid] <= i) lo = mid; else hi = mid;
+  int64_t sq = 0;
+  int lo = 0;
+  if (i < total) {
+    uint64_t e = slots[i];
+    int64_t val = (uint32_t)e ? (int32_t)(e >> 32) : 0;
+    sq = val * val;
+    int hi = nslices;   // base[lo] <= i < base[hi]
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (base[mid] <= i) lo = mid; else hi = mid;
+    }
   }
-  atomicAdd(reinterpret_cast<unsigned long long *>(SS + lo), (unsigned long long)(val * val));
+  wave_add64(SS, lo, sq);
 }
 
 // I: ordered coupled copy pairs (i,s),(i,s+1) sharing a community, per solve
 __global__ void k_q_inter(View0 g, int64_t n, const int32_t *memb, const int32_t *slast,
                           int64_t *I) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  int gs = g.uslice[v];
-  int j = g.usolve[v];
-  if (gs >= slast[j]) return;   // last slice of its solve
-  int64_t N = g.sstart[gs + 1] - g.sstart[gs];
-  if (memb[v] == memb[v + N]) atomicAdd(reinterpret_cast<unsigned long long *>(I + j), 2ull);
+  int64_t add = 0;
+  int j = 0;
+  if (v < n) {
+    int gs = g.uslice[v];
+    j = g.usolve[v];
+    if (gs < slast[j]) {   // not the last slice of its solve
+      int64_t N = g.sstart[gs + 1] - g.sstart[gs];
+      if (memb[v] == memb[v + N]) add = 2;
+    }
+  }
+  wave_add64(I, j, add);
 }
 
 // ------------------------------------------------------------------ small utilities

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmslm.so")
 
 MSLM_OK, MSLM_EINVAL, MSLM_ENOMEM, MSLM_EOVERFLOW, MSLM_EUNSUPPORTED, MSLM_EHIP, MSLM_EBUSY = \
     0, -1, -2, -3, -4, -5, -6
-MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE = 1, 2, 4
+MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE, MSLM_COUNT = 1, 2, 4, 8
 
 EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_footprint_bytes",
             "mslm_graph_info", "mslm_last_error", "mslm_batch_leiden", "mslm_server_create",
@@ -182,11 +182,11 @@ class Graph:
         return dict(n_supra=n.value, nnz=m.value, two_m=t.value)
 
     def leiden(self, gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0,
-               seed=0, profile=False, out=None):
+               seed=0, profile=False, count=False, out=None):
         """Returns (membership int32[T*N], result dict).  `out` may be a device tensor
         (torch, int32, T*N elements) to receive the membership on the device."""
         lib = load()
-        flags = MSLM_PROFILE if profile else 0
+        flags = (MSLM_PROFILE if profile else 0) | (MSLM_COUNT if count else 0)
         if out is not None:
             flags |= MSLM_OUTPUT_ON_DEVICE
             dest = C.c_void_p(int(out.data_ptr()))

@@ -109,3 +109,27 @@ def test_repeat_runs_bit_identical():
     b, rb = g.leiden(1)
     assert np.array_equal(a, b)
     assert np.array_equal(ra["q_components"], rb["q_components"])
+
+
+def test_config2_full_size_matches_oracle_record():
+    """Full-size config 2 (T=16 x N=100k, weights 1..8) against the oracle's stored result
+    (tests/golden/cfg2_expected.json, written by tests/golden/make_expected.py from the
+    oracle alone)."""
+    import hashlib
+    import json
+    import os
+    mslm = _mslm()
+    path = os.path.join(os.path.dirname(__file__), "golden", "cfg2_expected.json")
+    exp = json.load(open(path))
+    tg = gen.config2()
+    spec = gen.CONFIG_SOLVE[2]
+    g = mslm.Graph(tg, spec.omega)
+    memb, r = g.leiden(spec.gamma, max_levels=spec.max_levels,
+                       max_iterations=spec.max_iterations, seed=spec.seed)
+    g.close()
+    assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == exp["membership_sha256"]
+    assert [int(x) for x in r["q_components"]] == exp["q_components"]
+    q = mslm.q_exact(r["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
+    assert f"{q.numerator}/{q.denominator}" == exp["q"]
+    for k in STAT_KEYS:
+        assert r[k] == exp["stats"][k], k
