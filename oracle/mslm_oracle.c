@@ -681,9 +681,16 @@ static int64_t refine(const ctx_t *cx, const level_t *g, const uint32_t *P, cons
       free(buf); free(y);
     }
     for (int64_t v = 0; v < n; v++) if (active[v] && prop[v] == NONE_LABEL) active[v] = 0;
+    /* A proposer merges when its target sub-community keeps all its members this round:
+     *   (a) the target's founder does not propose (a larger sub-community never proposes), or
+     *   (b) the proposer outranks every proposing neighbour of its community and the target's
+     *       founder proposes to a target that is itself proposing (so the founder stays). */
     for (int64_t v = 0; v < n; v++) {
       elig[v] = 0;
       if (prop[v] == NONE_LABEL) continue;
+      uint32_t T = prop[v];
+      if (prop[T] == NONE_LABEL) { elig[v] = 1; any = 1; continue; }
+      if (prop[prop[T]] == NONE_LABEL) continue;
       int ok = 1;
       for (int64_t e = g->rp[v]; e < g->rp[v + 1] && ok; e++) {
         int32_t u = g->col[e];
@@ -698,9 +705,15 @@ static int64_t refine(const ctx_t *cx, const level_t *g, const uint32_t *P, cons
     for (int64_t v = 0; v < n; v++) {
       if (!elig[v]) continue;
       uint32_t T = prop[v];
+      /* edges to co-joiners of the same target become internal too */
+      int64_t corr = 0;
+      for (int64_t e = g->rp[v]; e < g->rp[v + 1]; e++) {
+        int32_t x = g->col[e];
+        if (elig[x] && prop[x] == T) corr += g->w[e];
+      }
       R[v] = T;
       single[v] = 0; active[v] = 0; single[T] = 0; active[T] = 0;
-      ext[T] += ext[v] - 2 * propw[v];
+      ext[T] += ext[v] - 2 * propw[v] - corr;
       for (int64_t j = g->pp[v]; j < g->pp[v + 1]; j++) map_add(&sr, T, g->ps[j], g->pk[j]);
       mask[T] |= mask[v];
       changed[T] = 1;

@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -71,11 +73,12 @@ struct Workspace {
   Buf colour, work0, work1, nwork, bkeys, bvals, bkeys2, bvals2, hist, target;
   Buf gk, gv, goff, glg;
   Buf sig_slots, sig_base, sig_shift, sig_used, sig_limit, sr_slots, sr_used, flag;
-  Buf R, ext, mask, active, wcT, elig, changed, clist, ccount, prop, propw;
+  Buf R, ext, mask, active, wcT, elig, changed, clist, ccount, prop, propr, propw;
   Buf r, minm, flag8, rank, akeys, avals, akeys2, avals2, nuniq, rowcnt, pkeys, pvals, pkeys2,
       pvals2, pnext;
   Buf ckeys, cvals, ckeys2, cvals2, head, ismin, segx, minof, crank;
   Buf qW, qSS, qI, ranges_lo, ranges_hi, ranges_off;
+  Buf sm_maxsw, sm_stat, sm_nz, sm_start;
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };

@@ -14,6 +14,15 @@ namespace mslm {
 
 typedef __int128 i128;
 
+// Barrier for one workgroup that also makes global writes of every wave visible to the
+// others: release before the barrier, and drop possibly stale vector-L1 lines after it
+// (Sigma-table atomics are performed in L2).
+__device__ inline void block_sync_global() {
+  __threadfence();
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // ------------------------------------------------------------------ per-solve constants
 struct SolveDev {
   const int64_t *p, *q, *pb, *a, *b;   // gamma = p/q, omega = a/b (reduced), pb = p*b
@@ -145,6 +154,12 @@ struct Policy0 {
                             const Score &a, const Score &b) {
     return a.g < b.g ? -1 : (a.g > b.g ? 1 : 0);
   }
+  // the null term is never negative, so q*S*W bounds a target's value from above; a target
+  // whose bound is strictly below the best value so far can neither win nor tie
+  __device__ static bool prunable(const UnitCtx &u, int64_t W, const Score &best) {
+    int64_t ub = u.m == 0 ? u.q * W : u.q * u.S0 * W;
+    return ub < best.g;
+  }
   __device__ static Score shfl(const Score &s, int m) {
     Score o;
     o.g = shfl_xor64(s.g, m);
@@ -228,6 +243,15 @@ struct PolicyK {
     if (fabs(d) > 2.0 * (a.er + b.er)) return d > 0 ? 1 : -1;
     atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
     return exact_cmp(g, u, sd, tab, a.lab, a.kind & 3, a.W, b.lab, b.kind & 3, b.W);
+  }
+  __device__ static bool prunable(const UnitCtx &u, int64_t W, const Score &best) {
+    if (u.m <= 1) {
+      i128 ub = (i128)u.q * W * (u.m ? u.S0 : 1);
+      return ub < best.ex;
+    }
+    // q*W rounded up versus a rigorous lower bound of the best value
+    double ub = (double)u.q * (double)W * (1.0 + 0x1p-48);
+    return ub < best.ap - best.er;
   }
   __device__ static Score shfl(const Score &s, int m) {
     Score o;
@@ -317,6 +341,48 @@ __device__ inline typename P::Score group_best(BlockGrp grp, const V &g, const U
   return b;
 }
 
+// heaviest entry of the accumulation table over the group (ties to the lower label), skipping
+// one excluded label; kNone when there is none
+template <class Grp, class Tab>
+__device__ inline void group_heaviest(Grp grp, const Tab &tab, uint32_t skip, const uint8_t *ok,
+                                      int64_t &W, uint32_t &lab, int64_t *sred, uint32_t *lred) {
+  const int r = grp.rank(), gsz = grp.size();
+  W = -1;
+  lab = kNone;
+  for (int i = r; i < tab.size(); i += gsz) {
+    uint32_t key = tab.K[i];
+    if (key == 0 || key - 1 == skip) continue;
+    if (ok && !ok[key - 1]) continue;
+    int64_t w = tab.V[i];
+    if (w > W || (w == W && key - 1 < lab)) {
+      W = w;
+      lab = key - 1;
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    int64_t w2 = shfl_xor64(W, m);
+    uint32_t l2 = shfl_xor32(lab, m);
+    if (w2 > W || (w2 == W && l2 < lab)) {
+      W = w2;
+      lab = l2;
+    }
+  }
+  if (gsz > 64) {
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      sred[wv] = W;
+      lred[wv] = lab;
+    }
+    grp.sync();
+    for (int i = 0; i < nw; i++)
+      if (sred[i] > W || (sred[i] == W && lred[i] < lab)) {
+        W = sred[i];
+        lab = lred[i];
+      }
+    grp.sync();
+  }
+}
+
 // ------------------------------------------------------------------ local moving
 // One unit: accumulate neighbour-community weights in the table, evaluate every candidate
 // community (strictly better gain wins, ties to the lower label, the empty community has
@@ -330,7 +396,8 @@ struct LmCounters {
 template <class P, class V, class Grp, class Tab>
 __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd, int64_t v,
                                    const uint32_t *comm, const SliceTable &sig, uint32_t fresh_base,
-                                   typename P::Score *red, LmCounters pc) {
+                                   typename P::Score *red, LmCounters pc, int64_t *sredW = nullptr,
+                                   uint32_t *sredL = nullptr) {
   const int r = grp.rank(), gsz = grp.size();
   for (int i = r; i < tab.size(); i += gsz) {
     tab.K[i] = 0;
@@ -348,10 +415,20 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   grp.sync();
   UnitCtx u = unit_ctx(g, sd, v, D);
   typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
+  // the heaviest candidate first: its value is a strong bound for pruning the others
+  int64_t hW;
+  uint32_t hL;
+  group_heaviest(grp, tab, D, (const uint8_t *)nullptr, hW, hL, sredW, sredL);
   int ncand = 0;
+  if (hL != kNone) {
+    typename P::Score s = P::make(g, u, sd, sig, hL, hW, kTarget);
+    if (better<P>(g, u, sd, sig, s, best)) best = s;
+    ncand = r == 0;
+  }
   for (int i = r; i < tab.size(); i += gsz) {
     uint32_t key = tab.K[i];
-    if (key == 0 || key - 1 == D) continue;
+    if (key == 0 || key - 1 == D || key - 1 == hL) continue;
+    if (P::prunable(u, tab.V[i], best)) continue;
     ncand++;
     typename P::Score s = P::make(g, u, sd, sig, key - 1, tab.V[i], kTarget);
     if (better<P>(g, u, sd, sig, s, best)) best = s;
@@ -473,9 +550,12 @@ __global__ __launch_bounds__(1024) void k_lm_block(V g, SolveDev sd, const int32
   __shared__ uint32_t sk[1 << kBlockLg];
   __shared__ int64_t sv[1 << kBlockLg];
   __shared__ typename P::Score red[16];
+  __shared__ int64_t hw[16];
+  __shared__ uint32_t hl[16];
   LdsTab tab{sk, sv, kBlockLg};
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
-    uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, units[idx], comm, sig, fresh_base, red, pc);
+    uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, units[idx], comm, sig, fresh_base, red, pc,
+                            hw, hl);
     if (threadIdx.x == 0) target[idx] = t;
   }
 }
@@ -489,10 +569,12 @@ __global__ __launch_bounds__(256) void k_lm_gtab(V g, SolveDev sd, const int32_t
                                                  const int64_t *goff, const int32_t *glg,
                                                  LmCounters pc) {
   __shared__ typename P::Score red[4];
+  __shared__ int64_t hw[4];
+  __shared__ uint32_t hl[4];
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int64_t v = units[idx];
     GTab tab{gk + goff[v], gv + goff[v], glg[v]};
-    uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, v, comm, sig, fresh_base, red, pc);
+    uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, v, comm, sig, fresh_base, red, pc, hw, hl);
     if (threadIdx.x == 0) target[idx] = t;
   }
 }
@@ -678,6 +760,250 @@ __global__ void k_gtab_assign(const int32_t *units, int64_t count, const int64_t
   if (i < count) goff[units[i]] = off[i];
 }
 
+// ------------------------------------------------------------------ small levels in one block
+// For levels with few units the schedule is bounded by launch latency (a hundred colours,
+// two launches per colour and sweep).  One workgroup of 1024 threads then runs the whole
+// phase: Jones-Plassmann colouring, bucketing by colour, and every colour-batched sweep with
+// block barriers between the decisions and the moves of each batch.  The arithmetic and the
+// decisions are the same functions as in the multi-launch path.
+struct SmallCtl {
+  const int32_t *maxsw;    // [J] sweep cap per solve
+  uint8_t *frozen;         // [J] solve takes no further moves at this level
+  uint32_t *moved;         // [J] moves of the current sweep
+  int64_t *sweeps, *moves, *caps;   // [J] per-solve statistics of this level (accumulated)
+  int J;
+  const uint32_t *limit;   // [slices] rebuild threshold of the Sigma sub-tables
+  const uint32_t *nz;      // [slices] key bound after a rebuild
+  int nslices;
+  int64_t tab_total;
+  int smax;                // largest sweep cap of the participating solves
+};
+
+constexpr int kSmallThreads = 1024;
+
+
+constexpr int kSmallWaves = kSmallThreads / 64;
+
+template <class P, class V, bool kSweeps>
+__global__ __launch_bounds__(kSmallThreads) void k_small_level(
+    V g, SolveDev sd, int64_t n, const int32_t *work, int64_t nwork, uint32_t *comm,
+    SliceTable sig, int32_t *colour, uint32_t *cnt, int32_t *fa, int32_t *fb, int32_t *order,
+    int64_t *start, uint32_t *target, uint32_t *gk, int64_t *gv, int glg, SmallCtl ctl, int it,
+    int lvl, int *ncol_out) {
+  __shared__ uint32_t sk[kSmallWaves][1 << kWaveLg];
+  __shared__ int64_t sv[kSmallWaves][1 << kWaveLg];
+  __shared__ uint32_t s_nf, s_nn;
+  __shared__ int s_maxc, s_any, s_rb;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // ---- colouring: count higher-priority neighbours, then colour ready frontiers
+  if (tid == 0) {
+    s_nf = 0;
+    s_maxc = -1;
+  }
+  __syncthreads();
+  for (int64_t i = tid; i < nwork; i += kSmallThreads) {
+    const int64_t v = work[i];
+    const int j = g.usolve[v];
+    const uint64_t sm = sd.seedmix[j];
+    const int64_t off = sd.uoff[j];
+    const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+    typename V::Row row = g.row(v, sd);
+    uint32_t c = 0;
+    for (int64_t e = row.lo; e < row.hi; e++) {
+      int32_t x = g.col[e];
+      if (g.wt(row, e, x) == 0) continue;
+      if (outranks(priority(sm, it, lvl, 0, (uint32_t)(x - off)), (uint32_t)x, hv, (uint32_t)v)) c++;
+    }
+    cnt[v] = c;
+    colour[v] = -1;
+    if (c == 0) fa[atomicAdd(&s_nf, 1u)] = (int32_t)v;
+  }
+  block_sync_global();
+  int32_t *cur = fa, *nxt = fb;
+  while (s_nf > 0) {
+    const uint32_t nf = s_nf;
+    __syncthreads();
+    if (tid == 0) s_nn = 0;
+    __syncthreads();
+    for (uint32_t idx = wv; idx < nf; idx += kSmallWaves) {
+      const int64_t v = cur[idx];
+      const int j = g.usolve[v];
+      const uint64_t sm = sd.seedmix[j];
+      const int64_t off = sd.uoff[j];
+      const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+      typename V::Row row = g.row(v, sd);
+      int result = -1;
+      for (int base = 0; result < 0; base += 64) {
+        uint64_t used = 0;
+        for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+          int32_t x = g.col[e];
+          if (g.wt(row, e, x) == 0) continue;
+          if (!outranks(priority(sm, it, lvl, 0, (uint32_t)(x - off)), (uint32_t)x, hv, (uint32_t)v))
+            continue;
+          int cx = colour[x];
+          if (cx >= base && cx < base + 64) used |= 1ull << (cx - base);
+        }
+        for (int m = 32; m >= 1; m >>= 1) used |= (uint64_t)shfl_xor64((int64_t)used, m);
+        if (~used) result = base + __builtin_ctzll(~used);
+      }
+      if (lane == 0) {
+        colour[v] = result;
+        atomicMax(&s_maxc, result);
+      }
+      for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+        int32_t x = g.col[e];
+        if (g.wt(row, e, x) == 0) continue;
+        if (outranks(priority(sm, it, lvl, 0, (uint32_t)(x - off)), (uint32_t)x, hv, (uint32_t)v))
+          continue;
+        if (atomicSub(cnt + x, 1u) == 1u) nxt[atomicAdd(&s_nn, 1u)] = x;
+      }
+    }
+    block_sync_global();
+    if (tid == 0) s_nf = s_nn;
+    int32_t *t = cur;
+    cur = nxt;
+    nxt = t;
+    __syncthreads();
+  }
+  // ---- bucket the units by colour, or by (colour, degree bin) for the multi-launch sweeps
+  const int ncol = s_maxc + 1;
+  const int nkey = kSweeps ? ncol : 8 * ncol;
+  auto key_of = [&](int64_t v) -> int {
+    return kSweeps ? colour[v] : (colour[v] << 3) | (int)degree_bin(g.degree(v));
+  };
+  for (int c = tid; c <= nkey; c += kSmallThreads) start[c] = 0;
+  __syncthreads();
+  for (int64_t i = tid; i < nwork; i += kSmallThreads)
+    atomicAdd(reinterpret_cast<unsigned long long *>(start + key_of(work[i]) + 1), 1ull);
+  __syncthreads();
+  if (tid == 0) {
+    for (int c = 0; c < nkey; c++) start[c + 1] += start[c];
+    *ncol_out = ncol;
+  }
+  __syncthreads();
+  // scatter: decisions inside a batch are independent and moves commute, so the order of
+  // units inside a colour does not matter
+  for (int c = tid; c < nkey; c += kSmallThreads) cnt[c] = (uint32_t)start[c];
+  __syncthreads();
+  for (int64_t i = tid; i < nwork; i += kSmallThreads) {
+    const int32_t v = work[i];
+    order[atomicAdd(cnt + key_of(v), 1u)] = v;
+  }
+  block_sync_global();
+  if (!kSweeps) return;
+  // ---- colour-batched sweeps
+  LdsTab ltab{sk[wv], sv[wv], kWaveLg};
+  const uint32_t gmask_lg = glg;
+  for (int t = 0; t < ctl.smax; t++) {
+    for (int j = tid; j < ctl.J; j += kSmallThreads) ctl.moved[j] = 0;
+    block_sync_global();
+    const uint32_t fresh_base = (uint32_t)(n * (int64_t)(1 + t));
+    for (int c = 0; c < ncol; c++) {
+      const int64_t lo = start[c], hi = start[c + 1];
+      for (int64_t idx = lo + wv; idx < hi; idx += kSmallWaves) {
+        const int64_t v = order[idx];
+        uint32_t tg;
+        if (g.degree(v) <= kWaveMaxDeg) {
+          tg = lm_unit<P>(WaveGrp(), ltab, g, sd, v, comm, sig, fresh_base,
+                          (typename P::Score *)nullptr, LmCounters{nullptr});
+        } else {
+          GTab gt{gk + ((int64_t)wv << gmask_lg), gv + ((int64_t)wv << gmask_lg), (int)gmask_lg};
+          tg = lm_unit<P>(WaveGrp(), gt, g, sd, v, comm, sig, fresh_base,
+                          (typename P::Score *)nullptr, LmCounters{nullptr});
+        }
+        if (lane == 0) target[idx] = tg;
+      }
+      block_sync_global();
+      for (int64_t idx = lo + tid; idx < hi; idx += kSmallThreads) {
+        const uint32_t C = target[idx];
+        if (C == kNone) continue;
+        const int64_t v = order[idx];
+        const int j = g.usolve[v];
+        if (ctl.frozen[j]) continue;
+        const uint32_t D = comm[v];
+        const int m = g.plen(v);
+        for (int jj = 0; jj < m; jj++) {
+          int gs;
+          int64_t k;
+          g.pent(v, jj, gs, k);
+          tab_add(sig, gs, D, -(int32_t)k);
+          tab_add(sig, gs, C, (int32_t)k);
+        }
+        comm[v] = C;
+        atomicAdd(ctl.moved + j, 1u);
+      }
+      block_sync_global();
+    }
+    // per-solve stopping rules after the sweep
+    if (tid == 0) {
+      s_any = 0;
+      s_rb = 0;
+    }
+    __syncthreads();
+    for (int j = tid; j < ctl.J; j += kSmallThreads) {
+      if (ctl.frozen[j]) continue;
+      ctl.sweeps[j]++;
+      ctl.moves[j] += ctl.moved[j];
+      if (ctl.moved[j] == 0) {
+        ctl.frozen[j] = 1;
+      } else if (t == ctl.maxsw[j] - 1) {
+        ctl.caps[j]++;
+        ctl.frozen[j] = 1;
+      } else {
+        s_any = 1;
+      }
+    }
+    for (int s2 = tid; s2 < ctl.nslices; s2 += kSmallThreads)
+      if (sig.used[s2] > ctl.limit[s2]) s_rb = 1;
+    block_sync_global();
+    if (!s_any) break;
+    if (s_rb) {   // compact the Sigma table: same contents, fewer dead keys
+      for (int64_t i = tid; i < ctl.tab_total; i += kSmallThreads) sig.slots[i] = 0;
+      block_sync_global();
+      for (int64_t v = tid; v < n; v += kSmallThreads) {
+        const int m = g.plen(v);
+        for (int jj = 0; jj < m; jj++) {
+          int gs;
+          int64_t k;
+          g.pent(v, jj, gs, k);
+          tab_add(sig, gs, comm[v], (int32_t)k, false);
+        }
+      }
+      for (int s2 = tid; s2 < ctl.nslices; s2 += kSmallThreads) sig.used[s2] = ctl.nz[s2];
+      block_sync_global();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ work-list segments
+// Up to three unit lists handled by one launch (one per group of degree bins).
+struct Segs {
+  const int32_t *p[3];
+  int64_t pre[4];   // prefix sums of the segment lengths
+  __device__ int64_t unit(int64_t i) const {
+    int k = i < pre[1] ? 0 : (i < pre[2] ? 1 : 2);
+    return p[k][i - pre[k]];
+  }
+  __device__ int seg(int64_t i) const { return i < pre[1] ? 0 : (i < pre[2] ? 1 : 2); }
+};
+
+// keep the units whose flag is still set, segment by segment
+__global__ void k_compact_segs(Segs in, const uint8_t *flag, int32_t *o0, int32_t *o1, int32_t *o2,
+                               uint32_t *cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < in.pre[3];
+  // a wave may straddle two segments: append segment by segment
+  for (int k = 0; k < 3; k++) {
+    bool keep = false;
+    int32_t v = 0;
+    if (live && in.seg(i) == k) {
+      v = (int32_t)in.unit(i);
+      keep = flag[v] != 0;
+    }
+    wave_append(k == 0 ? o0 : (k == 1 ? o1 : o2), cnt + k, keep, v);
+  }
+}
+
 // ------------------------------------------------------------------ refinement
 // Leiden refinement inside each community (Section 3.2 citing Traag et al.): singletons
 // that are well connected to their community merge into well-connected sub-communities
@@ -722,14 +1048,11 @@ __global__ __launch_bounds__(256) void k_ref_init(V g, SolveDev sd, int64_t n, c
 template <class V>
 __global__ void k_ref_wc(V g, SolveDev sd, const int32_t *list, int64_t count, const uint32_t *comm,
                          const int64_t *ext, const uint64_t *mask, SliceTable sr, SliceTable sig,
-                         uint8_t *wcT, uint8_t *active, uint8_t *only) {
+                         uint8_t *wcT, uint8_t *active, uint32_t *changed) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const int64_t T = list ? list[i] : i;
-  if (only) {
-    if (!only[T]) return;
-    only[T] = 0;
-  }
+  if (changed) changed[T] = 0;
   const int j = g.usolve[T];
   const int64_t q = sd.q[j], pb = sd.pb[j];
   const uint32_t K = comm[T];
@@ -786,8 +1109,10 @@ __global__ void k_ref_wc(V g, SolveDev sd, const int32_t *list, int64_t count, c
 template <class P, class V, class Grp, class Tab>
 __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd, int64_t v,
                                 const uint32_t *comm, const uint32_t *R, const uint8_t *wcT,
-                                const SliceTable &sr, uint32_t *prop, int64_t *propw,
-                                uint8_t *active, typename P::Score *red) {
+                                const SliceTable &sr, uint32_t *prop, uint32_t *propr,
+                                uint32_t stamp, int64_t *propw, uint8_t *active,
+                                typename P::Score *red, int64_t *sredW = nullptr,
+                                uint32_t *sredL = nullptr) {
   const int r = grp.rank(), gsz = grp.size();
   for (int i = r; i < tab.size(); i += gsz) {
     tab.K[i] = 0;
@@ -807,11 +1132,19 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
   UnitCtx u = unit_ctx(g, sd, v, D);
   const typename P::Score zero = P::make(g, u, sd, sr, kNone, 0, kEmpty);
   typename P::Score best = zero;
+  int64_t hW;
+  uint32_t hL;
+  group_heaviest(grp, tab, kNone, wcT, hW, hL, sredW, sredL);
+  if (hL != kNone) {
+    typename P::Score s = P::make(g, u, sd, sr, hL, hW, kTarget);
+    if (P::cmp(g, u, sd, sr, s, zero) > 0) best = s;
+  }
   for (int i = r; i < tab.size(); i += gsz) {
     uint32_t key = tab.K[i];
     if (key == 0) continue;
     uint32_t T = key - 1;
-    if (!wcT[T]) continue;
+    if (T == hL || !wcT[T]) continue;
+    if (P::prunable(u, tab.V[i], best)) continue;
     typename P::Score s = P::make(g, u, sd, sr, T, tab.V[i], kTarget);
     if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
     if (better<P>(g, u, sd, sr, s, best)) best = s;
@@ -820,9 +1153,13 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
   int64_t w = best.lab == kNone ? 0 : tab.get(best.lab);
   grp.sync();
   if (r == 0) {
-    prop[v] = best.lab;
-    propw[v] = w;
-    if (best.lab == kNone) active[v] = 0;
+    if (best.lab == kNone) {
+      active[v] = 0;
+    } else {
+      prop[v] = best.lab;
+      propw[v] = w;
+      propr[v] = stamp;
+    }
   }
 }
 
@@ -830,7 +1167,8 @@ template <class P, class V>
 __global__ __launch_bounds__(256) void k_ref_prop_wave(V g, SolveDev sd, const int32_t *units,
                                                        int64_t count, const uint32_t *comm,
                                                        const uint32_t *R, const uint8_t *wcT,
-                                                       SliceTable sr, uint32_t *prop, int64_t *propw,
+                                                       SliceTable sr, uint32_t *prop, uint32_t *propr,
+                                                       uint32_t stamp, int64_t *propw,
                                                        uint8_t *active) {
   __shared__ uint32_t sk[4][1 << kWaveLg];
   __shared__ int64_t sv[4][1 << kWaveLg];
@@ -838,12 +1176,9 @@ __global__ __launch_bounds__(256) void k_ref_prop_wave(V g, SolveDev sd, const i
   const int64_t idx = (int64_t)blockIdx.x * 4 + wv;
   if (idx >= count) return;
   const int64_t v = units[idx];
-  if (!active[v]) {
-    if ((threadIdx.x & 63) == 0) prop[v] = kNone;
-    return;
-  }
+  if (!active[v]) return;
   LdsTab tab{sk[wv], sv[wv], kWaveLg};
-  ref_unit<P>(WaveGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propw, active,
+  ref_unit<P>(WaveGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propr, stamp, propw, active,
               (typename P::Score *)nullptr);
 }
 
@@ -852,18 +1187,19 @@ __global__ __launch_bounds__(1024) void k_ref_prop_block(V g, SolveDev sd, const
                                                          int64_t count, const uint32_t *comm,
                                                          const uint32_t *R, const uint8_t *wcT,
                                                          SliceTable sr, uint32_t *prop,
+                                                         uint32_t *propr, uint32_t stamp,
                                                          int64_t *propw, uint8_t *active) {
   __shared__ uint32_t sk[1 << kBlockLg];
   __shared__ int64_t sv[1 << kBlockLg];
   __shared__ typename P::Score red[16];
+  __shared__ int64_t hw[16];
+  __shared__ uint32_t hl[16];
   LdsTab tab{sk, sv, kBlockLg};
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int64_t v = units[idx];
-    if (!active[v]) {
-      if (threadIdx.x == 0) prop[v] = kNone;
-      continue;
-    }
-    ref_unit<P>(BlockGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propw, active, red);
+    if (!active[v]) continue;
+    ref_unit<P>(BlockGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propr, stamp, propw, active,
+                red, hw, hl);
   }
 }
 
@@ -871,34 +1207,44 @@ template <class P, class V>
 __global__ __launch_bounds__(256) void k_ref_prop_gtab(V g, SolveDev sd, const int32_t *units,
                                                        int64_t count, const uint32_t *comm,
                                                        const uint32_t *R, const uint8_t *wcT,
-                                                       SliceTable sr, uint32_t *prop, int64_t *propw,
+                                                       SliceTable sr, uint32_t *prop, uint32_t *propr,
+                                                       uint32_t stamp, int64_t *propw,
                                                        uint8_t *active, uint32_t *gk, int64_t *gv,
                                                        const int64_t *goff, const int32_t *glg) {
   __shared__ typename P::Score red[4];
+  __shared__ int64_t hw[4];
+  __shared__ uint32_t hl[4];
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int64_t v = units[idx];
-    if (!active[v]) {
-      if (threadIdx.x == 0) prop[v] = kNone;
-      continue;
-    }
+    if (!active[v]) continue;
     GTab tab{gk + goff[v], gv + goff[v], glg[v]};
-    ref_unit<P>(BlockGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propw, active, red);
+    ref_unit<P>(BlockGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propr, stamp, propw, active,
+                red, hw, hl);
   }
 }
 
-// A proposer merges when no proposing neighbour of its community outranks it.
+// A proposer merges when its target sub-community keeps all its members this round:
+//  (a) the target's founder does not propose (sub-communities with two or more members never
+//      propose), or
+//  (b) the proposer outranks every proposing neighbour of its community, and the target's
+//      founder proposes to a target whose own founder proposes (so the founder cannot move).
+// Proposals and eligibility carry the round's stamp instead of being cleared.
 template <class V>
-__global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, int64_t n,
+__global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, Segs segs,
                                                       const uint32_t *comm, const uint32_t *prop,
-                                                      uint8_t *elig, uint32_t *nelig, int it,
-                                                      int lvl) {
+                                                      const uint32_t *propr, uint32_t stamp,
+                                                      uint32_t *elig, int it, int lvl) {
   const int lane = threadIdx.x & 63;
-  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (v >= n) return;
-  if (prop[v] == kNone) {
-    if (lane == 0) elig[v] = 0;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= segs.pre[3]) return;
+  const int64_t v = segs.unit(idx);
+  if (propr[v] != stamp) return;
+  const uint32_t T = prop[v];
+  if (propr[T] != stamp) {
+    if (lane == 0) elig[v] = stamp;
     return;
   }
+  if (propr[prop[T]] != stamp) return;
   const int j = g.usolve[v];
   const uint64_t sm = sd.seedmix[j];
   const int64_t off = sd.uoff[j];
@@ -908,38 +1254,80 @@ __global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, int64_t 
   int beaten = 0;
   for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
     int32_t x = g.col[e];
-    if (comm[x] != D || prop[x] == kNone) continue;
+    if (comm[x] != D || propr[x] != stamp) continue;
     if (g.wt(row, e, x) == 0) continue;
     uint64_t hx = priority(sm, it, lvl, 1, (uint32_t)(x - off));
     if (outranks(hx, (uint32_t)x, hv, (uint32_t)v)) beaten = 1;
   }
   for (int m = 32; m >= 1; m >>= 1) beaten |= __shfl_xor(beaten, m, 64);
-  if (lane == 0) elig[v] = !beaten;
-  (void)nelig;
-  (void)j;
+  if (lane == 0 && !beaten) elig[v] = stamp;
 }
 
+// Merge every eligible proposer into its target; edges between co-joiners of the same target
+// become internal as well.  The first merge into T queues T for a fresh well-connectedness
+// check.
 template <class V>
-__global__ void k_ref_apply(V g, SolveDev sd, int64_t n, const uint32_t *prop, const int64_t *propw,
-                            const uint8_t *elig, uint32_t *R, int64_t *ext, uint64_t *mask,
-                            uint8_t *active, uint8_t *changed, SliceTable sr) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || !elig[v]) return;
+__global__ __launch_bounds__(256) void k_ref_apply(V g, SolveDev sd, Segs segs, const uint32_t *prop,
+                                                   const int64_t *propw, const uint32_t *elig,
+                                                   uint32_t stamp, uint32_t *R, int64_t *ext,
+                                                   uint64_t *mask, uint8_t *active,
+                                                   uint32_t *changed, int32_t *clist,
+                                                   uint32_t *ccount, uint32_t *nelig,
+                                                   SliceTable sr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= segs.pre[3]) return;
+  const int64_t v = segs.unit(idx);
+  if (elig[v] != stamp) return;
   const uint32_t T = prop[v];
-  R[v] = T;
-  active[v] = 0;
-  active[T] = 0;
-  atomicAdd(reinterpret_cast<unsigned long long *>(ext + T),
-            (unsigned long long)(ext[v] - 2 * propw[v]));
-  int m = g.plen(v);
-  for (int jj = 0; jj < m; jj++) {
+  typename V::Row row = g.row(v, sd);
+  int64_t corr = 0;
+  for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+    int32_t x = g.col[e];
+    if (elig[x] == stamp && prop[x] == T) corr += g.wt(row, e, x);
+  }
+  corr = wave_sum64(corr);
+  const int m = g.plen(v);
+  for (int jj = lane; jj < m; jj += 64) {
     int gs;
     int64_t k;
     g.pent(v, jj, gs, k);
     tab_add(sr, gs, T, (int32_t)k, false);
   }
-  atomicOr(reinterpret_cast<unsigned long long *>(mask + T), (unsigned long long)mask[v]);
-  changed[T] = 1;
+  if (lane == 0) {
+    R[v] = T;
+    active[v] = 0;
+    active[T] = 0;
+    atomicAdd(reinterpret_cast<unsigned long long *>(ext + T),
+              (unsigned long long)(ext[v] - 2 * propw[v] - corr));
+    atomicOr(reinterpret_cast<unsigned long long *>(mask + T), (unsigned long long)mask[v]);
+  }
+  (void)changed;
+  (void)clist;
+  (void)ccount;
+  (void)nelig;
+}
+
+// merges per solve and the queue of sub-communities that received members (convergent)
+template <class V>
+__global__ void k_ref_post(V g, Segs segs, const uint32_t *prop, const uint32_t *elig,
+                           uint32_t stamp, uint32_t *changed, int32_t *clist, uint32_t *ccount,
+                           uint32_t *nelig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool merged = false, first = false;
+  int j = 0;
+  uint32_t T = 0;
+  if (i < segs.pre[3]) {
+    const int64_t v = segs.unit(i);
+    if (elig[v] == stamp) {
+      merged = true;
+      j = g.usolve[v];
+      T = prop[v];
+      first = atomicExch(changed + T, 1u) == 0u;
+    }
+  }
+  wave_count(nelig, j, merged);
+  wave_append(clist, ccount, first, (int32_t)T);
 }
 
 // ------------------------------------------------------------------ aggregation helpers
