@@ -183,6 +183,17 @@ template <class V>
 __device__ __noinline__ int exact_cmp(const V &g, const UnitCtx &u, const SolveDev &sd,
                                       const SliceTable &tab, uint32_t la, int ka, int64_t Wa,
                                       uint32_t lb, int kb, int64_t Wb) {
+  // equal per-slice terms (the usual case of two estimates that cannot be told apart: the
+  // two targets hold the same Sigma in every slice of the unit) need no big integers
+  bool same = true;
+  for (int jj = 0; jj < u.m && same; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(u.v, jj, gs, k);
+    same = target_y(tab, gs, k, la, ka) == target_y(tab, gs, k, lb, kb);
+  }
+  if (same) return Wa > Wb ? 1 : (Wa < Wb ? -1 : 0);
+  atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
   ExactAcc acc;
   acc.init();
   for (int jj = 0; jj < u.m; jj++) {
@@ -241,7 +252,6 @@ struct PolicyK {
     if ((a.kind & 4) && (b.kind & 4)) return a.W < b.W ? -1 : (a.W > b.W ? 1 : 0);   // both q*W
     double d = a.ap - b.ap;
     if (fabs(d) > 2.0 * (a.er + b.er)) return d > 0 ? 1 : -1;
-    atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
     return exact_cmp(g, u, sd, tab, a.lab, a.kind & 3, a.W, b.lab, b.kind & 3, b.W);
   }
   __device__ static bool prunable(const UnitCtx &u, int64_t W, const Score &best) {
