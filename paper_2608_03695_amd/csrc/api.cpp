@@ -335,6 +335,25 @@ mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int6
 
 }  // namespace
 
+namespace mslm {
+// shared with the request loop in server.cpp
+mslm_status api_fail(mslm_status s, const std::string &m) { return fail(s, m); }
+mslm_status api_check_desc(const mslm_graph_desc *d) {
+  mslm_status s = check_desc_shape(d);
+  return s != MSLM_OK ? s : check_desc_edges(d);
+}
+mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, SolveSpec &sp) {
+  return make_spec(p, on, od, sp);
+}
+void api_finish(const GraphDev &g, const SolveSpec &sp, SolveOut &o, mslm_result *res) {
+  std::string a, b;
+  double qd = 0;
+  q_exact(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
+  o.res.q = qd;
+  if (res) *res = o.res;
+}
+}  // namespace mslm
+
 // ------------------------------------------------------------------ exported functions
 extern "C" {
 
@@ -354,6 +373,8 @@ mslm_status mslm_create(const mslm_graph_desc *desc, void *hip_stream, mslm_grap
     h->g.omega_num = desc->omega_num;
     h->g.omega_den = desc->omega_den;
     build_graph(h->g, *desc, h->st, h->ws);
+    MSLM_HIP(hipStreamSynchronize(h->st));
+    workspace_release_build(h->ws);
   } catch (const Error &e) {
     return fail(e.status, e.what());
   } catch (const std::exception &e) {
@@ -413,11 +434,7 @@ size_t mslm_footprint_bytes(const mslm_graph_desc *d) {
 
 static mslm_status finish_result(const GraphDev &g, const SolveSpec &sp, SolveOut &o,
                                  mslm_result *res) {
-  std::string a, b;
-  double qd = 0;
-  q_exact(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
-  o.res.q = qd;
-  if (res) *res = o.res;
+  api_finish(g, sp, o, res);
   return MSLM_OK;
 }
 

@@ -79,6 +79,7 @@ struct Workspace {
   Buf ckeys, cvals, ckeys2, cvals2, head, ismin, segx, minof, crank;
   Buf qW, qSS, qI, ranges_lo, ranges_hi, ranges_off;
   Buf sm_maxsw, sm_stat, sm_nz, sm_start;
+  Buf b_src, b_dst, b_w, b_off, b_twom;   // graph build inputs and per-slice sums
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };
@@ -88,6 +89,13 @@ void workspace_free(Workspace *ws) {
   if (!ws) return;
   for (auto e : ws->evpool) (void)hipEventDestroy(e);
   delete ws;
+}
+
+void workspace_release_build(Workspace *ws) {
+  if (!ws) return;
+  for (Buf *b : {&ws->b_src, &ws->b_dst, &ws->b_w, &ws->akeys, &ws->akeys2, &ws->avals,
+                 &ws->avals2, &ws->temp})
+    b->release();
 }
 
 static void *temp_get(void *ctx, size_t bytes) {
@@ -187,20 +195,19 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   g.N = N;
   g.T = T;
   g.n = n;
-  // edge lists on the device
-  Buf dsrc, ddst, dw, doff;
+  // edge lists on the device (workspace buffers: repeated builds allocate nothing new)
   const int32_t *src = d.src, *dst = d.dst, *w = d.weight;
   if (!on_dev) {
-    src = dsrc.get<int32_t>(E);
-    dst = ddst.get<int32_t>(E);
+    src = ws->b_src.get<int32_t>(E);
+    dst = ws->b_dst.get<int32_t>(E);
     h2d(const_cast<int32_t *>(src), d.src, E, st);
     h2d(const_cast<int32_t *>(dst), d.dst, E, st);
     if (d.weight) {
-      w = dw.get<int32_t>(E);
+      w = ws->b_w.get<int32_t>(E);
       h2d(const_cast<int32_t *>(w), d.weight, E, st);
     }
   }
-  int64_t *off = doff.get<int64_t>(T + 1);
+  int64_t *off = ws->b_off.get<int64_t>(T + 1);
   h2d(off, d.slice_offsets, T + 1, st);
   if (on_dev && E > 0) {   // host validation covers host inputs; device inputs are checked here
     int *bad = ws->flag.get<int>(1);
@@ -211,16 +218,15 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
     MSLM_HIP(hipStreamSynchronize(st));
     if (hbad) throw Error(MSLM_EINVAL, "edge list has an id out of range, a self-loop or a weight < 1");
   }
-  Buf keys, vals, keys2, vals2, nun;
-  uint64_t *k1 = keys.get<uint64_t>(mraw);
-  int64_t *v1 = vals.get<int64_t>(mraw);
+  uint64_t *k1 = ws->akeys.get<uint64_t>(mraw);
+  int64_t *v1 = ws->avals.get<int64_t>(mraw);
   if (E > 0) k_build_intra<<<nblk(E), kBS, 0, st>>>(src, dst, w, off, T, N, E, k1, v1);
   if (ninter > 0) k_build_inter<<<nblk(ninter), kBS, 0, st>>>(N, T, k1 + 2 * E, v1 + 2 * E);
-  uint64_t *k2 = keys2.get<uint64_t>(mraw);
-  int64_t *v2 = vals2.get<int64_t>(mraw);
+  uint64_t *k2 = ws->akeys2.get<uint64_t>(mraw);
+  int64_t *v2 = ws->avals2.get<int64_t>(mraw);
   int endbit = 32 + bits_for((uint64_t)n);
   MSLM_PRIM(sort_pairs_u64_i64(k1, k2, v1, v2, mraw, endbit, st, temp_alloc(ws)));
-  int64_t *dn = nun.get<int64_t>(1);
+  int64_t *dn = ws->nuniq.get<int64_t>(1);
   MSLM_PRIM(reduce_by_key_u64_i64(k2, k1, v2, v1, dn, mraw, st, temp_alloc(ws)));
   int64_t m = 0;
   d2h(&m, dn, 1, st);
@@ -236,8 +242,7 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   int64_t *rp = g.rp.get<int64_t>(n + 1);
   MSLM_PRIM(exclusive_sum_i64(cnt, rp, n + 1, st, temp_alloc(ws)));
   int32_t *kd = g.k.get<int32_t>(n);
-  Buf tw;
-  int64_t *twom = tw.get<int64_t>(2 * T);
+  int64_t *twom = ws->b_twom.get<int64_t>(2 * T);
   MSLM_HIP(hipMemsetAsync(twom, 0, sizeof(int64_t) * 2 * T, st));
   k_build_degree<<<nblk(n), kBS, 0, st>>>(rp, col, wv, n, N, kd, twom, twom + T);
   k_max_degree<<<nblk(n), kBS, 0, st>>>(rp, n, flags + 1);
@@ -253,7 +258,6 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
       throw Error(MSLM_EOVERFLOW, "a slice's total degree 2m_s reaches 2^31");
   g.unit = hf[0] == 0;
   g.maxdeg = hf[1];
-  if (g.unit) g.w.release();
 }
 
 namespace {

@@ -86,6 +86,8 @@ struct Workspace;   // opaque, cached per graph or per batch
 
 Workspace *workspace_new();
 void workspace_free(Workspace *ws);
+// Return the graph-build scratch (edge lists, sort keys) of a workspace to the device.
+void workspace_release_build(Workspace *ws);
 
 // Build the level-0 CSR of a graph from (host or device) edge lists.
 void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspace *ws);

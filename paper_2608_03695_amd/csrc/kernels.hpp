@@ -1467,6 +1467,24 @@ __global__ void k_count_heads(const uint32_t *sv, const uint8_t *head, const int
   bool h = i < n && head[i];
   wave_count(cnt, h ? usolve[sv[i]] : 0, h);
 }
+__global__ void k_solve_label_keys(const uint32_t *lab, const int32_t *usolve, int64_t n,
+                                   uint64_t *keys, int32_t *vals) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) {
+    keys[v] = ((uint64_t)(uint32_t)usolve[v] << 32) | lab[v];
+    vals[v] = (int32_t)v;
+  }
+}
+__global__ void k_count_key_heads(const uint64_t *keys, int64_t n, uint32_t *cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool h = i < n && (i == 0 || keys[i] != keys[i - 1]);
+  wave_count(cnt, h ? (int)(keys[i] >> 32) : 0, h);
+}
+__global__ void k_offset_labels(const int32_t *lab, const int32_t *usolve, const int64_t *uoff,
+                                int64_t n, uint32_t *out) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) out[v] = (uint32_t)(uoff[usolve[v]] + lab[v]);
+}
 __global__ void k_count_roots_R(const uint32_t *R, const int32_t *usolve, int64_t n, uint32_t *cnt) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool h = u < n && R[u] == (uint32_t)u;

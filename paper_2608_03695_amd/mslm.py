@@ -217,6 +217,48 @@ def footprint_bytes(tg, omega=Fraction(1)) -> int:
     return int(load().mslm_footprint_bytes(C.byref(d)))
 
 
+class Server:
+    """Continuous-batching request loop (mslm_server_*): submit() copies the graph and
+    returns a ticket; wait() returns (membership, result dict, latency seconds)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=4):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.mslm_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self._h = h
+        self._shape = {}
+
+    def submit(self, tg, gamma=Fraction(1), omega=Fraction(1), max_levels=32, max_iterations=2,
+               seed=0) -> int:
+        d, keep = _desc(tg, omega)
+        p = params(gamma, None, max_levels, max_iterations, 0, seed, 0)
+        t = C.c_uint64()
+        _check(load().mslm_server_submit(self._h, C.byref(d), C.byref(p), C.byref(t)))
+        self._shape[t.value] = (tg.n_nodes, tg.n_slices)
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        n_nodes, n_slices = self._shape.get(ticket, (0, 1))   # unknown: the library says so
+        memb = np.empty(n_nodes * n_slices, dtype=np.int32)
+        res = Result()
+        lat = C.c_double()
+        _check(load().mslm_server_wait(self._h, C.c_uint64(ticket), int(timeout_ms), _ptr(memb),
+                                       C.byref(res), C.byref(lat)))
+        self._shape.pop(ticket, None)
+        return memb, res.as_dict(n_slices), lat.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mslm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def batch_leiden(graphs: Sequence[Graph], solves, stream=None):
     """solves: list of (graph index, gamma, omega, max_levels, max_iterations, seed).
     Returns a list of (membership, result dict), bit-identical to plain calls."""

@@ -1,0 +1,115 @@
+"""GPU: batched solves and the serving loop give the same results as plain calls.
+
+Batching runs many (graph, gamma, omega) solves as one disjoint union; serving groups the
+requests waiting at each moment and runs groups concurrently on several streams.  Both must
+reproduce every plain mslm_leiden result exactly (memberships, Q components, statistics).
+"""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+from paper_2608_03695_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+STAT_KEYS = ["sweeps", "moves", "sweep_cap_hits", "refine_rounds", "merges", "splits",
+             "levels_run", "iterations_run", "n_communities"]
+
+
+def _mslm():
+    from paper_2608_03695_amd import mslm
+    return mslm
+
+
+def _graphs():
+    return [
+        gen.planted_partition(300, 3, 5, 0.1, 0.01, 0.1, seed=31, name="pp300"),
+        gen.dcsbm(1500, 5, 10, 12, 0.3, 2.5, 0.05, weights_max=8, seed=32, name="dc1500w"),
+        gen.erdos_renyi(200, 2, 0.03, seed=33, name="er200"),
+        gen.dcsbm(4000, 7, 8, 20, 0.25, 2.5, 0.05, seed=34, name="dc4000"),
+        gen.from_edge_lists(3, [[], []], name="empty"),
+    ]
+
+
+def _same(a, b, case):
+    ma, ra = a
+    mb, rb = b
+    assert np.array_equal(ma, mb), case
+    assert np.array_equal(ra["q_components"], rb["q_components"]), case
+    for k in STAT_KEYS:
+        assert ra[k] == rb[k], f"{case}: {k} {ra[k]} != {rb[k]}"
+
+
+def test_batch_equals_plain_calls():
+    mslm = _mslm()
+    tgs = _graphs()
+    handles = [mslm.Graph(tg, 1) for tg in tgs]
+    solves = []
+    for gi in range(len(tgs)):
+        for gamma in (F(1, 2), F(1), F(2)):
+            for omega in (F(1, 10), F(1), F(10)):
+                solves.append((gi, gamma, omega, 32, 2, 0))
+    solves.append((1, F(1), F(1), 1, 1, 7))      # other level/iteration caps and seed
+    solves.append((3, F(1), F(1, 2), 3, 0, 99))
+    got = mslm.batch_leiden(handles, solves)
+    for (gi, gamma, omega, lv, it, seed), out in zip(solves, got):
+        plain = handles[gi].leiden(gamma, omega, max_levels=lv, max_iterations=it, seed=seed)
+        _same(out, plain, f"{tgs[gi].name} gamma={gamma} omega={omega} levels={lv} it={it}")
+    for h in handles:
+        h.close()
+
+
+def test_batch_matches_oracle_directly():
+    import oracle
+    mslm = _mslm()
+    tgs = _graphs()[:3]
+    handles = [mslm.Graph(tg, 1) for tg in tgs]
+    solves = [(i, F(1), F(1, 10), 32, 2, 0) for i in range(len(tgs))]
+    got = mslm.batch_leiden(handles, solves)
+    for tg, (m, r) in zip(tgs, got):
+        om, oc, _ = oracle.OracleGraph(tg, F(1, 10)).leiden(1, max_levels=32, max_iterations=2,
+                                                            seed=0)
+        assert np.array_equal(m, om), tg.name
+        assert np.array_equal(r["q_components"], oc), tg.name
+
+
+def test_server_results_equal_alone_and_in_mix():
+    mslm = _mslm()
+    tgs = _graphs()
+    reqs = []
+    for i in range(24):
+        tg = tgs[i % len(tgs)]
+        gamma = (F(1, 2), F(1), F(2))[i % 3]
+        omega = (F(1, 10), F(1), F(10))[(i // 3) % 3]
+        reqs.append((tg, gamma, omega))
+    srv = mslm.Server(8 << 30, max_slots=3)
+    tickets = [srv.submit(tg, gamma, omega) for tg, gamma, omega in reqs]
+    outs = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (tg, gamma, omega), (m, r, lat) in zip(reqs, outs):
+        assert lat > 0
+        g = mslm.Graph(tg, omega)
+        plain = g.leiden(gamma)
+        g.close()
+        _same((m, r), plain, f"{tg.name} gamma={gamma} omega={omega}")
+
+
+def test_server_admission_and_errors():
+    mslm = _mslm()
+    tg = gen.planted_partition(300, 3, 5, 0.1, 0.01, 0.1, seed=31)
+    need = mslm.footprint_bytes(tg)
+    # a request larger than the whole budget is refused at submit
+    small = mslm.Server(need // 2, max_slots=2)
+    with pytest.raises(mslm.MslmError):
+        small.submit(tg)
+    small.close()
+    # a budget for exactly one request at a time still serves everything, one by one
+    one = mslm.Server(need, max_slots=2)
+    ts = [one.submit(tg, F(1), F(1)) for _ in range(3)]
+    outs = [one.wait(t) for t in ts]
+    for m, r, _ in outs[1:]:
+        assert np.array_equal(m, outs[0][0])
+    with pytest.raises(mslm.MslmError):
+        one.wait(12345)          # unknown ticket
+    one.close()
