@@ -33,14 +33,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, workers):
     from paper_2608_03695_amd import gen
     if name == "cfg1":
         return gen.config1(), gen.CONFIG_SOLVE[1]
     if name == "cfg2":
-        return gen.config2(), gen.CONFIG_SOLVE[2]
+        return gen.config2(workers), gen.CONFIG_SOLVE[2]
     if name == "cfg3":
-        return gen.config3(), gen.CONFIG_SOLVE[3]
+        return gen.config3(workers), gen.CONFIG_SOLVE[3]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -72,19 +72,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true",
                     help="skip the extra counting solve (keeps profiler traces to the timed steps)")
+    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes drawing the synthetic snapshots (1 under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               f"multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
 
+    # inputs are drawn before anything touches the GPU (the generator may use child processes)
+    log(f"generating {args.workload}")
+    tg, spec = workload(args.workload, args.gen_workers)
     import torch
     from paper_2608_03695_amd import mslm
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
-    log(f"generating {args.workload}")
-    tg, spec = workload(args.workload)
     log(f"N={tg.n_nodes} T={tg.n_slices} E={tg.n_edges}; uploading")
     stream = torch.cuda.current_stream()
     g = mslm.Graph(tg, spec.omega, stream=stream)

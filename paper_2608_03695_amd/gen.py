@@ -162,7 +162,37 @@ def _sample_in_block(theta, labels, comm_of_u, rng, k):
     return order[idx]
 
 
-def dcsbm(n, t, mean_degree, k, mu, alpha, churn, weights_max=1, seed=0, name="dcsbm"):
+def _dcsbm_slice(s, seed, cdf, theta, labels, k, m, mu, weights_max):
+    """Edges of snapshot s, drawn from the snapshot's own generator (seed, s + 1)."""
+    n = cdf.size
+    rng = np.random.default_rng([seed, s + 1])
+    u = np.searchsorted(cdf, rng.random(m), side="right").clip(0, n - 1)
+    inside = rng.random(m) >= mu
+    x = np.empty(m, dtype=np.int64)
+    x[inside] = _sample_in_block(theta, labels, labels[u[inside]], rng, k)
+    out_idx = np.nonzero(~inside)[0]
+    xo = np.searchsorted(cdf, rng.random(out_idx.size), side="right").clip(0, n - 1)
+    bad = labels[xo] == labels[u[out_idx]]
+    tries = 0
+    while bad.any() and tries < 1000:
+        xo[bad] = np.searchsorted(cdf, rng.random(int(bad.sum())), side="right").clip(0, n - 1)
+        bad = labels[xo] == labels[u[out_idx]]
+        tries += 1
+    x[out_idx] = xo
+    uu, xx = _dedup_pairs(u, x, n)
+    w = rng.integers(1, weights_max + 1, size=uu.size) if weights_max > 1 else None
+    return uu.astype(np.int32), xx.astype(np.int32), None if w is None else w.astype(np.int32)
+
+
+def _pool(workers):
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    # fresh interpreters: the parent may already hold a GPU context
+    return cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+
+
+def dcsbm(n, t, mean_degree, k, mu, alpha, churn, weights_max=1, seed=0, name="dcsbm",
+          workers=1):
     """Degree-corrected SBM snapshots with power-law propensities and community churn.
 
     Propensity theta_i is fixed across snapshots.  Per snapshot, round(n*mean/2) endpoint
@@ -170,7 +200,9 @@ def dcsbm(n, t, mean_degree, k, mu, alpha, churn, weights_max=1, seed=0, name="d
     else x ~ theta outside it (rejection).  Self-pairs and repeated pairs are dropped.
     Between snapshots floor(churn*n) nodes move to another community chosen with
     probability proportional to its size.  Weights are uniform integers in
-    1..weights_max (``None`` when weights_max == 1).
+    1..weights_max (``None`` when weights_max == 1).  The propensities and the community
+    chain come from generator ``seed``; snapshot s draws its edges from generator
+    (seed, s + 1), so snapshots can be drawn in ``workers`` processes with identical output.
     """
     rng = np.random.default_rng(seed)
     theta = _powerlaw_propensity(n, alpha, mean_degree, rng)
@@ -179,7 +211,7 @@ def dcsbm(n, t, mean_degree, k, mu, alpha, churn, weights_max=1, seed=0, name="d
     cdf = np.cumsum(theta)
     cdf /= cdf[-1]
     m = int(round(n * mean_degree / 2))
-    per_slice, planted = [], []
+    planted = []
     for s in range(t):
         if s > 0:
             labels = labels.copy()
@@ -193,24 +225,15 @@ def dcsbm(n, t, mean_degree, k, mu, alpha, churn, weights_max=1, seed=0, name="d
                                              side="right").clip(0, k - 1)
                 clash = new == labels[movers]
             labels[movers] = new
-        planted.append(labels.astype(np.int32))
-        u = np.searchsorted(cdf, rng.random(m), side="right").clip(0, n - 1)
-        inside = rng.random(m) >= mu
-        x = np.empty(m, dtype=np.int64)
-        x[inside] = _sample_in_block(theta, labels, labels[u[inside]], rng, k)
-        out_idx = np.nonzero(~inside)[0]
-        xo = np.searchsorted(cdf, rng.random(out_idx.size), side="right").clip(0, n - 1)
-        bad = labels[xo] == labels[u[out_idx]]
-        tries = 0
-        while bad.any() and tries < 1000:
-            xo[bad] = np.searchsorted(cdf, rng.random(int(bad.sum())), side="right").clip(0, n - 1)
-            bad = labels[xo] == labels[u[out_idx]]
-            tries += 1
-        x[out_idx] = xo
-        uu, xx = _dedup_pairs(u, x, n)
-        w = rng.integers(1, weights_max + 1, size=uu.size) if weights_max > 1 else None
-        per_slice.append((uu, xx, w))
-    return _assemble(n, t, per_slice, np.stack(planted), name, weighted=weights_max > 1)
+        planted.append(labels)
+    args = [(s, seed, cdf, theta, planted[s], k, m, mu, weights_max) for s in range(t)]
+    if workers > 1 and t > 1:
+        with _pool(min(workers, t)) as ex:
+            per_slice = list(ex.map(_dcsbm_slice, *zip(*args)))
+    else:
+        per_slice = [_dcsbm_slice(*a) for a in args]
+    planted = np.stack([p.astype(np.int32) for p in planted])
+    return _assemble(n, t, per_slice, planted, name, weighted=weights_max > 1)
 
 
 # --------------------------------------------------------------------------- small random graphs
@@ -250,16 +273,16 @@ def config1():
     return planted_partition(1000, 4, 10, 0.05, 0.002, 0.10, seed=0, name="cfg1_planted_T4_N1k")
 
 
-def config2():
+def config2(workers=1):
     """DC-SBM: T=16 x N=100k, exponent 2.5, mean degree 16, 100 communities, mu=.3, w in 1..8."""
     return dcsbm(100_000, 16, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=2,
-                 name="cfg2_dcsbm_T16_N100k")
+                 name="cfg2_dcsbm_T16_N100k", workers=workers)
 
 
-def config3():
+def config3(workers=1):
     """DC-SBM: T=64 x N=1M, exponent 2.1, mean degree 10, 1000 communities, mu=.4, unit."""
     return dcsbm(1_000_000, 64, 10, 1000, 0.4, 2.1, 0.02, weights_max=1, seed=3,
-                 name="cfg3_dcsbm_T64_N1M")
+                 name="cfg3_dcsbm_T64_N1M", workers=workers)
 
 
 CONFIG_SOLVE = {
@@ -318,7 +341,16 @@ def serve_trace(n_requests=1000, rate_per_s=100.0, n_graphs=512, large_frac=0.05
     return reqs
 
 
-def large_serve_graph(i):
+def large_serve_graph(i, workers=1):
     """One of the eight config-2-sized graphs of the served mix (seeds 9000..9007)."""
     return dcsbm(100_000, 16, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=9000 + i,
-                 name=f"cfg5_large{i}")
+                 name=f"cfg5_large{i}", workers=workers)
+
+
+def batch_graphs(indices, scale=1.0, workers=1):
+    """Several graphs of the batched workload, drawn in ``workers`` processes."""
+    indices = list(indices)
+    if workers > 1 and len(indices) > 1:
+        with _pool(workers) as ex:
+            return list(ex.map(batch_graph, indices, [scale] * len(indices)))
+    return [batch_graph(g, scale) for g in indices]
