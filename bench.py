@@ -46,21 +46,35 @@ def workload(name, workers):
 
 def cpu_baseline(args):
     """The oracle, as it stands, on a bounded sample of the same workload family: the
-    config-2 generator restricted to its first 4 snapshots (same N, degree law, churn)."""
+    workload's generator restricted to its first snapshots (same N, degree law, churn)."""
     import oracle
     from paper_2608_03695_amd import gen
-    tg = gen.dcsbm(100_000, 4, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=2,
-                   name="cfg2_first4_slices")
-    og = oracle.OracleGraph(tg, 1)
+    if args.workload == "cfg3":
+        tg = gen.dcsbm(1_000_000, 2, 10, 1000, 0.4, 2.1, 0.02, weights_max=1, seed=3,
+                       name="cfg3_first2_slices")
+        omega, gamma, what = Fraction(1, 2), 1, "N=1M x T=2 snapshots of the config-3 generator"
+    else:
+        tg = gen.dcsbm(100_000, 4, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=2,
+                       name="cfg2_first4_slices")
+        omega, gamma, what = 1, 1, "N=100k x T=4 snapshots of the config-2 generator"
+    og = oracle.OracleGraph(tg, omega)
     rp, col, w, raw, twom = og.csr()
     m_supra = int(rp[-1]) // 2
     t0 = time.perf_counter()
-    og.leiden(1, max_levels=32, max_iterations=2, seed=0)
+    og.leiden(gamma, max_levels=32, max_iterations=2, seed=0)
     dt = time.perf_counter() - t0
     return {"value": m_supra / dt, "unit": "supra-edges/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{tg.name}: N=100k x T=4 snapshots of the config-2 generator, "
-                      f"{m_supra} supra-edges, one full solve (2 iterations) in {dt:.1f} s"}
+            "sample": f"{tg.name}: {what}, {m_supra} supra-edges, one full solve "
+                      f"(2 iterations) in {dt:.1f} s"}
+
+
+def roofline(nbytes, ms, launches, kernel):
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+            "bytes_per_step": nbytes, "kernel_ms_per_step": ms, "launches_per_step": launches,
+            "avg_launch_us": ms * 1e3 / max(launches, 1)}
 
 
 def main():
@@ -104,22 +118,24 @@ def main():
     for i in range(args.steps):
         _, r = g.leiden(profile=True, **kw)
         results.append(r)
+        log(f"step {i} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log("timed steps done")
     ms_step = (t1 - t0) * 1000.0 / args.steps
     # the schedule is deterministic: one counting run gives the exact work of every step
     if args.no_count:
-        rc = {"lm_units": 0, "lm_entries": 0, "lm_candidates": 0}
+        rc = {k: 0 for k in ("lm_units", "lm_entries", "lm_candidates", "lm0_units",
+                             "lm0_entries", "lm0_candidates")}
     else:
         _, rc = g.leiden(count=True, **kw)
     weighted = tg.weight is not None
-    per_step_bytes = (rc["lm_units"] * BYTES_UNIT
-                      + rc["lm_entries"] * (BYTES_ENTRY + (BYTES_WEIGHT if weighted else 0))
-                      + rc["lm_candidates"] * BYTES_CAND)
-    lm_ms = sum(r["lm_kernel_ms"] for r in results) / len(results)
-    launches = results[0]["lm_launches"]
-    achieved = per_step_bytes / (lm_ms * 1e-3) / 1e9 if lm_ms > 0 else 0.0
+
+    def nbytes(pre):
+        return (rc[pre + "_units"] * BYTES_UNIT
+                + rc[pre + "_entries"] * (BYTES_ENTRY + (BYTES_WEIGHT if weighted else 0))
+                + rc[pre + "_candidates"] * BYTES_CAND)
+    mean = lambda key: sum(r[key] for r in results) / len(results)  # noqa: E731
     q = mslm.q_exact(results[-1]["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
     out = {
         "metric": METRIC,
@@ -133,12 +149,12 @@ def main():
                    "supra_nodes": info["n_supra"], "supra_edges": m_supra,
                    "gamma": str(spec.gamma), "omega": str(spec.omega),
                    "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_lm_wave/k_lm_block/k_lm_gtab (local-moving decisions)",
-                     "bytes_per_step": per_step_bytes, "kernel_ms_per_step": lm_ms,
-                     "launches_per_step": launches,
-                     "avg_launch_us": lm_ms * 1e3 / max(launches, 1)},
+        # the HBM-bound loop: level-0 local-moving decisions (every sweep of every iteration)
+        "roofline": roofline(nbytes("lm0"), mean("lm0_kernel_ms"), results[0]["lm0_launches"],
+                             "k_lm_group/k_lm_wave/k_lm_block/k_lm_gtab at level 0"),
+        "roofline_all_levels": roofline(nbytes("lm"), mean("lm_kernel_ms"),
+                                        results[0]["lm_launches"],
+                                        "local-moving decisions at every level"),
         "phases_ms": {k: results[-1][k] for k in ("ms_colour", "ms_local_move", "ms_refine",
                                                   "ms_aggregate", "ms_finish")},
         "solve": {"Q": float(q), "n_communities": results[-1]["n_communities"],

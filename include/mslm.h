@@ -96,6 +96,9 @@ typedef struct {
   int64_t lm_units, lm_entries, lm_candidates;   /* work of those kernels: units decided,
                                      adjacency entries scanned, candidate communities (COUNT) */
   int64_t q_components[3 * 64 + 1];
+  double lm0_kernel_ms;           /* the level-0 share of lm_kernel_ms (MSLM_PROFILE)         */
+  int64_t lm0_launches;           /* level-0 decision launches (MSLM_PROFILE)                 */
+  int64_t lm0_units, lm0_entries, lm0_candidates;   /* level-0 share of the work (COUNT)   */
 } mslm_result;
 
 /* Build the device supra-CSR (Eq. 3) of a temporal graph: both directions of every intra

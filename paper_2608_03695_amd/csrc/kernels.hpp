@@ -6,6 +6,7 @@
 // priority seed, local id offset) and its slices are global slice ids, so nothing here
 // ever compares quantities of two different solves.
 #pragma once
+#include <type_traits>
 #include <math.h>
 
 #include "device.hpp"
@@ -185,6 +186,7 @@ __device__ __noinline__ int exact_cmp(const V &g, const UnitCtx &u, const SolveD
                                       uint32_t lb, int kb, int64_t Wb) {
   // equal per-slice terms (the usual case of two estimates that cannot be told apart: the
   // two targets hold the same Sigma in every slice of the unit) need no big integers
+  atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks) + 1, 1ull);
   bool same = true;
   for (int jj = 0; jj < u.m && same; jj++) {
     int gs;
@@ -237,12 +239,16 @@ struct PolicyK {
         acc += t;
         mag += fabs(t);
       }
-      double qw = (double)u.q * (double)W;
-      s.ap = qw - (double)u.pb * acc;
-      s.er = (double)(u.m + 8) * 0x1p-50 * (fabs(qw) + (double)u.pb * mag);
-      if (mag == 0.0 || u.pb == 0) s.kind |= 4;
+      finish(u, W, acc, mag, s);
     }
     return s;
+  }
+  // estimate and error bound from the summed null terms (any summation order)
+  __device__ static void finish(const UnitCtx &u, int64_t W, double acc, double mag, Score &s) {
+    double qw = (double)u.q * (double)W;
+    s.ap = qw - (double)u.pb * acc;
+    s.er = (double)(u.m + 8) * 0x1p-50 * (fabs(qw) + (double)u.pb * mag);
+    if (mag == 0.0 || u.pb == 0) s.kind |= 4;
   }
   template <class V>
   __device__ static int cmp(const V &g, const UnitCtx &u, const SolveDev &sd, const SliceTable &tab,
@@ -393,6 +399,89 @@ __device__ inline void group_heaviest(Grp grp, const Tab &tab, uint32_t skip, co
   }
 }
 
+// ------------------------------------------------------------------ cooperative evaluation
+// Units spanning many slices: the lanes of an aligned subgroup of mp = 2^ceil(log2 m) lanes
+// hold one profile slice each (slice, degree, S and that slice's Sigma sub-table, loaded
+// once per unit), so one candidate costs one independent lookup per lane and a butterfly
+// sum instead of m dependent lookups in one lane.
+constexpr int kCoopMinM = 4;
+__host__ __device__ inline int coop_width(int m) {
+  int mp = 4;
+  while (mp < m) mp <<= 1;
+  return mp;
+}
+
+struct CoopLane {
+  int mp;          // subgroup width
+  int j;           // this lane's slice index within the profile (valid when j < m)
+  bool valid;
+  int64_t k;       // unit degree in that slice
+  double S;        // slice denominator
+  const uint64_t *sub;
+  uint32_t mask;
+  int shift;
+};
+
+template <class V>
+__device__ inline CoopLane coop_lane(const V &g, const UnitCtx &u, const SolveDev &sd,
+                                     const SliceTable &tab, int rank) {
+  CoopLane c;
+  c.mp = coop_width(u.m);
+  c.j = rank & (c.mp - 1);
+  c.valid = c.j < u.m;
+  c.k = 0;
+  c.S = 1.0;
+  c.sub = tab.slots;
+  c.mask = 0;
+  c.shift = 32;
+  if (c.valid) {
+    int gs;
+    g.pent(u.v, c.j, gs, c.k);
+    c.S = (double)sd.S[gs];
+    c.shift = tab.shift[gs];
+    c.mask = 0xffffffffu >> c.shift;
+    c.sub = tab.slots + tab.base[gs];
+  }
+  return c;
+}
+
+// Score of one target, identical on every lane of the subgroup.
+__device__ inline ScoreK coop_make(const UnitCtx &u, const CoopLane &c, uint32_t lab, int64_t W,
+                                   int kind) {
+  ScoreK s;
+  s.lab = kind == kEmpty ? kNone : lab;
+  s.kind = kind;
+  s.W = W;
+  s.ex = 0;
+  double t = 0.0;
+  if (c.valid && kind != kEmpty) {
+    const uint32_t key = lab + 1;
+    uint32_t h = fib_hash(lab, c.shift);
+    int64_t y = 0;
+    for (;;) {
+      const uint64_t e = c.sub[h];
+      const uint32_t kk = (uint32_t)e;
+      if (kk == key) {
+        y = (int32_t)(e >> 32);
+        break;
+      }
+      if (kk == 0) break;
+      h = (h + 1) & c.mask;
+    }
+    if (kind == kStay) y -= c.k;
+    t = (double)(c.k * y) / c.S;
+  }
+  double acc = t, mag = fabs(t);
+  for (int o = 1; o < c.mp; o <<= 1) {
+    acc += __shfl_xor(acc, o, 64);
+    mag += __shfl_xor(mag, o, 64);
+  }
+  s.ap = 0;
+  s.er = 0;
+  PolicyK::finish(u, W, acc, mag, s);
+  return s;
+}
+
 // ------------------------------------------------------------------ local moving
 // One unit: accumulate neighbour-community weights in the table, evaluate every candidate
 // community (strictly better gain wins, ties to the lower label, the empty community has
@@ -402,6 +491,49 @@ __device__ inline void group_heaviest(Grp grp, const Tab &tab, uint32_t skip, co
 struct LmCounters {
   unsigned long long *c;
 };
+
+template <class P, class Grp, class Tab, class V>
+__device__ inline uint32_t lm_unit_coop(Grp grp, Tab tab, const V &g, const SolveDev &sd,
+                                        const UnitCtx &u, const SliceTable &sig,
+                                        uint32_t fresh_base, typename P::Score *red,
+                                        LmCounters pc, typename P::Score best, int64_t hW,
+                                        uint32_t hL) {
+  const int r = grp.rank(), gsz = grp.size();
+  const CoopLane c = coop_lane(g, u, sd, sig, r);
+  const int sub = r / c.mp, nsub = gsz / c.mp;
+  int ncand = 0;
+  if (hL != kNone) {
+    ScoreK s = coop_make(u, c, hL, hW, kTarget);
+    if (better<P>(g, u, sd, sig, s, best)) best = s;
+    ncand = r == 0;
+  }
+  // subgroups take table slots in turn; every lane runs the same number of turns
+  for (int i0 = 0; i0 < tab.size(); i0 += nsub) {
+    const int i = i0 + sub;
+    const uint32_t key = i < tab.size() ? tab.K[i] : 0u;
+    if (key == 0 || key - 1 == u.D || key - 1 == hL) continue;
+    const int64_t W = tab.V[i];
+    if (P::prunable(u, W, best)) continue;
+    ncand += c.j == 0;
+    ScoreK s = coop_make(u, c, key - 1, W, kTarget);
+    if (better<P>(g, u, sd, sig, s, best)) best = s;
+  }
+  if (pc.c) {
+    if (ncand) atomicAdd(pc.c + 2, (unsigned long long)ncand);
+    if (r == 0) {
+      atomicAdd(pc.c + 0, 1ull);
+      atomicAdd(pc.c + 1, (unsigned long long)g.degree(u.v));
+    }
+  }
+  best = group_best<P>(grp, g, u, sd, sig, best, red);
+  const int64_t wD = tab.get(u.D);
+  const ScoreK stay = coop_make(u, c, u.D, wD, kStay);
+  uint32_t out = kNone;
+  if (P::cmp(g, u, sd, sig, best, stay) > 0)
+    out = best.lab == kNone ? fresh_base + (uint32_t)u.v : best.lab;
+  grp.sync();
+  return out;
+}
 
 template <class P, class V, class Grp, class Tab>
 __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd, int64_t v,
@@ -429,6 +561,10 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   int64_t hW;
   uint32_t hL;
   group_heaviest(grp, tab, D, (const uint8_t *)nullptr, hW, hL, sredW, sredL);
+  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) {
+    if (u.m >= kCoopMinM)
+      return lm_unit_coop<P>(grp, tab, g, sd, u, sig, fresh_base, red, pc, best, hW, hL);
+  }
   int ncand = 0;
   if (hL != kNone) {
     typename P::Score s = P::make(g, u, sd, sig, hL, hW, kTarget);
@@ -471,6 +607,24 @@ constexpr int kNumBins = 7;
 __host__ __device__ inline uint32_t degree_bin(int64_t d) {
   return d <= 4 ? 0u : d <= 8 ? 1u : d <= 16 ? 2u : d <= 32 ? 3u
        : d <= kWaveMaxDeg ? 4u : d <= kBlockMaxDeg ? 5u : 6u;
+}
+// Bin of a unit of degree d in m slices: by degree; a unit in kCoopMinM or more slices is
+// evaluated cooperatively by a wave, or by a block when its (candidate x slice) work exceeds
+// 64 turns of a wave.  A bin never receives a degree above its table's capacity
+// (bin_fits checks that on the host before the first solve).
+__host__ __device__ inline uint32_t bin_of(int64_t d, int m) {
+  if (m < kCoopMinM) return degree_bin(d);
+  if (d > kBlockMaxDeg) return 6u;
+  if (d > kWaveMaxDeg || d * coop_width(m) > 64 * 64) return 5u;
+  return 4u;
+}
+__host__ __device__ inline bool bin_fits(int64_t d, uint32_t bin) {
+  const int64_t cap[kNumBins] = {4, 8, 16, 32, kWaveMaxDeg, kBlockMaxDeg, INT64_MAX};
+  return bin < (uint32_t)kNumBins && d <= cap[bin];
+}
+__device__ inline uint32_t unit_bin(const View0 &g, int64_t v) { return degree_bin(g.degree(v)); }
+__device__ inline uint32_t unit_bin(const ViewK &g, int64_t v) {
+  return bin_of(g.degree(v), g.plen(v));
 }
 
 // Units of degree <= G: G lanes per unit, one adjacency entry per lane; the group merges
@@ -732,7 +886,7 @@ __global__ void k_batch_keys(V g, int64_t n, const int32_t *colour, const uint8_
     keys[v] = kInactiveKey;
     return;
   }
-  keys[v] = ((uint32_t)colour[v] << 3) | degree_bin(g.degree(v));
+  keys[v] = ((uint32_t)colour[v] << 3) | unit_bin(g, v);
 }
 
 template <class V>
@@ -741,7 +895,7 @@ __global__ void k_bin_keys(V g, int64_t n, const uint8_t *sactive, uint32_t *key
   if (v >= n) return;
   vals[v] = (uint32_t)v;
   uint32_t bin = kNumBins;
-  if (sactive[g.usolve[v]]) bin = degree_bin(g.degree(v));
+  if (sactive[g.usolve[v]]) bin = unit_bin(g, v);
   keys[v] = bin;
 }
 // first[key] = first position of key in a sorted key array (keys below nkeys only)
@@ -879,7 +1033,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
   const int ncol = s_maxc + 1;
   const int nkey = kSweeps ? ncol : 8 * ncol;
   auto key_of = [&](int64_t v) -> int {
-    return kSweeps ? colour[v] : (colour[v] << 3) | (int)degree_bin(g.degree(v));
+    return kSweeps ? colour[v] : (colour[v] << 3) | (int)unit_bin(g, v);
   };
   for (int c = tid; c <= nkey; c += kSmallThreads) start[c] = 0;
   __syncthreads();

@@ -56,7 +56,10 @@ class Result(C.Structure):
                 ("ms_refine", C.c_double), ("ms_aggregate", C.c_double),
                 ("ms_finish", C.c_double), ("lm_kernel_ms", C.c_double),
                 ("lm_launches", C.c_int64), ("lm_units", C.c_int64), ("lm_entries", C.c_int64),
-                ("lm_candidates", C.c_int64), ("q_components", C.c_int64 * (3 * 64 + 1))]
+                ("lm_candidates", C.c_int64), ("q_components", C.c_int64 * (3 * 64 + 1)),
+                ("lm0_kernel_ms", C.c_double), ("lm0_launches", C.c_int64),
+                ("lm0_units", C.c_int64), ("lm0_entries", C.c_int64),
+                ("lm0_candidates", C.c_int64)]
 
     def as_dict(self, n_slices):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "q_components"}
