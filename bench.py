@@ -6,6 +6,8 @@ already resident in HBM.  Prints one JSON line (see the keys below).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg1]
                     [--no-cpu-baseline]
+    python bench.py --workload cfg4 [--graphs 512]         # batched grid vs plain calls
+    python bench.py --workload cfg5 [--requests 1000]      # served Poisson trace vs plain FIFO
 """
 from __future__ import annotations
 
@@ -77,6 +79,162 @@ def roofline(nbytes, ms, launches, kernel):
             "avg_launch_us": ms * 1e3 / max(launches, 1)}
 
 
+def _digest(memb, res):
+    import hashlib
+    h = hashlib.sha256(memb.astype("int32").tobytes())
+    h.update(res["q_components"].astype("int64").tobytes())
+    return h.hexdigest()
+
+
+def bench_batched(args):
+    """Config 4: the (graph x gamma x omega) grid of the batched workload as one batched call
+    (mslm_batch_leiden, run in chunks of bounded size) against the same solves as one plain
+    mslm_leiden call each, over the same resident graphs; every result must be identical."""
+    from paper_2608_03695_amd import gen
+    ng = args.graphs
+    log(f"generating {ng} batched-workload graphs")
+    tgs = gen.batch_graphs(range(ng), workers=args.gen_workers)
+    import torch
+    from paper_2608_03695_amd import mslm
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    handles = [mslm.Graph(tg, 1) for tg in tgs]
+    m_supra = sum(h.info()["nnz"] // 2 for h in handles)
+    solves = [(g, sp.gamma, sp.omega, sp.max_levels, sp.max_iterations, sp.seed)
+              for g, sp in gen.batch_solves(ng)]
+    log(f"{len(solves)} solves over {ng} graphs ({m_supra} supra-edges); warm-up")
+    mslm.batch_leiden(handles, solves[: min(len(solves), 18)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = mslm.batch_leiden(handles, solves)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batched: {t_batch:.2f} s")
+    dig_batch = [_digest(m, r) for m, r in got]
+    del got
+    t0 = time.perf_counter()
+    dig_plain = []
+    for i, (gi, gam, om, lv, it, seed) in enumerate(solves):
+        m, r = handles[gi].leiden(gam, om, max_levels=lv, max_iterations=it, seed=seed)
+        dig_plain.append(_digest(m, r))
+        if i % 500 == 499:
+            log(f"plain {i + 1}/{len(solves)}")
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = sum(a == b for a, b in zip(dig_batch, dig_plain))
+    return {
+        "metric": "batched solves/s vs plain (config 4)",
+        "value": len(solves) / t_batch, "unit": "solves/s",
+        "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"cfg4_batched_{ng}_graphs_x_9_solves", "graphs": ng,
+                   "solves": len(solves), "supra_edges_per_grid_point": m_supra},
+        "batched_s": t_batch, "plain_s": t_plain, "plain_solves_per_s": len(solves) / t_plain,
+        "speedup_vs_plain": t_plain / t_batch,
+        "identical_results": f"{same}/{len(solves)}",
+    }
+
+
+def bench_served(args):
+    """Config 5: Poisson request stream through the continuous-batching server (admission by
+    footprint, worker slots on their own streams) against a FIFO replay of the same trace
+    through plain create + leiden + destroy, one request at a time."""
+    import threading
+    import numpy as np
+    from paper_2608_03695_amd import gen
+    ng = args.graphs
+    log(f"generating {ng} batched-workload graphs and 8 config-2-sized graphs")
+    small = gen.batch_graphs(range(ng), workers=args.gen_workers)
+    large = [gen.large_serve_graph(i, workers=args.gen_workers) for i in range(8)]
+    import torch
+    from paper_2608_03695_amd import mslm
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free * 0.6)
+
+    def requests(rate):
+        out = []
+        for rq in gen.serve_trace(args.requests, rate, n_graphs=ng):
+            tg = large[rq["graph"]] if rq["large"] else small[rq["graph"]]
+            out.append((rq["t"], tg, rq["spec"]))
+        return out
+
+    def run_server(reqs, realtime):
+        srv = mslm.Server(budget, max_slots=args.slots)
+        tickets = [None] * len(reqs)
+        done = {}
+
+        def submit():
+            t0 = time.perf_counter()
+            for i, (t, tg, sp) in enumerate(reqs):
+                if realtime:
+                    dt = t - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                tickets[i] = srv.submit(tg, sp.gamma, sp.omega, sp.max_levels,
+                                        sp.max_iterations, sp.seed)
+        th = threading.Thread(target=submit)
+        t0 = time.perf_counter()
+        th.start()
+        th.join()
+        lat = []
+        for i in range(len(reqs)):
+            m, r, l = srv.wait(tickets[i])
+            done[i] = _digest(m, r)
+            lat.append(l)
+            if i % 200 == 199:
+                log(f"served {i + 1}/{len(reqs)}")
+        t_all = time.perf_counter() - t0
+        srv.close()
+        return np.array(lat), t_all, done
+
+    # capacity: every request submitted at once
+    reqs0 = requests(1.0)
+    log("capacity run")
+    lat0, t0_all, _ = run_server([(0.0, tg, sp) for _, tg, sp in reqs0], False)
+    capacity = len(reqs0) / t0_all
+    rate = 0.7 * capacity
+    reqs = requests(rate)
+    log(f"capacity {capacity:.1f} solves/s; Poisson replay at {rate:.1f}/s")
+    lat, t_all, dig_srv = run_server(reqs, True)
+    # FIFO replay through plain calls on the same arrival times
+    log("plain FIFO replay")
+    lat_p = []
+    dig_plain = {}
+    t0 = time.perf_counter()
+    for i, (t, tg, sp) in enumerate(reqs):
+        now = time.perf_counter() - t0
+        if now < t:
+            time.sleep(t - now)
+        g = mslm.Graph(tg, sp.omega)
+        m, r = g.leiden(sp.gamma, sp.omega, max_levels=sp.max_levels,
+                        max_iterations=sp.max_iterations, seed=sp.seed)
+        g.close()
+        lat_p.append(time.perf_counter() - t0 - t)
+        dig_plain[i] = _digest(m, r)
+        if i % 200 == 199:
+            log(f"plain {i + 1}/{len(reqs)}")
+    t_plain = time.perf_counter() - t0
+    lat_p = np.array(lat_p)
+    same = sum(dig_srv[i] == dig_plain[i] for i in range(len(reqs)))
+    return {
+        "metric": "served p50/p99 latency and solves/s vs plain FIFO (config 5)",
+        "value": len(reqs) / t_all, "unit": "solves/s",
+        "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "cfg5_poisson_mix", "requests": len(reqs), "graphs": ng,
+                   "large_fraction": 0.05, "slots": args.slots, "budget_bytes": budget,
+                   "rate_per_s": rate},
+        "capacity_solves_per_s": capacity,
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "plain_p50_s": float(np.percentile(lat_p, 50)),
+        "plain_p99_s": float(np.percentile(lat_p, 99)),
+        "plain_solves_per_s": len(reqs) / t_plain,
+        "identical_results": f"{same}/{len(reqs)}",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,12 +246,19 @@ def main():
                     help="skip the extra counting solve (keeps profiler traces to the timed steps)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes drawing the synthetic snapshots (1 under a profiler)")
+    ap.add_argument("--graphs", type=int, default=512, help="cfg4/cfg5: batched-workload graphs")
+    ap.add_argument("--requests", type=int, default=1000, help="cfg5: requests in the trace")
+    ap.add_argument("--slots", type=int, default=4, help="cfg5: server worker slots")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               f"multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
 
+    if args.workload in ("cfg4", "cfg5"):
+        out = bench_batched(args) if args.workload == "cfg4" else bench_served(args)
+        print(json.dumps(out), flush=True)
+        return
     # inputs are drawn before anything touches the GPU (the generator may use child processes)
     log(f"generating {args.workload}")
     tg, spec = workload(args.workload, args.gen_workers)

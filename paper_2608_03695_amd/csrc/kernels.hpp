@@ -334,6 +334,13 @@ struct BlockGrp {
   __device__ int size() const { return blockDim.x; }
   __device__ void sync() const { __syncthreads(); }
 };
+// A block whose accumulation table lives in global memory: its barriers must also make the
+// plain stores and atomics of every wave visible to the others.
+struct BlockGrpG {
+  __device__ int rank() const { return threadIdx.x; }
+  __device__ int size() const { return blockDim.x; }
+  __device__ void sync() const { block_sync_global(); }
+};
 
 // Reduce a score over the group; every thread gets the result.
 template <class P, class V>
@@ -355,6 +362,13 @@ __device__ inline typename P::Score group_best(BlockGrp grp, const V &g, const U
     if (better<P>(g, u, sd, tab, red[i], b)) b = red[i];
   grp.sync();
   return b;
+}
+
+template <class P, class V>
+__device__ inline typename P::Score group_best(BlockGrpG, const V &g, const UnitCtx &u,
+                                               const SolveDev &sd, const SliceTable &tab,
+                                               typename P::Score s, typename P::Score *red) {
+  return group_best<P>(BlockGrp(), g, u, sd, tab, s, red);   // LDS only
 }
 
 // heaviest entry of the accumulation table over the group (ties to the lower label), skipping
@@ -738,7 +752,7 @@ __global__ __launch_bounds__(256) void k_lm_gtab(V g, SolveDev sd, const int32_t
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int64_t v = units[idx];
     GTab tab{gk + goff[v], gv + goff[v], glg[v]};
-    uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, v, comm, sig, fresh_base, red, pc, hw, hl);
+    uint32_t t = lm_unit<P>(BlockGrpG(), tab, g, sd, v, comm, sig, fresh_base, red, pc, hw, hl);
     if (threadIdx.x == 0) target[idx] = t;
   }
 }
@@ -1035,20 +1049,22 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
   auto key_of = [&](int64_t v) -> int {
     return kSweeps ? colour[v] : (colour[v] << 3) | (int)unit_bin(g, v);
   };
+  // every hand-over of global memory between waves (plain stores, then atomics or loads of
+  // other waves) goes through block_sync_global: a plain barrier does not wait for stores
   for (int c = tid; c <= nkey; c += kSmallThreads) start[c] = 0;
-  __syncthreads();
+  block_sync_global();
   for (int64_t i = tid; i < nwork; i += kSmallThreads)
     atomicAdd(reinterpret_cast<unsigned long long *>(start + key_of(work[i]) + 1), 1ull);
-  __syncthreads();
+  block_sync_global();
   if (tid == 0) {
     for (int c = 0; c < nkey; c++) start[c + 1] += start[c];
     *ncol_out = ncol;
   }
-  __syncthreads();
+  block_sync_global();
   // scatter: decisions inside a batch are independent and moves commute, so the order of
   // units inside a colour does not matter
   for (int c = tid; c < nkey; c += kSmallThreads) cnt[c] = (uint32_t)start[c];
-  __syncthreads();
+  block_sync_global();
   for (int64_t i = tid; i < nwork; i += kSmallThreads) {
     const int32_t v = work[i];
     order[atomicAdd(cnt + key_of(v), 1u)] = v;
@@ -1382,7 +1398,7 @@ __global__ __launch_bounds__(256) void k_ref_prop_gtab(V g, SolveDev sd, const i
     const int64_t v = units[idx];
     if (!active[v]) continue;
     GTab tab{gk + goff[v], gv + goff[v], glg[v]};
-    ref_unit<P>(BlockGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propr, stamp, propw, active,
+    ref_unit<P>(BlockGrpG(), tab, g, sd, v, comm, R, wcT, sr, prop, propr, stamp, propw, active,
                 red, hw, hl);
   }
 }
@@ -1634,6 +1650,10 @@ __global__ void k_count_key_heads(const uint64_t *keys, int64_t n, uint32_t *cnt
   bool h = i < n && (i == 0 || keys[i] != keys[i - 1]);
   wave_count(cnt, h ? (int)(keys[i] >> 32) : 0, h);
 }
+__global__ void k_fingerprint(const uint32_t *lab, int64_t n, unsigned long long *acc) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicAdd(acc, (unsigned long long)mix64(((uint64_t)v << 32) | lab[v]));
+}
 __global__ void k_offset_labels(const int32_t *lab, const int32_t *usolve, const int64_t *uoff,
                                 int64_t n, uint32_t *out) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1700,25 +1720,28 @@ __global__ __launch_bounds__(256) void k_uf_link(View0 g, SolveDev sd, const int
     }
 }
 
+// Root of every element into a separate array: other threads' path halving keeps rewriting
+// parent[] with ancestors while this runs, so parent[] itself is not a root map afterwards.
 __global__ void k_uf_roots(int32_t *parent, const int64_t *lo, const int64_t *hi, int nr,
-                           uint8_t *isroot) {
+                           uint8_t *isroot, int32_t *root) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int k = 0; k < nr; k++)
     for (int64_t i = lo[k] + tid; i < hi[k]; i += stride) {
       int32_t r = uf_find(parent, (int32_t)i);
-      parent[i] = r;
+      root[i] = r;
       isroot[i] = r == (int32_t)i;
     }
 }
 
-__global__ void k_label_out(const int32_t *parent, const int64_t *rank, const int64_t *lo,
+// memb[i] = rank of i's root among the roots of its range; root and memb may alias
+__global__ void k_label_out(const int32_t *root, const int64_t *rank, const int64_t *lo,
                             const int64_t *hi, const int64_t *roff, int nr, int32_t *memb) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int k = 0; k < nr; k++)
     for (int64_t i = lo[k] + tid; i < hi[k]; i += stride)
-      memb[i] = (int32_t)(rank[parent[i]] - roff[k]);
+      memb[i] = (int32_t)(rank[root[i]] - roff[k]);
 }
 
 __global__ void k_flatten(const int64_t *map0, const uint32_t *P, const int64_t *lo,

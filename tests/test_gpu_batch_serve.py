@@ -113,3 +113,24 @@ def test_server_admission_and_errors():
     with pytest.raises(mslm.MslmError):
         one.wait(12345)          # unknown ticket
     one.close()
+
+
+def test_same_handle_parameter_sweep_matches_oracle():
+    """Many solves with different (gamma, omega) on one graph handle, then one compared with
+    the oracle: the connectivity split must not depend on what earlier solves left behind
+    (a root map read while other threads still halve paths once gave wrong labels)."""
+    import oracle
+    mslm = _mslm()
+    tg = gen.batch_graph(20)          # N=4883, T=27: the batched workload's graph 20
+    g = mslm.Graph(tg, 1)
+    for gamma in (F(1, 2), F(1), F(2)):
+        for omega in (F(1, 10), F(1), F(10)):
+            g.leiden(gamma, omega)
+    m, r = g.leiden(F(1), F(10))
+    g.close()
+    om, oc, ost = oracle.OracleGraph(tg, F(10)).leiden(F(1), max_levels=32, max_iterations=2,
+                                                       seed=0)
+    assert np.array_equal(m, om)
+    assert np.array_equal(r["q_components"], oc)
+    for k in STAT_KEYS:
+        assert r[k] == ost[k], k
