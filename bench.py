@@ -105,23 +105,31 @@ def bench_batched(args):
     log(f"{len(solves)} solves over {ng} graphs ({m_supra} supra-edges); warm-up")
     mslm.batch_leiden(handles, solves[: min(len(solves), 18)])
     torch.cuda.synchronize()
+    # batched calls of 576 solves each (the library chunks further by size); a progress line
+    # after each keeps long runs visibly alive
+    dig_batch = []
+    t_batch = 0.0
+    step = 576
+    for c0 in range(0, len(solves), step):
+        t0 = time.perf_counter()
+        got = mslm.batch_leiden(handles, solves[c0:c0 + step])
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t0
+        dig_batch += [_digest(m, r) for m, r in got]
+        del got
+        log(f"batched {min(c0 + step, len(solves))}/{len(solves)}: {t_batch:.1f} s")
+    # plain calls on every k-th solve of the grid (k = --plain-sample), same order
+    picked = list(range(0, len(solves), max(1, args.plain_sample)))
     t0 = time.perf_counter()
-    got = mslm.batch_leiden(handles, solves)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    log(f"batched: {t_batch:.2f} s")
-    dig_batch = [_digest(m, r) for m, r in got]
-    del got
-    t0 = time.perf_counter()
-    dig_plain = []
-    for i, (gi, gam, om, lv, it, seed) in enumerate(solves):
+    same = 0
+    for n_done, i in enumerate(picked):
+        gi, gam, om, lv, it, seed = solves[i]
         m, r = handles[gi].leiden(gam, om, max_levels=lv, max_iterations=it, seed=seed)
-        dig_plain.append(_digest(m, r))
-        if i % 500 == 499:
-            log(f"plain {i + 1}/{len(solves)}")
+        same += _digest(m, r) == dig_batch[i]
+        if n_done % 200 == 199:
+            log(f"plain {n_done + 1}/{len(picked)}")
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    same = sum(a == b for a, b in zip(dig_batch, dig_plain))
     return {
         "metric": "batched solves/s vs plain (config 4)",
         "value": len(solves) / t_batch, "unit": "solves/s",
@@ -129,9 +137,10 @@ def bench_batched(args):
         "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"cfg4_batched_{ng}_graphs_x_9_solves", "graphs": ng,
                    "solves": len(solves), "supra_edges_per_grid_point": m_supra},
-        "batched_s": t_batch, "plain_s": t_plain, "plain_solves_per_s": len(solves) / t_plain,
-        "speedup_vs_plain": t_plain / t_batch,
-        "identical_results": f"{same}/{len(solves)}",
+        "batched_s": t_batch, "plain_sample": f"every {max(1, args.plain_sample)}th solve",
+        "plain_s": t_plain, "plain_solves_per_s": len(picked) / t_plain,
+        "speedup_vs_plain": (len(solves) / t_batch) / (len(picked) / t_plain),
+        "identical_results": f"{same}/{len(picked)} sampled solves",
     }
 
 
@@ -249,6 +258,8 @@ def main():
     ap.add_argument("--graphs", type=int, default=512, help="cfg4/cfg5: batched-workload graphs")
     ap.add_argument("--requests", type=int, default=1000, help="cfg5: requests in the trace")
     ap.add_argument("--slots", type=int, default=4, help="cfg5: server worker slots")
+    ap.add_argument("--plain-sample", type=int, default=8,
+                    help="cfg4: time plain calls on every k-th solve of the grid")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "

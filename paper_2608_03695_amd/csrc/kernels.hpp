@@ -284,6 +284,47 @@ struct PolicyK {
   }
 };
 
+// Aggregated levels, units in at most one slice: the same int128 value as PolicyK's
+// single-slice case without the multi-slice machinery (far fewer registers).
+struct Score1 {
+  i128 ex;
+  uint32_t lab;
+};
+struct PolicyK1 {
+  typedef Score1 Score;
+  template <class V>
+  __device__ static Score make(const V &, const UnitCtx &u, const SolveDev &,
+                               const SliceTable &tab, uint32_t lab, int64_t W, int kind) {
+    Score s;
+    s.lab = kind == kEmpty ? kNone : lab;
+    i128 val = (i128)u.q * W;
+    if (u.m == 1) {
+      int64_t y = target_y(tab, u.gs0, u.k0, lab, kind);
+      val = val * u.S0 - (i128)u.pb * (i128)(u.k0 * y);
+    }
+    s.ex = val;
+    return s;
+  }
+  template <class V>
+  __device__ static int cmp(const V &, const UnitCtx &, const SolveDev &, const SliceTable &,
+                            const Score &a, const Score &b) {
+    return a.ex < b.ex ? -1 : (a.ex > b.ex ? 1 : 0);
+  }
+  __device__ static bool prunable(const UnitCtx &u, int64_t W, const Score &best) {
+    i128 ub = (i128)u.q * W * (u.m ? u.S0 : 1);
+    return ub < best.ex;
+  }
+  __device__ static Score shfl(const Score &s, int m) {
+    Score o;
+    uint64_t lo = (uint64_t)s.ex, hi = (uint64_t)(s.ex >> 64);
+    lo = (uint64_t)shfl_xor64((int64_t)lo, m);
+    hi = (uint64_t)shfl_xor64((int64_t)hi, m);
+    o.ex = (i128)(((unsigned __int128)hi << 64) | lo);
+    o.lab = shfl_xor32(s.lab, m);
+    return o;
+  }
+};
+
 template <class P, class V>
 __device__ inline bool better(const V &g, const UnitCtx &u, const SolveDev &sd, const SliceTable &tab,
                               const typename P::Score &a, const typename P::Score &b) {
@@ -610,17 +651,25 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
 }
 
 constexpr int kWaveLg = 9;        // 512-slot LDS table per wave: units of degree <= 256
-constexpr int kBlockLg = 13;      // 8192-slot LDS table per block: degree <= 4096
+constexpr int kBlockLg = 13;      // 8192-slot LDS table per 1024-thread block: degree <= 4096
+constexpr int kSmallBlockLg = 11; // 2048-slot LDS table per 256-thread block: degree <= 1024
 constexpr int kWaveMaxDeg = 256;
+constexpr int kSmallBlockMaxDeg = 1024;
 constexpr int kBlockMaxDeg = 4096;
 
 // Degree bins of the decision kernels: 0..3 lane groups of 4/8/16/32 lanes per unit (one
 // adjacency entry per lane, equal labels merged with shuffles), 4 a wave with an LDS
 // table, 5 a block with an LDS table, 6 a block with a global-memory table.
-constexpr int kNumBins = 7;
+constexpr int kNumBins = 8;
+constexpr int kBinWaveLast = 4;          // bins 0..4 fit a wave's table
+constexpr int kBinGtab = kNumBins - 1;   // global-memory tables
+// Colour batches are bucketed by (colour, slot): slots 0..7 are the degree bins; at aggregated
+// levels units in at most one slice use slots 8..15 and the lean single-slice decision.
+constexpr int kBatchShift = 4;
+constexpr int kBatchSlots = 1 << kBatchShift;
 __host__ __device__ inline uint32_t degree_bin(int64_t d) {
   return d <= 4 ? 0u : d <= 8 ? 1u : d <= 16 ? 2u : d <= 32 ? 3u
-       : d <= kWaveMaxDeg ? 4u : d <= kBlockMaxDeg ? 5u : 6u;
+       : d <= kWaveMaxDeg ? 4u : d <= kSmallBlockMaxDeg ? 5u : d <= kBlockMaxDeg ? 6u : 7u;
 }
 // Bin of a unit of degree d in m slices: by degree; a unit in kCoopMinM or more slices is
 // evaluated cooperatively by a wave, or by a block when its (candidate x slice) work exceeds
@@ -628,17 +677,24 @@ __host__ __device__ inline uint32_t degree_bin(int64_t d) {
 // (bin_fits checks that on the host before the first solve).
 __host__ __device__ inline uint32_t bin_of(int64_t d, int m) {
   if (m < kCoopMinM) return degree_bin(d);
-  if (d > kBlockMaxDeg) return 6u;
-  if (d > kWaveMaxDeg || d * coop_width(m) > 64 * 64) return 5u;
-  return 4u;
+  const int64_t work = d * coop_width(m);
+  if (d > kBlockMaxDeg) return 7u;
+  if (d <= kWaveMaxDeg && work <= 64 * 64) return 4u;
+  if (d <= kSmallBlockMaxDeg && work <= 256 * 64) return 5u;
+  return 6u;
 }
 __host__ __device__ inline bool bin_fits(int64_t d, uint32_t bin) {
-  const int64_t cap[kNumBins] = {4, 8, 16, 32, kWaveMaxDeg, kBlockMaxDeg, INT64_MAX};
+  const int64_t cap[kNumBins] = {4, 8, 16, 32, kWaveMaxDeg, kSmallBlockMaxDeg, kBlockMaxDeg,
+                                 INT64_MAX};
   return bin < (uint32_t)kNumBins && d <= cap[bin];
 }
 __device__ inline uint32_t unit_bin(const View0 &g, int64_t v) { return degree_bin(g.degree(v)); }
 __device__ inline uint32_t unit_bin(const ViewK &g, int64_t v) {
   return bin_of(g.degree(v), g.plen(v));
+}
+__device__ inline uint32_t batch_slot(const View0 &g, int64_t v) { return unit_bin(g, v); }
+__device__ inline uint32_t batch_slot(const ViewK &g, int64_t v) {
+  return unit_bin(g, v) + (g.plen(v) <= 1 ? (uint32_t)kNumBins : 0u);
 }
 
 // Units of degree <= G: G lanes per unit, one adjacency entry per lane; the group merges
@@ -720,17 +776,17 @@ __global__ __launch_bounds__(256) void k_lm_wave(V g, SolveDev sd, const int32_t
   if ((threadIdx.x & 63) == 0) target[idx] = t;
 }
 
-template <class P, class V>
-__global__ __launch_bounds__(1024) void k_lm_block(V g, SolveDev sd, const int32_t *units,
-                                                   int64_t count, const uint32_t *comm,
-                                                   SliceTable sig, uint32_t *target,
-                                                   uint32_t fresh_base, LmCounters pc) {
-  __shared__ uint32_t sk[1 << kBlockLg];
-  __shared__ int64_t sv[1 << kBlockLg];
-  __shared__ typename P::Score red[16];
-  __shared__ int64_t hw[16];
-  __shared__ uint32_t hl[16];
-  LdsTab tab{sk, sv, kBlockLg};
+template <class P, class V, int NT, int LG>
+__global__ __launch_bounds__(NT) void k_lm_block(V g, SolveDev sd, const int32_t *units,
+                                                 int64_t count, const uint32_t *comm,
+                                                 SliceTable sig, uint32_t *target,
+                                                 uint32_t fresh_base, LmCounters pc) {
+  __shared__ uint32_t sk[1 << LG];
+  __shared__ int64_t sv[1 << LG];
+  __shared__ typename P::Score red[NT / 64];
+  __shared__ int64_t hw[NT / 64];
+  __shared__ uint32_t hl[NT / 64];
+  LdsTab tab{sk, sv, LG};
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, units[idx], comm, sig, fresh_base, red, pc,
                             hw, hl);
@@ -900,7 +956,7 @@ __global__ void k_batch_keys(V g, int64_t n, const int32_t *colour, const uint8_
     keys[v] = kInactiveKey;
     return;
   }
-  keys[v] = ((uint32_t)colour[v] << 3) | unit_bin(g, v);
+  keys[v] = ((uint32_t)colour[v] << kBatchShift) | batch_slot(g, v);
 }
 
 template <class V>
@@ -1045,9 +1101,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
   }
   // ---- bucket the units by colour, or by (colour, degree bin) for the multi-launch sweeps
   const int ncol = s_maxc + 1;
-  const int nkey = kSweeps ? ncol : 8 * ncol;
+  const int nkey = kSweeps ? ncol : kBatchSlots * ncol;
   auto key_of = [&](int64_t v) -> int {
-    return kSweeps ? colour[v] : (colour[v] << 3) | (int)unit_bin(g, v);
+    return kSweeps ? colour[v] : (colour[v] << kBatchShift) | (int)batch_slot(g, v);
   };
   // every hand-over of global memory between waves (plain stores, then atomics or loads of
   // other waves) goes through block_sync_global: a plain barrier does not wait for stores
