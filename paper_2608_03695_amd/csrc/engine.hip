@@ -80,6 +80,7 @@ struct Workspace {
   Buf qW, qSS, qI, ranges_lo, ranges_hi, ranges_off;
   Buf sm_maxsw, sm_stat, sm_nz, sm_start;
   Buf b_src, b_dst, b_w, b_off, b_twom;   // graph build inputs and per-slice sums
+  Buf hubpart;                            // per-block best candidates of hub units
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };

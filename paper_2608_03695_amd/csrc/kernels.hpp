@@ -813,6 +813,130 @@ __global__ __launch_bounds__(256) void k_lm_gtab(V g, SolveDev sd, const int32_t
   }
 }
 
+// ------------------------------------------------------------------ hub units
+// Units above the block bins are spread over kHubBlocks blocks each (grid = kHubBlocks x
+// units): the blocks clear, fill and scan disjoint parts of the unit's global table, each
+// scan keeps its best candidate, and one wave per unit reduces those with the same total
+// order (value, then label) and compares with staying.  The result equals one group's.
+constexpr int kHubBlocks = 16;
+
+__global__ __launch_bounds__(256) void k_hub_clear(const int32_t *units, const int64_t *goff,
+                                                   const int32_t *glg, uint32_t *gk, int64_t *gv) {
+  const int64_t v = units[blockIdx.y];
+  const int64_t size = 1ll << glg[v], base = goff[v];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < size;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    gk[base + i] = 0;
+    gv[base + i] = 0;
+  }
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_hub_accum(V g, SolveDev sd, const int32_t *units,
+                                                   const uint32_t *comm, const int64_t *goff,
+                                                   const int32_t *glg, uint32_t *gk, int64_t *gv,
+                                                   LmCounters pc) {
+  const int64_t v = units[blockIdx.y];
+  GTab tab{gk + goff[v], gv + goff[v], glg[v]};
+  typename V::Row row = g.row(v, sd);
+  for (int64_t e = row.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < row.hi;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = g.col[e];
+    const int64_t w = g.wt(row, e, x);
+    if (w != 0) tab.add(comm[x], w);
+  }
+  if (pc.c && blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicAdd(pc.c + 0, 1ull);
+    atomicAdd(pc.c + 1, (unsigned long long)(row.hi - row.lo));
+  }
+}
+
+template <class P, class V>
+__global__ __launch_bounds__(256) void k_hub_eval(V g, SolveDev sd, const int32_t *units,
+                                                  const uint32_t *comm, SliceTable sig,
+                                                  const int64_t *goff, const int32_t *glg,
+                                                  const uint32_t *gk, const int64_t *gv,
+                                                  typename P::Score *part, LmCounters pc) {
+  __shared__ typename P::Score red[4];
+  const int64_t v = units[blockIdx.y];
+  const uint32_t D = comm[v];
+  const uint32_t *K = gk + goff[v];
+  const int64_t *Wt = gv + goff[v];
+  const int64_t size = 1ll << glg[v];
+  const int64_t span = (size + gridDim.x - 1) / gridDim.x;
+  const int64_t s0 = (int64_t)blockIdx.x * span, s1 = s0 + span < size ? s0 + span : size;
+  const UnitCtx u = unit_ctx(g, sd, v, D);
+  typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
+  int ncand = 0;
+  bool coop = false;
+  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) coop = u.m >= kCoopMinM;
+  if (coop) {
+    if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) {
+      const CoopLane c = coop_lane(g, u, sd, sig, threadIdx.x);
+      const int sub = threadIdx.x / c.mp, nsub = blockDim.x / c.mp;
+      for (int64_t i0 = s0; i0 < s1; i0 += nsub) {
+        const int64_t i = i0 + sub;
+        const uint32_t key = i < s1 ? K[i] : 0u;
+        if (key == 0 || key - 1 == D) continue;
+        const int64_t W = Wt[i];
+        if (P::prunable(u, W, best)) continue;
+        ncand += c.j == 0;
+        ScoreK sc = coop_make(u, c, key - 1, W, kTarget);
+        if (better<P>(g, u, sd, sig, sc, best)) best = sc;
+      }
+    }
+  } else {
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+      const uint32_t key = K[i];
+      if (key == 0 || key - 1 == D) continue;
+      const int64_t W = Wt[i];
+      if (P::prunable(u, W, best)) continue;
+      ncand++;
+      typename P::Score sc = P::make(g, u, sd, sig, key - 1, W, kTarget);
+      if (better<P>(g, u, sd, sig, sc, best)) best = sc;
+    }
+  }
+  if (pc.c && ncand) atomicAdd(pc.c + 2, (unsigned long long)ncand);
+  best = group_best<P>(BlockGrp(), g, u, sd, sig, best, red);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = best;
+}
+
+template <class P, class V>
+__global__ __launch_bounds__(64) void k_hub_final(V g, SolveDev sd, const int32_t *units,
+                                                  int64_t count, const uint32_t *comm,
+                                                  SliceTable sig, const int64_t *goff,
+                                                  const int32_t *glg, const uint32_t *gk,
+                                                  const int64_t *gv,
+                                                  const typename P::Score *part, int nparts,
+                                                  uint32_t *target, uint32_t fresh_base) {
+  const int64_t idx = blockIdx.x;
+  if (idx >= count) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t v = units[idx];
+  const uint32_t D = comm[v];
+  const UnitCtx u = unit_ctx(g, sd, v, D);
+  typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
+  if (lane < nparts) best = part[idx * nparts + lane];
+  best = wave_best<P>(g, u, sd, sig, best);
+  GTab tab{const_cast<uint32_t *>(gk) + goff[v], const_cast<int64_t *>(gv) + goff[v], glg[v]};
+  const int64_t wD = tab.get(D);
+  typename P::Score stay;
+  bool coop = false;
+  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) coop = u.m >= kCoopMinM;
+  if (coop) {
+    if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value)
+      stay = coop_make(u, coop_lane(g, u, sd, sig, lane), D, wD, kStay);
+  } else {
+    stay = P::make(g, u, sd, sig, D, wD, kStay);
+  }
+  if (lane == 0) {
+    uint32_t out = kNone;
+    if (P::cmp(g, u, sd, sig, best, stay) > 0)
+      out = best.lab == kNone ? fresh_base + (uint32_t)v : best.lab;
+    target[idx] = out;
+  }
+}
+
 // Apply the decided moves of one colour batch: new label, Sigma delta for every profile slice.
 template <class V>
 __global__ void k_lm_apply(V g, const int32_t *units, int64_t count, const uint32_t *target,
