@@ -701,14 +701,14 @@ __device__ inline uint32_t batch_slot(const ViewK &g, int64_t v) {
 // equal community labels with shuffles (the first lane holding a label leads it), every
 // leader evaluates its community, and the group reduces to the best.
 template <class P, class V, int G>
-__global__ __launch_bounds__(256) void k_lm_group(V g, SolveDev sd, const int32_t *units,
-                                                  int64_t count, const uint32_t *comm,
-                                                  SliceTable sig, uint32_t *target,
-                                                  uint32_t fresh_base, LmCounters pc) {
+__device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int32_t *units,
+                                      int64_t count, const uint32_t *comm, const SliceTable &sig,
+                                      uint32_t *target, uint32_t fresh_base, LmCounters pc,
+                                      int64_t blk) {
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);
-  const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t idx = (blk * blockDim.x + threadIdx.x) / G;
   if (idx >= count) return;   // whole groups leave together; shuffles stay inside a group
   const int64_t v = units[idx];
   const uint32_t D = comm[v];
@@ -760,6 +760,14 @@ __global__ __launch_bounds__(256) void k_lm_group(V g, SolveDev sd, const int32_
   }
 }
 
+template <class P, class V, int G>
+__global__ __launch_bounds__(256) void k_lm_group(V g, SolveDev sd, const int32_t *units,
+                                                  int64_t count, const uint32_t *comm,
+                                                  SliceTable sig, uint32_t *target,
+                                                  uint32_t fresh_base, LmCounters pc) {
+  lm_group_block<P, V, G>(g, sd, units, count, comm, sig, target, fresh_base, pc, blockIdx.x);
+}
+
 template <class P, class V>
 __global__ __launch_bounds__(256) void k_lm_wave(V g, SolveDev sd, const int32_t *units,
                                                  int64_t count, const uint32_t *comm,
@@ -792,6 +800,126 @@ __global__ __launch_bounds__(NT) void k_lm_block(V g, SolveDev sd, const int32_t
                             hw, hl);
     if (threadIdx.x == 0) target[idx] = t;
   }
+}
+
+// Bins 0..5 of one colour batch in one launch: consecutive block ranges per bin, each block
+// running that bin's code (fewer launches and no per-bin tail).
+struct BinSeg {
+  const int32_t *units;
+  uint32_t *target;
+  int64_t count;
+  int64_t blk0;     // first block of the segment
+};
+struct MultiSeg {
+  BinSeg s[6];
+  int64_t nblk;     // total blocks
+};
+
+template <class P, class V>
+__global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
+                                                  const uint32_t *comm, SliceTable sig,
+                                                  uint32_t fresh_base, LmCounters pc) {
+  __shared__ uint32_t sk[1 << kSmallBlockLg];        // 4 wave tables of 512, or one of 2048
+  __shared__ int64_t sv[1 << kSmallBlockLg];
+  __shared__ typename P::Score red[4];
+  __shared__ int64_t hw[4];
+  __shared__ uint32_t hl[4];
+  const int64_t b = blockIdx.x;
+  int k = 0;
+  while (k < 5 && b >= ms.s[k + 1].blk0) k++;
+  const BinSeg sg = ms.s[k];
+  const int64_t lb = b - sg.blk0;
+  switch (k) {
+    case 0:
+      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 1:
+      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 2:
+      lm_group_block<P, V, 16>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
+                               lb);
+      break;
+    case 3:
+      lm_group_block<P, V, 32>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
+                               lb);
+      break;
+    case 4: {
+      const int wv = threadIdx.x >> 6;
+      const int64_t idx = lb * 4 + wv;
+      if (idx >= sg.count) return;
+      LdsTab tab{sk + (wv << kWaveLg), sv + (wv << kWaveLg), kWaveLg};
+      uint32_t t = lm_unit<P>(WaveGrp(), tab, g, sd, sg.units[idx], comm, sig, fresh_base,
+                              (typename P::Score *)nullptr, pc);
+      if ((threadIdx.x & 63) == 0) sg.target[idx] = t;
+      break;
+    }
+    default: {
+      LdsTab tab{sk, sv, kSmallBlockLg};
+      uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, sg.units[lb], comm, sig, fresh_base, red,
+                              pc, hw, hl);
+      if (threadIdx.x == 0) sg.target[lb] = t;
+    }
+  }
+}
+
+// Latency mode (aggregated levels, colour batches of few units): every bin below the hub bin
+// of both unit classes in one launch.  Occupancy does not matter here, so one 1024-thread
+// kernel carries both policies and an LDS table large enough for degree 4096.
+struct LatSegs {
+  BinSeg s[2 * kBinGtab];   // class (single-slice, multi-slice) x bins 0..kBinGtab-1
+};
+
+template <class P, class V>
+__device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg, int bin,
+                               int64_t lb, const uint32_t *comm, const SliceTable &sig,
+                               uint32_t fresh_base, LmCounters pc, uint32_t *sk, int64_t *sv,
+                               typename P::Score *red, int64_t *hw, uint32_t *hl) {
+  switch (bin) {
+    case 0:
+      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 1:
+      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 2:
+      lm_group_block<P, V, 16>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
+                               lb);
+      break;
+    case 3:
+      lm_group_block<P, V, 32>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
+                               lb);
+      break;
+    default: {   // one unit per block; table sized by the bin's degree bound
+      const int lg = bin <= 5 ? kSmallBlockLg : kBlockLg;
+      LdsTab tab{sk, sv, lg};
+      uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, sg.units[lb], comm, sig, fresh_base, red,
+                              pc, hw, hl);
+      if (threadIdx.x == 0) sg.target[lb] = t;
+    }
+  }
+}
+
+template <class V>
+__global__ __launch_bounds__(1024) void k_lm_lat(V g, SolveDev sd, LatSegs ls,
+                                                 const uint32_t *comm, SliceTable sig,
+                                                 uint32_t fresh_base, LmCounters pc) {
+  __shared__ uint32_t sk[1 << kBlockLg];
+  __shared__ int64_t sv[1 << kBlockLg];
+  __shared__ ScoreK redK[16];
+  __shared__ Score1 red1[16];
+  __shared__ int64_t hw[16];
+  __shared__ uint32_t hl[16];
+  const int64_t b = blockIdx.x;
+  int k = 0;
+  while (k < 2 * kBinGtab - 1 && b >= ls.s[k + 1].blk0) k++;
+  const BinSeg sg = ls.s[k];
+  const int64_t lb = b - sg.blk0;
+  const int bin = k % kBinGtab;
+  if (k < kBinGtab)
+    lat_bin<PolicyK1>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, red1, hw, hl);
+  else
+    lat_bin<PolicyK>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, redK, hw, hl);
 }
 
 // Units of very high degree: a global-memory table per unit, slot offsets from a scan.
