@@ -1146,14 +1146,11 @@ __global__ __launch_bounds__(256) void k_jp_count(V g, SolveDev sd, const int32_
   wave_append(front, nfront, ready, (int32_t)v);
 }
 
+// Colour one frontier unit (one wave) and release its lower-priority neighbours into next.
 template <class V>
-__global__ __launch_bounds__(256) void k_jp_front(V g, SolveDev sd, const int32_t *front, int64_t nf,
-                                                  int32_t *colour, uint32_t *cnt, int32_t *next,
-                                                  uint32_t *nnext, int it, int lvl) {
+__device__ inline void jp_unit(const V &g, const SolveDev &sd, int64_t v, int32_t *colour,
+                               uint32_t *cnt, int32_t *next, uint32_t *nnext, int it, int lvl) {
   const int lane = threadIdx.x & 63;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= nf) return;
-  const int64_t v = front[idx];
   const int j = g.usolve[v];
   const uint64_t sm = sd.seedmix[j];
   const int64_t off = sd.uoff[j];
@@ -1193,6 +1190,24 @@ __global__ __launch_bounds__(256) void k_jp_front(V g, SolveDev sd, const int32_
     base = (uint32_t)__shfl((int)base, 0, 64);
     if (ready) next[base + __popcll(bal & ((1ull << lane) - 1))] = x;
   }
+}
+
+// One Jones-Plassmann round with its frontier size read on the device, so rounds can be
+// launched back to back without a host round trip: round r colours list[r&1] (count
+// counts[r%3]), appends the released units to list[(r+1)&1] (counts[(r+1)%3]) and clears the
+// counter of round r+2.  A round with an empty frontier does nothing.
+template <class V>
+__global__ __launch_bounds__(256) void k_jp_round(V g, SolveDev sd, int32_t *list0,
+                                                  int32_t *list1, uint32_t *counts,
+                                                  int32_t *colour, uint32_t *cnt, int r, int it,
+                                                  int lvl) {
+  const int64_t nf = counts[r % 3];
+  const int32_t *cur = (r & 1) ? list1 : list0;
+  int32_t *next = (r & 1) ? list0 : list1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[(r + 2) % 3] = 0;
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nf;
+       idx += (int64_t)gridDim.x * 4)
+    jp_unit(g, sd, (int64_t)cur[idx], colour, cnt, next, counts + (r + 1) % 3, it, lvl);
 }
 
 // sort key of a unit for batching: colour, then degree bin
