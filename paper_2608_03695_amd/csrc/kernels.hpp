@@ -181,20 +181,9 @@ struct ScoreK {
 };
 
 template <class V>
-__device__ __noinline__ int exact_cmp(const V &g, const UnitCtx &u, const SolveDev &sd,
+__device__ __noinline__ int exact_big(const V &g, const UnitCtx &u, const SolveDev &sd,
                                       const SliceTable &tab, uint32_t la, int ka, int64_t Wa,
                                       uint32_t lb, int kb, int64_t Wb) {
-  // equal per-slice terms (the usual case of two estimates that cannot be told apart: the
-  // two targets hold the same Sigma in every slice of the unit) need no big integers
-  atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks) + 1, 1ull);
-  bool same = true;
-  for (int jj = 0; jj < u.m && same; jj++) {
-    int gs;
-    int64_t k;
-    g.pent(u.v, jj, gs, k);
-    same = target_y(tab, gs, k, la, ka) == target_y(tab, gs, k, lb, kb);
-  }
-  if (same) return Wa > Wb ? 1 : (Wa < Wb ? -1 : 0);
   atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
   ExactAcc acc;
   acc.init();
@@ -207,6 +196,25 @@ __device__ __noinline__ int exact_cmp(const V &g, const UnitCtx &u, const SolveD
     acc.term(k * (ya - yb), sd.S[gs]);
   }
   return acc.sign(u.q, Wa - Wb, u.pb);
+}
+
+// Exact order of two targets whose estimates cannot be told apart.  Equal per-slice terms
+// (the usual case: both targets hold the same Sigma in every slice of the unit) are settled
+// here, inline; only a genuine near-tie calls the out-of-line big-integer evaluation (a call
+// spills the caller's registers, so it must stay off the common path).
+template <class V>
+__device__ inline int exact_cmp(const V &g, const UnitCtx &u, const SolveDev &sd,
+                                const SliceTable &tab, uint32_t la, int ka, int64_t Wa,
+                                uint32_t lb, int kb, int64_t Wb) {
+  bool same = true;
+  for (int jj = 0; jj < u.m && same; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(u.v, jj, gs, k);
+    same = target_y(tab, gs, k, la, ka) == target_y(tab, gs, k, lb, kb);
+  }
+  if (same) return Wa > Wb ? 1 : (Wa < Wb ? -1 : 0);
+  return exact_big(g, u, sd, tab, la, ka, Wa, lb, kb, Wb);
 }
 
 struct PolicyK {
