@@ -79,6 +79,31 @@ def roofline(nbytes, ms, launches, kernel):
             "avg_launch_us": ms * 1e3 / max(launches, 1)}
 
 
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "device.hpp", "engine_solve.inc"):
+        with open(os.path.join(ROOT, "paper_2608_03695_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, launches):
+    """HBM bytes per launch of the level-0 decision kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy), or None when the
+    summary is for another workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "lm0_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("workload") != workload or rec.get("sources_sha256") != kernel_sources_sha():
+        return None
+    if rec.get("launches") != launches:
+        return None
+    return (rec["fetch_bytes"] + rec["write_bytes"]) / rec["launches"]
+
+
 def _digest(memb, res):
     import hashlib
     h = hashlib.sha256(memb.astype("int32").tobytes())
@@ -327,7 +352,7 @@ def main():
                    "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
         # the HBM-bound loop: level-0 local-moving decisions (every sweep of every iteration)
         "roofline": roofline(nbytes("lm0"), mean("lm0_kernel_ms"), results[0]["lm0_launches"],
-                             "k_lm_group/k_lm_wave/k_lm_block/k_lm_gtab at level 0"),
+                             "k_lm_multi<Policy0, View0> (level-0 decisions)"),
         "roofline_all_levels": roofline(nbytes("lm"), mean("lm_kernel_ms"),
                                         results[0]["lm_launches"],
                                         "local-moving decisions at every level"),
@@ -338,6 +363,12 @@ def main():
                   "iterations": results[-1]["iterations_run"],
                   "exact_fallbacks": results[-1]["exact_fallbacks"]},
     }
+    rl = out["roofline"]
+    t = measured_traffic(tg.name, rl["launches_per_step"])
+    if t is not None:
+        rl["traffic"] = t
+        rl["traffic_gbs"] = t * rl["launches_per_step"] / (rl["kernel_ms_per_step"] * 1e-3) / 1e9
+        rl["bytes_per_launch"] = rl["bytes_per_step"] / max(rl["launches_per_step"], 1)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args)
