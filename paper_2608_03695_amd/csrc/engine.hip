@@ -81,6 +81,7 @@ struct Workspace {
   Buf sm_maxsw, sm_stat, sm_nz, sm_start;
   Buf b_src, b_dst, b_w, b_off, b_twom;   // graph build inputs and per-slice sums
   Buf hubpart;                            // per-block best candidates of hub units
+  Buf jph0, jph1;                         // heavy frontier lists of the colouring
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };
@@ -162,26 +163,46 @@ __global__ void k_build_csr(const uint64_t *keys, const int64_t *vals, int64_t m
   atomicAdd(reinterpret_cast<unsigned long long *>(rowcnt + (k >> 32)), 1ull);
 }
 
+// Intra degree of every unit and, per slice, 2m_s and the count of units with nonzero degree.
+// A wave's units are consecutive, so they nearly always lie in one slice: the wave sums first
+// and issues one atomic per counter (one atomic per unit on 64 addresses serialises).
 __global__ void k_build_degree(const int64_t *rp, const int32_t *col, const int32_t *w, int64_t n,
                                int32_t N, int32_t *kdeg, int64_t *twom, int64_t *nz) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  int64_t s = v / N, lo = s * N, hi = lo + N;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = v < n;
+  const int64_t s = live ? v / N : -1;
   int64_t d = 0;
-  for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
-    int32_t x = col[e];
-    if (x >= lo && x < hi) d += w[e];
+  if (live) {
+    const int64_t lo = s * N, hi = lo + N;
+    for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+      int32_t x = col[e];
+      if (x >= lo && x < hi) d += w[e];
+    }
+    kdeg[v] = (int32_t)(d < 0x7fffffff ? d : 0x7fffffff);
   }
-  kdeg[v] = (int32_t)(d < 0x7fffffff ? d : 0x7fffffff);
-  if (d) {
+  // lane 0 holds the wave's smallest unit, so it is live whenever any lane is
+  const int64_t s0 = __shfl(s, 0, 64);
+  if (__all(!live || s == s0)) {
+    int64_t dd = d, z = d != 0;
+    for (int m = 32; m >= 1; m >>= 1) {
+      dd += shfl_xor64(dd, m);
+      z += shfl_xor64(z, m);
+    }
+    if ((threadIdx.x & 63) == 0 && dd) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(twom + s0), (unsigned long long)dd);
+      atomicAdd(reinterpret_cast<unsigned long long *>(nz + s0), (unsigned long long)z);
+    }
+  } else if (d) {
     atomicAdd(reinterpret_cast<unsigned long long *>(twom + s), (unsigned long long)d);
     atomicAdd(reinterpret_cast<unsigned long long *>(nz + s), 1ull);
   }
 }
 
 __global__ void k_max_degree(const int64_t *rp, int64_t n, int *mx) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicMax(mx, (int)std::min<int64_t>(rp[v + 1] - rp[v], 0x7fffffff));
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int d = v < n ? (int)std::min<int64_t>(rp[v + 1] - rp[v], 0x7fffffff) : 0;
+  for (int m = 32; m >= 1; m >>= 1) d = max(d, __shfl_xor(d, m, 64));
+  if ((threadIdx.x & 63) == 0 && d > 0) atomicMax(mx, d);
 }
 
 }  // namespace

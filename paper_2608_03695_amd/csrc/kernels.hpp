@@ -817,11 +817,13 @@ struct BinSeg {
   uint32_t *target;
   int64_t count;
   int64_t blk0;     // first block of the segment
+  int64_t nbk;      // blocks with work (k_lm_multi: the segment spans nbk rounded up to kXcds)
 };
 struct MultiSeg {
   BinSeg s[6];
-  int64_t nblk;     // total blocks
+  int64_t nblk;     // blocks with work (the grid is rounded up to a multiple of kXcds)
 };
+constexpr int kXcds = 8;   // MI355X: eight accelerator complex dies, each with its own L2
 
 template <class P, class V>
 __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
@@ -832,11 +834,18 @@ __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
   __shared__ typename P::Score red[4];
   __shared__ int64_t hw[4];
   __shared__ uint32_t hl[4];
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin and every segment starts
+  // at a multiple of 8, so within a segment block p serves the (p % 8)-th eighth of the
+  // segment's units; units are in id (slice-major) order, so each XCD's L2 sees the labels
+  // and Sigma sub-tables of a few slices while every XCD gets an equal share of every bin
   const int64_t b = blockIdx.x;
   int k = 0;
   while (k < 5 && b >= ms.s[k + 1].blk0) k++;
   const BinSeg sg = ms.s[k];
-  const int64_t lb = b - sg.blk0;
+  const int64_t p = b - sg.blk0;
+  const int64_t per = (sg.nbk + kXcds - 1) / kXcds;
+  const int64_t lb = (p % kXcds) * per + p / kXcds;
+  if (lb >= sg.nbk) return;
   switch (k) {
     case 0:
       lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
@@ -908,16 +917,18 @@ __device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg,
   }
 }
 
+constexpr int kLatThreads = 1024;
+
 template <class V>
-__global__ __launch_bounds__(1024) void k_lm_lat(V g, SolveDev sd, LatSegs ls,
-                                                 const uint32_t *comm, SliceTable sig,
-                                                 uint32_t fresh_base, LmCounters pc) {
+__global__ __launch_bounds__(kLatThreads) void k_lm_lat(V g, SolveDev sd, LatSegs ls,
+                                                        const uint32_t *comm, SliceTable sig,
+                                                        uint32_t fresh_base, LmCounters pc) {
   __shared__ uint32_t sk[1 << kBlockLg];
   __shared__ int64_t sv[1 << kBlockLg];
-  __shared__ ScoreK redK[16];
-  __shared__ Score1 red1[16];
-  __shared__ int64_t hw[16];
-  __shared__ uint32_t hl[16];
+  __shared__ ScoreK redK[kLatThreads / 64];
+  __shared__ Score1 red1[kLatThreads / 64];
+  __shared__ int64_t hw[kLatThreads / 64];
+  __shared__ uint32_t hl[kLatThreads / 64];
   const int64_t b = blockIdx.x;
   int k = 0;
   while (k < 2 * kBinGtab - 1 && b >= ls.s[k + 1].blk0) k++;
@@ -1126,10 +1137,20 @@ __global__ void k_rebuild_check(const uint32_t *used, const uint32_t *limit, int
 // result equals the sequential greedy colouring in priority order.  Each unit counts its
 // higher-priority neighbours once; a round colours the ready frontier and releases the
 // lower-priority neighbours, so every row is scanned a constant number of times.
+// Frontier lists of a colouring round: units above kJpHeavy neighbours are coloured by a
+// whole block (their scans would hold a single wave for long), the others by one wave.
+constexpr int kJpHeavy = 512;
+struct JpLists {
+  int32_t *light[2];
+  int32_t *heavy[2];
+  uint32_t *counts;   // [0..2] light counters, [3..5] heavy counters (round r uses r % 3)
+};
+
 template <class V>
 __global__ __launch_bounds__(256) void k_jp_count(V g, SolveDev sd, const int32_t *work,
                                                   int64_t nwork, uint32_t *cnt, int32_t *front,
-                                                  uint32_t *nfront, int it, int lvl) {
+                                                  uint32_t *nfront, int32_t *hfront,
+                                                  uint32_t *nhfront, int it, int lvl) {
   // one thread per unit; ready units are appended once per wave
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool ready = false;
@@ -1151,37 +1172,21 @@ __global__ __launch_bounds__(256) void k_jp_count(V g, SolveDev sd, const int32_
     cnt[v] = c;
     ready = c == 0;
   }
-  wave_append(front, nfront, ready, (int32_t)v);
+  const bool heavy = idx < nwork && g.degree(v) > kJpHeavy;
+  wave_append(front, nfront, ready && !heavy, (int32_t)v);
+  wave_append(hfront, nhfront, ready && heavy, (int32_t)v);
 }
 
-// Colour one frontier unit (one wave) and release its lower-priority neighbours into next.
+// Release the lower-priority neighbours of v over entries [lo, hi) with stride `step`
+// starting at this thread's offset; the last release of a neighbour queues it for the next
+// round (light or heavy list by degree).  Every thread of the wave must call this.
 template <class V>
-__device__ inline void jp_unit(const V &g, const SolveDev &sd, int64_t v, int32_t *colour,
-                               uint32_t *cnt, int32_t *next, uint32_t *nnext, int it, int lvl) {
-  const int lane = threadIdx.x & 63;
-  const int j = g.usolve[v];
-  const uint64_t sm = sd.seedmix[j];
-  const int64_t off = sd.uoff[j];
-  const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
-  typename V::Row row = g.row(v, sd);
-  int result = -1;
-  for (int base = 0; result < 0; base += 64) {
-    uint64_t used = 0;
-    for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
-      int32_t x = g.col[e];
-      if (g.wt(row, e, x) == 0) continue;
-      uint64_t hx = priority(sm, it, lvl, 0, (uint32_t)(x - off));
-      if (!outranks(hx, (uint32_t)x, hv, (uint32_t)v)) continue;
-      int cx = colour[x];
-      if (cx >= base && cx < base + 64) used |= 1ull << (cx - base);
-    }
-    for (int m = 32; m >= 1; m >>= 1) used |= (uint64_t)shfl_xor64((int64_t)used, m);
-    if (~used) result = base + __builtin_ctzll(~used);
-  }
-  if (lane == 0) colour[v] = result;
-  // release the lower-priority neighbours; the last one to be released joins the next round
-  for (int64_t e0 = row.lo; e0 < row.hi; e0 += 64) {
-    int64_t e = e0 + lane;
+__device__ inline void jp_release(const V &g, const typename V::Row &row, int64_t first,
+                                  int step, int64_t v, uint64_t sm, int64_t off, uint64_t hv,
+                                  uint32_t *cnt, int32_t *nl, uint32_t *cl, int32_t *nh,
+                                  uint32_t *ch, int it, int lvl) {
+  for (int64_t e0 = row.lo; e0 < row.hi; e0 += step) {
+    const int64_t e = e0 + first;
     bool ready = false;
     int32_t x = 0;
     if (e < row.hi) {
@@ -1191,31 +1196,124 @@ __device__ inline void jp_unit(const V &g, const SolveDev &sd, int64_t v, int32_
         if (!outranks(hx, (uint32_t)x, hv, (uint32_t)v)) ready = atomicSub(cnt + x, 1u) == 1u;
       }
     }
-    uint64_t bal = __ballot(ready);
-    if (!bal) continue;
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(nnext, (uint32_t)__popcll(bal));
-    base = (uint32_t)__shfl((int)base, 0, 64);
-    if (ready) next[base + __popcll(bal & ((1ull << lane) - 1))] = x;
+    const bool heavy = ready && g.degree(x) > kJpHeavy;
+    wave_append(nl, cl, ready && !heavy, x);
+    wave_append(nh, ch, heavy, x);
   }
 }
 
-// One Jones-Plassmann round with its frontier size read on the device, so rounds can be
-// launched back to back without a host round trip: round r colours list[r&1] (count
-// counts[r%3]), appends the released units to list[(r+1)&1] (counts[(r+1)%3]) and clears the
-// counter of round r+2.  A round with an empty frontier does nothing.
+// Colours of the higher-priority neighbours of v are marked in an LDS bitmap of NW words
+// (atomic OR), a window of 64*NW colours at a time; the first clear bit is v's colour.
+// sync() orders the bitmap's clear, marks and reads among the threads that share it.
+template <int NW, class V, class Sync>
+__device__ inline int jp_first_free(const V &g, const typename V::Row &row, int first, int step,
+                                    int64_t v, uint64_t sm, int64_t off, uint64_t hv,
+                                    const int32_t *colour, int it, int lvl, uint64_t *bits,
+                                    Sync sync) {
+  const int lane = threadIdx.x & 63;
+  int result = -1;
+  for (int base = 0; result < 0; base += 64 * NW) {
+    for (int i = first; i < NW; i += step) bits[i] = 0;
+    sync();
+    for (int64_t e = row.lo + first; e < row.hi; e += step) {
+      const int32_t x = g.col[e];
+      if (g.wt(row, e, x) == 0) continue;
+      const uint64_t hx = priority(sm, it, lvl, 0, (uint32_t)(x - off));
+      if (!outranks(hx, (uint32_t)x, hv, (uint32_t)v)) continue;
+      const int d = colour[x] - base;
+      if (d >= 0 && d < 64 * NW) atomicOr((unsigned long long *)(bits + (d >> 6)), 1ull << (d & 63));
+    }
+    sync();
+    // every wave reads the bitmap and finds the same first clear bit
+    for (int w0 = 0; w0 < NW && result < 0; w0 += 64) {
+      const uint64_t word = w0 + lane < NW ? bits[w0 + lane] : ~0ull;
+      const uint64_t freew = __ballot(~word != 0);
+      if (freew) {
+        const int L = __builtin_ctzll(freew);
+        const uint64_t wl = (uint64_t)__shfl((long long)word, L, 64);
+        result = base + (w0 + L) * 64 + __builtin_ctzll(~wl);
+      }
+    }
+    sync();
+  }
+  return result;
+}
+
+struct WaveLdsSync {
+  // a wave's LDS operations complete in issue order; this only keeps the compiler from
+  // moving them across the phases
+  __device__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+};
+struct BlockLdsSync {
+  __device__ void operator()() const { __syncthreads(); }
+};
+
+// A light unit (at most kJpHeavy entries) has a colour of at most kJpHeavy, inside one
+// window of this many bitmap words.
+constexpr int kJpLightWords = (kJpHeavy + 64) / 64;
+constexpr int kJpBlockWords = 64;
+
+// Colour one light frontier unit with one wave.
 template <class V>
-__global__ __launch_bounds__(256) void k_jp_round(V g, SolveDev sd, int32_t *list0,
-                                                  int32_t *list1, uint32_t *counts,
-                                                  int32_t *colour, uint32_t *cnt, int r, int it,
-                                                  int lvl) {
-  const int64_t nf = counts[r % 3];
-  const int32_t *cur = (r & 1) ? list1 : list0;
-  int32_t *next = (r & 1) ? list0 : list1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) counts[(r + 2) % 3] = 0;
+__device__ inline void jp_unit(const V &g, const SolveDev &sd, int64_t v, int32_t *colour,
+                               uint32_t *cnt, int32_t *nl, uint32_t *cl, int32_t *nh,
+                               uint32_t *ch, int it, int lvl, uint64_t *bits) {
+  const int lane = threadIdx.x & 63;
+  const int j = g.usolve[v];
+  const uint64_t sm = sd.seedmix[j];
+  const int64_t off = sd.uoff[j];
+  const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+  typename V::Row row = g.row(v, sd);
+  const int result = jp_first_free<kJpLightWords>(g, row, lane, 64, v, sm, off, hv, colour, it,
+                                                  lvl, bits, WaveLdsSync());
+  if (lane == 0) colour[v] = result;
+  jp_release(g, row, lane, 64, v, sm, off, hv, cnt, nl, cl, nh, ch, it, lvl);
+}
+
+// Colour one heavy frontier unit with the whole block (all threads must call this).
+template <class V>
+__device__ inline void jp_unit_block(const V &g, const SolveDev &sd, int64_t v, int32_t *colour,
+                                     uint32_t *cnt, int32_t *nl, uint32_t *cl, int32_t *nh,
+                                     uint32_t *ch, int it, int lvl, uint64_t *bits) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int j = g.usolve[v];
+  const uint64_t sm = sd.seedmix[j];
+  const int64_t off = sd.uoff[j];
+  const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+  typename V::Row row = g.row(v, sd);
+  const int result = jp_first_free<kJpBlockWords>(g, row, tid, nt, v, sm, off, hv, colour, it,
+                                                  lvl, bits, BlockLdsSync());
+  if (tid == 0) colour[v] = result;
+  jp_release(g, row, tid, nt, v, sm, off, hv, cnt, nl, cl, nh, ch, it, lvl);
+}
+
+// One Jones-Plassmann round with its frontier sizes read on the device, so rounds can be
+// launched back to back without a host round trip: round r colours the lists of parity r&1
+// (sizes counts[r%3] and counts[3 + r%3]), appends the released units to the other lists
+// (counters (r+1)%3) and clears the counters of round r+2.  Waves take the light units,
+// then whole blocks take the heavy ones.  A round with empty frontiers does nothing.
+template <class V>
+__global__ __launch_bounds__(256) void k_jp_round(V g, SolveDev sd, JpLists L, int32_t *colour,
+                                                  uint32_t *cnt, int r, int it, int lvl) {
+  __shared__ uint64_t s_light[4][kJpLightWords];
+  __shared__ uint64_t s_block[kJpBlockWords];
+  const int64_t nf = L.counts[r % 3], nh = L.counts[3 + r % 3];
+  const int p = r & 1;
+  int32_t *nl = L.light[p ^ 1], *nhv = L.heavy[p ^ 1];
+  uint32_t *cl = L.counts + (r + 1) % 3, *ch = L.counts + 3 + (r + 1) % 3;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    L.counts[(r + 2) % 3] = 0;
+    L.counts[3 + (r + 2) % 3] = 0;
+  }
   for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nf;
        idx += (int64_t)gridDim.x * 4)
-    jp_unit(g, sd, (int64_t)cur[idx], colour, cnt, next, counts + (r + 1) % 3, it, lvl);
+    jp_unit(g, sd, (int64_t)L.light[p][idx], colour, cnt, nl, cl, nhv, ch, it, lvl,
+            s_light[threadIdx.x >> 6]);
+  for (int64_t idx = blockIdx.x; idx < nh; idx += gridDim.x)
+    jp_unit_block(g, sd, (int64_t)L.heavy[p][idx], colour, cnt, nl, cl, nhv, ch, it, lvl, s_block);
 }
 
 // sort key of a unit for batching: colour, then degree bin
@@ -1487,31 +1585,41 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
 }
 
 // ------------------------------------------------------------------ work-list segments
-// Up to three unit lists handled by one launch (one per group of degree bins).
+// Refinement work lists by degree: lane groups of 4, 8, 16 and 32 lanes (degree up to the
+// group size), waves, LDS blocks, global tables.
+constexpr int kRefLists = 7;
 struct Segs {
-  const int32_t *p[3];
-  int64_t pre[4];   // prefix sums of the segment lengths
+  const int32_t *p[kRefLists];
+  int64_t pre[kRefLists + 1];   // prefix sums of the segment lengths
+  __device__ int seg(int64_t i) const {
+    int k = 0;
+    while (k < kRefLists - 1 && i >= pre[k + 1]) k++;
+    return k;
+  }
   __device__ int64_t unit(int64_t i) const {
-    int k = i < pre[1] ? 0 : (i < pre[2] ? 1 : 2);
+    const int k = seg(i);
     return p[k][i - pre[k]];
   }
-  __device__ int seg(int64_t i) const { return i < pre[1] ? 0 : (i < pre[2] ? 1 : 2); }
+  __device__ int64_t total() const { return pre[kRefLists]; }
+};
+struct SegOut {
+  int32_t *p[kRefLists];
 };
 
 // keep the units whose flag is still set, segment by segment
-__global__ void k_compact_segs(Segs in, const uint8_t *flag, int32_t *o0, int32_t *o1, int32_t *o2,
-                               uint32_t *cnt) {
+__global__ void k_compact_segs(Segs in, const uint8_t *flag, SegOut out, uint32_t *cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = i < in.pre[3];
-  // a wave may straddle two segments: append segment by segment
-  for (int k = 0; k < 3; k++) {
+  const bool live = i < in.total();
+  const int ks = live ? in.seg(i) : -1;
+  // a wave may straddle segments: append segment by segment
+  for (int k = 0; k < kRefLists; k++) {
     bool keep = false;
     int32_t v = 0;
-    if (live && in.seg(i) == k) {
+    if (ks == k) {
       v = (int32_t)in.unit(i);
       keep = flag[v] != 0;
     }
-    wave_append(k == 0 ? o0 : (k == 1 ? o1 : o2), cnt + k, keep, v);
+    wave_append(out.p[k], cnt + k, keep, v);
   }
 }
 
@@ -1674,6 +1782,72 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
   }
 }
 
+// Proposals of units of degree <= G with G lanes each: neighbours inside the community are
+// merged by sub-community with shuffles, every leader evaluates its sub-community (well
+// connected, positive gain), and the group reduces to the best (ties to the lower label).
+template <class P, class V, int G>
+__global__ __launch_bounds__(256) void k_ref_group(V g, SolveDev sd, const int32_t *units,
+                                                   int64_t count, const uint32_t *comm,
+                                                   const uint32_t *R, const uint8_t *wcT,
+                                                   SliceTable sr, uint32_t *prop, uint32_t *propr,
+                                                   uint32_t stamp, int64_t *propw,
+                                                   uint8_t *active) {
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G - 1);
+  const int gbase = lane & ~(G - 1);
+  const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  if (idx >= count) return;   // whole groups leave together
+  const int64_t v = units[idx];
+  if (!active[v]) return;
+  const uint32_t D = comm[v];
+  typename V::Row row = g.row(v, sd);
+  const int64_t e = row.lo + gl;
+  uint32_t c = kNone;
+  int64_t w = 0;
+  if (e < row.hi) {
+    const int32_t x = g.col[e];
+    if (comm[x] == D) {
+      w = g.wt(row, e, x);
+      if (w != 0) c = R[x];
+    }
+  }
+  int64_t wsum = 0;
+  bool leader = c != kNone;
+  for (int j = 0; j < G; j++) {
+    const uint32_t cj = (uint32_t)__shfl((int)c, gbase + j, 64);
+    const int64_t wj = __shfl(w, gbase + j, 64);
+    if (cj == c) {
+      wsum += wj;
+      if (j < gl) leader = false;
+    }
+  }
+  const UnitCtx u = unit_ctx(g, sd, v, D);
+  const typename P::Score zero = P::make(g, u, sd, sr, kNone, 0, kEmpty);
+  typename P::Score best = zero;
+  if (leader && wcT[c]) {
+    typename P::Score s = P::make(g, u, sd, sr, c, wsum, kTarget);
+    if (P::cmp(g, u, sd, sr, s, zero) > 0) best = s;
+  }
+  for (int m = G / 2; m >= 1; m >>= 1) {
+    typename P::Score o = P::shfl(best, m);
+    if (better<P>(g, u, sd, sr, o, best)) best = o;
+  }
+  // the weight to the chosen sub-community sits with its leader
+  const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1)) << gbase;
+  const uint64_t bal = __ballot(leader && c == best.lab) & gmask;
+  const int src = bal ? __builtin_ctzll(bal) : gbase;
+  const int64_t wb = __shfl(wsum, src, 64);
+  if (gl == 0) {
+    if (best.lab == kNone) {
+      active[v] = 0;
+    } else {
+      prop[v] = best.lab;
+      propw[v] = wb;
+      propr[v] = stamp;
+    }
+  }
+}
+
 template <class P, class V>
 __global__ __launch_bounds__(256) void k_ref_prop_wave(V g, SolveDev sd, const int32_t *units,
                                                        int64_t count, const uint32_t *comm,
@@ -1747,7 +1921,7 @@ __global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, Segs seg
                                                       uint32_t *elig, int it, int lvl) {
   const int lane = threadIdx.x & 63;
   const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= segs.pre[3]) return;
+  if (idx >= segs.total()) return;
   const int64_t v = segs.unit(idx);
   if (propr[v] != stamp) return;
   const uint32_t T = prop[v];
@@ -1787,7 +1961,7 @@ __global__ __launch_bounds__(256) void k_ref_apply(V g, SolveDev sd, Segs segs, 
                                                    SliceTable sr) {
   const int lane = threadIdx.x & 63;
   const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= segs.pre[3]) return;
+  if (idx >= segs.total()) return;
   const int64_t v = segs.unit(idx);
   if (elig[v] != stamp) return;
   const uint32_t T = prop[v];
@@ -1828,7 +2002,7 @@ __global__ void k_ref_post(V g, Segs segs, const uint32_t *prop, const uint32_t 
   bool merged = false, first = false;
   int j = 0;
   uint32_t T = 0;
-  if (i < segs.pre[3]) {
+  if (i < segs.total()) {
     const int64_t v = segs.unit(i);
     if (elig[v] == stamp) {
       merged = true;
