@@ -167,6 +167,23 @@ __device__ inline void lds_add(uint32_t *K, int64_t *V, int lg, uint32_t label, 
   }
 }
 
+// As lds_add; the first insertion of a key also appends its slot to the list L (length *n),
+// so that scans visit the occupied slots only.
+__device__ inline void lds_add_listed(uint32_t *K, int64_t *V, int lg, uint32_t label, int64_t w,
+                                      uint16_t *L, int *n) {
+  const uint32_t key = label + 1, mask = (1u << lg) - 1;
+  uint32_t h = fib_hash(label, 32 - lg);
+  for (;;) {
+    uint32_t prev = atomicCAS(&K[h], 0u, key);
+    if (prev == 0 || prev == key) {
+      if (prev == 0) L[atomicAdd(n, 1)] = (uint16_t)h;
+      atomicAdd(reinterpret_cast<unsigned long long *>(&V[h]), (unsigned long long)w);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
 __device__ inline int64_t lds_get(const uint32_t *K, const int64_t *V, int lg, uint32_t label) {
   const uint32_t key = label + 1, mask = (1u << lg) - 1;
   uint32_t h = fib_hash(label, 32 - lg);

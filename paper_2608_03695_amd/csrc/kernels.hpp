@@ -351,13 +351,22 @@ __device__ inline typename P::Score wave_best(const V &g, const UnitCtx &u, cons
 }
 
 // ------------------------------------------------------------------ accumulation tables
+// LDS accumulation table with the list of its occupied slots (L holds at most the number of
+// distinct keys: the unit's degree bound for its bin, and never more than the table size).
 struct LdsTab {
   uint32_t *K;
   int64_t *V;
   int lg;
+  uint16_t *L;
+  int *n;
   __device__ int size() const { return 1 << lg; }
-  __device__ void add(uint32_t lab, int64_t w) const { lds_add(K, V, lg, lab, w); }
+  __device__ void add(uint32_t lab, int64_t w) const { lds_add_listed(K, V, lg, lab, w, L, n); }
   __device__ int64_t get(uint32_t lab) const { return lds_get(K, V, lg, lab); }
+  __device__ int count() const { return *(volatile int *)n; }
+  __device__ int slot(int i) const { return L[i]; }
+  __device__ void reset(int rank) const {
+    if (rank == 0) *n = 0;
+  }
 };
 struct GTab {
   uint32_t *K;
@@ -370,6 +379,9 @@ struct GTab {
   __device__ int64_t get(uint32_t lab) const {
     return gtab_get(K, V, (1u << lg) - 1, 32 - lg, lab);
   }
+  __device__ int count() const { return 1 << lg; }
+  __device__ int slot(int i) const { return i; }
+  __device__ void reset(int) const {}
 };
 
 // Group = the threads cooperating on one unit: one wave, or a whole block.
@@ -428,11 +440,13 @@ __device__ inline void group_heaviest(Grp grp, const Tab &tab, uint32_t skip, co
   const int r = grp.rank(), gsz = grp.size();
   W = -1;
   lab = kNone;
-  for (int i = r; i < tab.size(); i += gsz) {
-    uint32_t key = tab.K[i];
+  const int nc = tab.count();
+  for (int i = r; i < nc; i += gsz) {
+    const int h = tab.slot(i);
+    uint32_t key = tab.K[h];
     if (key == 0 || key - 1 == skip) continue;
     if (ok && !ok[key - 1]) continue;
-    int64_t w = tab.V[i];
+    int64_t w = tab.V[h];
     if (w > W || (w == W && key - 1 < lab)) {
       W = w;
       lab = key - 1;
@@ -571,11 +585,13 @@ __device__ inline uint32_t lm_unit_coop(Grp grp, Tab tab, const V &g, const Solv
     ncand = r == 0;
   }
   // subgroups take table slots in turn; every lane runs the same number of turns
-  for (int i0 = 0; i0 < tab.size(); i0 += nsub) {
+  const int nc = tab.count();
+  for (int i0 = 0; i0 < nc; i0 += nsub) {
     const int i = i0 + sub;
-    const uint32_t key = i < tab.size() ? tab.K[i] : 0u;
+    const int h = i < nc ? tab.slot(i) : 0;
+    const uint32_t key = i < nc ? tab.K[h] : 0u;
     if (key == 0 || key - 1 == u.D || key - 1 == hL) continue;
-    const int64_t W = tab.V[i];
+    const int64_t W = tab.V[h];
     if (P::prunable(u, W, best)) continue;
     ncand += c.j == 0;
     ScoreK s = coop_make(u, c, key - 1, W, kTarget);
@@ -608,6 +624,7 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
     tab.K[i] = 0;
     tab.V[i] = 0;
   }
+  tab.reset(r);
   grp.sync();
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
@@ -634,12 +651,14 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
     if (better<P>(g, u, sd, sig, s, best)) best = s;
     ncand = r == 0;
   }
-  for (int i = r; i < tab.size(); i += gsz) {
-    uint32_t key = tab.K[i];
+  const int nc = tab.count();
+  for (int i = r; i < nc; i += gsz) {
+    const int h = tab.slot(i);
+    uint32_t key = tab.K[h];
     if (key == 0 || key - 1 == D || key - 1 == hL) continue;
-    if (P::prunable(u, tab.V[i], best)) continue;
+    if (P::prunable(u, tab.V[h], best)) continue;
     ncand++;
-    typename P::Score s = P::make(g, u, sd, sig, key - 1, tab.V[i], kTarget);
+    typename P::Score s = P::make(g, u, sd, sig, key - 1, tab.V[h], kTarget);
     if (better<P>(g, u, sd, sig, s, best)) best = s;
   }
   if (pc.c) {
@@ -659,7 +678,7 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
 }
 
 constexpr int kWaveLg = 9;        // 512-slot LDS table per wave: units of degree <= 256
-constexpr int kBlockLg = 13;      // 8192-slot LDS table per 1024-thread block: degree <= 4096
+constexpr int kBlockLg = 13;      // 8192-slot LDS table per block: degree <= 4096
 constexpr int kSmallBlockLg = 11; // 2048-slot LDS table per 256-thread block: degree <= 1024
 constexpr int kWaveMaxDeg = 256;
 constexpr int kSmallBlockMaxDeg = 1024;
@@ -783,10 +802,12 @@ __global__ __launch_bounds__(256) void k_lm_wave(V g, SolveDev sd, const int32_t
                                                  uint32_t fresh_base, LmCounters pc) {
   __shared__ uint32_t sk[4][1 << kWaveLg];
   __shared__ int64_t sv[4][1 << kWaveLg];
+  __shared__ uint16_t sl[4][kWaveMaxDeg];
+  __shared__ int sn[4];
   const int wv = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * 4 + wv;
   if (idx >= count) return;
-  LdsTab tab{sk[wv], sv[wv], kWaveLg};
+  LdsTab tab{sk[wv], sv[wv], kWaveLg, sl[wv], sn + wv};
   uint32_t t = lm_unit<P>(WaveGrp(), tab, g, sd, units[idx], comm, sig, fresh_base,
                           (typename P::Score *)nullptr, pc);
   if ((threadIdx.x & 63) == 0) target[idx] = t;
@@ -799,10 +820,12 @@ __global__ __launch_bounds__(NT) void k_lm_block(V g, SolveDev sd, const int32_t
                                                  uint32_t fresh_base, LmCounters pc) {
   __shared__ uint32_t sk[1 << LG];
   __shared__ int64_t sv[1 << LG];
+  __shared__ uint16_t sl[1 << (LG - 1)];   // degree bound of the bin: half the table
+  __shared__ int sn;
   __shared__ typename P::Score red[NT / 64];
   __shared__ int64_t hw[NT / 64];
   __shared__ uint32_t hl[NT / 64];
-  LdsTab tab{sk, sv, LG};
+  LdsTab tab{sk, sv, LG, sl, &sn};
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, units[idx], comm, sig, fresh_base, red, pc,
                             hw, hl);
@@ -831,6 +854,8 @@ __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
                                                   uint32_t fresh_base, LmCounters pc) {
   __shared__ uint32_t sk[1 << kSmallBlockLg];        // 4 wave tables of 512, or one of 2048
   __shared__ int64_t sv[1 << kSmallBlockLg];
+  __shared__ uint16_t sl[kSmallBlockMaxDeg];         // 4 lists of 256, or one of 1024
+  __shared__ int sn[4];
   __shared__ typename P::Score red[4];
   __shared__ int64_t hw[4];
   __shared__ uint32_t hl[4];
@@ -865,14 +890,15 @@ __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
       const int wv = threadIdx.x >> 6;
       const int64_t idx = lb * 4 + wv;
       if (idx >= sg.count) return;
-      LdsTab tab{sk + (wv << kWaveLg), sv + (wv << kWaveLg), kWaveLg};
+      LdsTab tab{sk + (wv << kWaveLg), sv + (wv << kWaveLg), kWaveLg, sl + wv * kWaveMaxDeg,
+                 sn + wv};
       uint32_t t = lm_unit<P>(WaveGrp(), tab, g, sd, sg.units[idx], comm, sig, fresh_base,
                               (typename P::Score *)nullptr, pc);
       if ((threadIdx.x & 63) == 0) sg.target[idx] = t;
       break;
     }
     default: {
-      LdsTab tab{sk, sv, kSmallBlockLg};
+      LdsTab tab{sk, sv, kSmallBlockLg, sl, sn};
       uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, sg.units[lb], comm, sig, fresh_base, red,
                               pc, hw, hl);
       if (threadIdx.x == 0) sg.target[lb] = t;
@@ -881,8 +907,9 @@ __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
 }
 
 // Latency mode (aggregated levels, colour batches of few units): every bin below the hub bin
-// of both unit classes in one launch.  Occupancy does not matter here, so one 1024-thread
-// kernel carries both policies and an LDS table large enough for degree 4096.
+// of both unit classes in one launch.  Occupancy does not matter here, so one kernel carries
+// both policies and an LDS table large enough for degree 4096; its blocks have 512 threads,
+// which leaves the multi-slice policy the registers it needs without spilling.
 struct LatSegs {
   BinSeg s[2 * kBinGtab];   // class (single-slice, multi-slice) x bins 0..kBinGtab-1
 };
@@ -891,7 +918,8 @@ template <class P, class V>
 __device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg, int bin,
                                int64_t lb, const uint32_t *comm, const SliceTable &sig,
                                uint32_t fresh_base, LmCounters pc, uint32_t *sk, int64_t *sv,
-                               typename P::Score *red, int64_t *hw, uint32_t *hl) {
+                               uint16_t *sl, int *sn, typename P::Score *red, int64_t *hw,
+                               uint32_t *hl) {
   switch (bin) {
     case 0:
       lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
@@ -909,7 +937,7 @@ __device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg,
       break;
     default: {   // one unit per block; table sized by the bin's degree bound
       const int lg = bin <= 5 ? kSmallBlockLg : kBlockLg;
-      LdsTab tab{sk, sv, lg};
+      LdsTab tab{sk, sv, lg, sl, sn};
       uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, sg.units[lb], comm, sig, fresh_base, red,
                               pc, hw, hl);
       if (threadIdx.x == 0) sg.target[lb] = t;
@@ -917,7 +945,11 @@ __device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg,
   }
 }
 
-constexpr int kLatThreads = 1024;
+constexpr int kLatThreads = 512;
+// Block size of the 8192-slot table kernels: the multi-slice policy needs more than the 128
+// registers per lane that 1024-thread blocks allow
+template <class P>
+constexpr int kBlockThreads = std::is_same<P, PolicyK>::value ? 512 : 1024;
 
 template <class V>
 __global__ __launch_bounds__(kLatThreads) void k_lm_lat(V g, SolveDev sd, LatSegs ls,
@@ -925,6 +957,8 @@ __global__ __launch_bounds__(kLatThreads) void k_lm_lat(V g, SolveDev sd, LatSeg
                                                         uint32_t fresh_base, LmCounters pc) {
   __shared__ uint32_t sk[1 << kBlockLg];
   __shared__ int64_t sv[1 << kBlockLg];
+  __shared__ uint16_t sl[kBlockMaxDeg];
+  __shared__ int sn;
   __shared__ ScoreK redK[kLatThreads / 64];
   __shared__ Score1 red1[kLatThreads / 64];
   __shared__ int64_t hw[kLatThreads / 64];
@@ -936,9 +970,11 @@ __global__ __launch_bounds__(kLatThreads) void k_lm_lat(V g, SolveDev sd, LatSeg
   const int64_t lb = b - sg.blk0;
   const int bin = k % kBinGtab;
   if (k < kBinGtab)
-    lat_bin<PolicyK1>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, red1, hw, hl);
+    lat_bin<PolicyK1>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, red1, hw,
+                      hl);
   else
-    lat_bin<PolicyK>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, redK, hw, hl);
+    lat_bin<PolicyK>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, redK, hw,
+                     hl);
 }
 
 // Units of very high degree: a global-memory table per unit, slot offsets from a scan.
@@ -1399,6 +1435,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
     int lvl, int *ncol_out) {
   __shared__ uint32_t sk[kSmallWaves][1 << kWaveLg];
   __shared__ int64_t sv[kSmallWaves][1 << kWaveLg];
+  __shared__ uint16_t sl[kSmallWaves][kWaveMaxDeg];
+  __shared__ int sn[kSmallWaves];
   __shared__ uint32_t s_nf, s_nn;
   __shared__ int s_maxc, s_any, s_rb;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1501,7 +1539,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
   block_sync_global();
   if (!kSweeps) return;
   // ---- colour-batched sweeps
-  LdsTab ltab{sk[wv], sv[wv], kWaveLg};
+  LdsTab ltab{sk[wv], sv[wv], kWaveLg, sl[wv], sn + wv};
   const uint32_t gmask_lg = glg;
   for (int t = 0; t < ctl.smax; t++) {
     for (int j = tid; j < ctl.J; j += kSmallThreads) ctl.moved[j] = 0;
@@ -1737,6 +1775,7 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
     tab.K[i] = 0;
     tab.V[i] = 0;
   }
+  tab.reset(r);
   grp.sync();
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
@@ -1758,13 +1797,15 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
     typename P::Score s = P::make(g, u, sd, sr, hL, hW, kTarget);
     if (P::cmp(g, u, sd, sr, s, zero) > 0) best = s;
   }
-  for (int i = r; i < tab.size(); i += gsz) {
-    uint32_t key = tab.K[i];
+  const int nc = tab.count();
+  for (int i = r; i < nc; i += gsz) {
+    const int h = tab.slot(i);
+    uint32_t key = tab.K[h];
     if (key == 0) continue;
     uint32_t T = key - 1;
     if (T == hL || !wcT[T]) continue;
-    if (P::prunable(u, tab.V[i], best)) continue;
-    typename P::Score s = P::make(g, u, sd, sr, T, tab.V[i], kTarget);
+    if (P::prunable(u, tab.V[h], best)) continue;
+    typename P::Score s = P::make(g, u, sd, sr, T, tab.V[h], kTarget);
     if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
     if (better<P>(g, u, sd, sr, s, best)) best = s;
   }
@@ -1857,18 +1898,20 @@ __global__ __launch_bounds__(256) void k_ref_prop_wave(V g, SolveDev sd, const i
                                                        uint8_t *active) {
   __shared__ uint32_t sk[4][1 << kWaveLg];
   __shared__ int64_t sv[4][1 << kWaveLg];
+  __shared__ uint16_t sl[4][kWaveMaxDeg];
+  __shared__ int sn[4];
   const int wv = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * 4 + wv;
   if (idx >= count) return;
   const int64_t v = units[idx];
   if (!active[v]) return;
-  LdsTab tab{sk[wv], sv[wv], kWaveLg};
+  LdsTab tab{sk[wv], sv[wv], kWaveLg, sl[wv], sn + wv};
   ref_unit<P>(WaveGrp(), tab, g, sd, v, comm, R, wcT, sr, prop, propr, stamp, propw, active,
               (typename P::Score *)nullptr);
 }
 
-template <class P, class V>
-__global__ __launch_bounds__(1024) void k_ref_prop_block(V g, SolveDev sd, const int32_t *units,
+template <class P, class V, int NT>
+__global__ __launch_bounds__(NT) void k_ref_prop_block(V g, SolveDev sd, const int32_t *units,
                                                          int64_t count, const uint32_t *comm,
                                                          const uint32_t *R, const uint8_t *wcT,
                                                          SliceTable sr, uint32_t *prop,
@@ -1876,10 +1919,12 @@ __global__ __launch_bounds__(1024) void k_ref_prop_block(V g, SolveDev sd, const
                                                          int64_t *propw, uint8_t *active) {
   __shared__ uint32_t sk[1 << kBlockLg];
   __shared__ int64_t sv[1 << kBlockLg];
-  __shared__ typename P::Score red[16];
-  __shared__ int64_t hw[16];
-  __shared__ uint32_t hl[16];
-  LdsTab tab{sk, sv, kBlockLg};
+  __shared__ uint16_t sl[kBlockMaxDeg];
+  __shared__ int sn;
+  __shared__ typename P::Score red[NT / 64];
+  __shared__ int64_t hw[NT / 64];
+  __shared__ uint32_t hl[NT / 64];
+  LdsTab tab{sk, sv, kBlockLg, sl, &sn};
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int64_t v = units[idx];
     if (!active[v]) continue;
