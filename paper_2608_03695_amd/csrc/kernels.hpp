@@ -1427,6 +1427,7 @@ constexpr int kSmallThreads = 1024;
 
 constexpr int kSmallWaves = kSmallThreads / 64;
 
+constexpr int kSmallRowThread = 32;   // rows counted by a single thread in a small level
 template <class P, class V, bool kSweeps>
 __global__ __launch_bounds__(kSmallThreads) void k_small_level(
     V g, SolveDev sd, int64_t n, const int32_t *work, int64_t nwork, uint32_t *comm,
@@ -1437,6 +1438,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
   __shared__ int64_t sv[kSmallWaves][1 << kWaveLg];
   __shared__ uint16_t sl[kSmallWaves][kWaveMaxDeg];
   __shared__ int sn[kSmallWaves];
+  __shared__ uint64_t s_bits[kSmallWaves][kJpLightWords];
+  __shared__ int64_t s_part[kSmallThreads];
   __shared__ uint32_t s_nf, s_nn;
   __shared__ int s_maxc, s_any, s_rb;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1446,8 +1449,31 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
     s_maxc = -1;
   }
   __syncthreads();
+  // rows up to kSmallRowThread entries are counted by one thread, longer ones by a wave
+  for (int64_t i = wv; i < nwork; i += kSmallWaves) {
+    const int64_t v = work[i];
+    if (g.degree(v) <= kSmallRowThread) continue;
+    const int j = g.usolve[v];
+    const uint64_t sm = sd.seedmix[j];
+    const int64_t off = sd.uoff[j];
+    const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+    typename V::Row row = g.row(v, sd);
+    int64_t c = 0;
+    for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+      int32_t x = g.col[e];
+      if (g.wt(row, e, x) == 0) continue;
+      if (outranks(priority(sm, it, lvl, 0, (uint32_t)(x - off)), (uint32_t)x, hv, (uint32_t)v)) c++;
+    }
+    for (int m = 32; m >= 1; m >>= 1) c += shfl_xor64(c, m);
+    if (lane == 0) {
+      cnt[v] = (uint32_t)c;
+      colour[v] = -1;
+      if (c == 0) fa[atomicAdd(&s_nf, 1u)] = (int32_t)v;
+    }
+  }
   for (int64_t i = tid; i < nwork; i += kSmallThreads) {
     const int64_t v = work[i];
+    if (g.degree(v) > kSmallRowThread) continue;
     const int j = g.usolve[v];
     const uint64_t sm = sd.seedmix[j];
     const int64_t off = sd.uoff[j];
@@ -1477,20 +1503,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
       const int64_t off = sd.uoff[j];
       const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
       typename V::Row row = g.row(v, sd);
-      int result = -1;
-      for (int base = 0; result < 0; base += 64) {
-        uint64_t used = 0;
-        for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
-          int32_t x = g.col[e];
-          if (g.wt(row, e, x) == 0) continue;
-          if (!outranks(priority(sm, it, lvl, 0, (uint32_t)(x - off)), (uint32_t)x, hv, (uint32_t)v))
-            continue;
-          int cx = colour[x];
-          if (cx >= base && cx < base + 64) used |= 1ull << (cx - base);
-        }
-        for (int m = 32; m >= 1; m >>= 1) used |= (uint64_t)shfl_xor64((int64_t)used, m);
-        if (~used) result = base + __builtin_ctzll(~used);
-      }
+      const int result = jp_first_free<kJpLightWords>(g, row, lane, 64, v, sm, off, hv, colour,
+                                                      it, lvl, s_bits[wv], WaveLdsSync());
       if (lane == 0) {
         colour[v] = result;
         atomicMax(&s_maxc, result);
@@ -1523,10 +1537,29 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_level(
   for (int64_t i = tid; i < nwork; i += kSmallThreads)
     atomicAdd(reinterpret_cast<unsigned long long *>(start + key_of(work[i]) + 1), 1ull);
   block_sync_global();
-  if (tid == 0) {
-    for (int c = 0; c < nkey; c++) start[c + 1] += start[c];
-    *ncol_out = ncol;
+  // inclusive prefix sum of the key counts start[1..nkey]: contiguous chunks per thread, the
+  // chunk totals scanned in LDS
+  {
+    int64_t *a = start + 1;
+    const int64_t chunk = (nkey + kSmallThreads - 1) / kSmallThreads;
+    const int64_t c0 = (int64_t)tid * chunk, c1 = c0 + chunk < nkey ? c0 + chunk : nkey;
+    int64_t sum = 0;
+    for (int64_t c = c0; c < c1; c++) sum += a[c];
+    s_part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < kSmallThreads; o <<= 1) {
+      const int64_t t = tid >= o ? s_part[tid - o] : 0;
+      __syncthreads();
+      s_part[tid] += t;
+      __syncthreads();
+    }
+    int64_t run = tid ? s_part[tid - 1] : 0;
+    for (int64_t c = c0; c < c1; c++) {
+      run += a[c];
+      a[c] = run;
+    }
   }
+  if (tid == 0) *ncol_out = ncol;
   block_sync_global();
   // scatter: decisions inside a batch are independent and moves commute, so the order of
   // units inside a colour does not matter
