@@ -352,10 +352,10 @@ def main():
                    "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
         # the HBM-bound loop: level-0 local-moving decisions (every sweep of every iteration)
         "roofline": roofline(nbytes("lm0"), mean("lm0_kernel_ms"), results[0]["lm0_launches"],
-                             "k_lm_multi<Policy0, View0> (level-0 decisions)"),
-        "roofline_all_levels": roofline(nbytes("lm"), mean("lm_kernel_ms"),
-                                        results[0]["lm_launches"],
-                                        "local-moving decisions at every level"),
+                             "level-0 decision launches: k_lm_multi<Policy0, View0> (bins up "
+                             "to 1024 entries) and k_lm_block<Policy0, View0, 1024> (larger)"),
+        # the work of the aggregated levels' decisions (not timed: their launches are short)
+        "bytes_all_levels": nbytes("lm"),
         "phases_ms": {k: results[-1][k] for k in ("ms_colour", "ms_local_move", "ms_refine",
                                                   "ms_aggregate", "ms_finish")},
         "solve": {"Q": float(q), "n_communities": results[-1]["n_communities"],

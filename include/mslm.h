@@ -74,8 +74,9 @@ typedef struct {
   int32_t reserved0;
   uint64_t seed;
   uint32_t flags;                 /* MSLM_OUTPUT_ON_DEVICE: membership is a device pointer;
-                                     MSLM_PROFILE: time every local-moving decision kernel
-                                     with HIP events on the graph's stream;
+                                     MSLM_PROFILE: time every level-0 local-moving decision
+                                     launch with HIP events on the graph's stream (the short
+                                     launches of aggregated levels are left untimed);
                                      MSLM_COUNT: count the work of those kernels            */
   uint32_t reserved1;
 } mslm_params;
@@ -90,13 +91,13 @@ typedef struct {
   int64_t sweeps, moves, sweep_cap_hits, refine_rounds, merges, splits, exact_fallbacks;
   double ms_total;                /* host wall clock of the call                            */
   double ms_colour, ms_local_move, ms_refine, ms_aggregate, ms_finish;   /* device, by phase */
-  double lm_kernel_ms;            /* summed durations of the local-moving decision kernels,
-                                     measured only with MSLM_PROFILE                        */
-  int64_t lm_launches;            /* number of those kernel launches (MSLM_PROFILE)          */
+  double lm_kernel_ms;            /* summed durations of the timed decision launches
+                                     (MSLM_PROFILE: level 0 only, equal to lm0_kernel_ms)     */
+  int64_t lm_launches;            /* number of those launches (MSLM_PROFILE)                 */
   int64_t lm_units, lm_entries, lm_candidates;   /* work of those kernels: units decided,
                                      adjacency entries scanned, candidate communities (COUNT) */
   int64_t q_components[3 * 64 + 1];
-  double lm0_kernel_ms;           /* the level-0 share of lm_kernel_ms (MSLM_PROFILE)         */
+  double lm0_kernel_ms;           /* level-0 decision kernel time (MSLM_PROFILE)              */
   int64_t lm0_launches;           /* level-0 decision launches (MSLM_PROFILE)                 */
   int64_t lm0_units, lm0_entries, lm0_candidates;   /* level-0 share of the work (COUNT)   */
 } mslm_result;
