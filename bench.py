@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 from fractions import Fraction
@@ -77,6 +78,22 @@ def roofline(nbytes, ms, launches, kernel):
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
             "bytes_per_step": nbytes, "kernel_ms_per_step": ms, "launches_per_step": launches,
             "avg_launch_us": ms * 1e3 / max(launches, 1)}
+
+
+def device_copy_gbs(torch):
+    """Read+write bandwidth of a plain 1 GiB device-to-device copy, by HIP events."""
+    a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def kernel_sources_sha():
@@ -305,7 +322,11 @@ def main():
         raise SystemExit("no GPU visible")
     log(f"N={tg.n_nodes} T={tg.n_slices} E={tg.n_edges}; uploading")
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_c0 = time.perf_counter()
     g = mslm.Graph(tg, spec.omega, stream=stream)
+    torch.cuda.synchronize()
+    ms_create = (time.perf_counter() - t_c0) * 1000.0   # host upload + supra-CSR build
     info = g.info()
     m_supra = info["nnz"] // 2
     kw = dict(gamma=spec.gamma, max_levels=spec.max_levels, max_iterations=spec.max_iterations,
@@ -316,14 +337,18 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
+    step_ms = []
     for i in range(args.steps):
-        _, r = g.leiden(profile=True, **kw)
+        ts = time.perf_counter()
+        _, r = g.leiden(profile=True, **kw)   # synchronous: the membership is on the host
+        step_ms.append((time.perf_counter() - ts) * 1000.0)
         results.append(r)
         log(f"step {i} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log("timed steps done")
     ms_step = (t1 - t0) * 1000.0 / args.steps
+    copy_gbs = device_copy_gbs(torch)
     # the schedule is deterministic: one counting run gives the exact work of every step
     if args.no_count:
         rc = {k: 0 for k in ("lm_units", "lm_entries", "lm_candidates", "lm0_units",
@@ -356,6 +381,11 @@ def main():
                              "to 1024 entries) and k_lm_block<Policy0, View0, 1024> (larger)"),
         # the work of the aggregated levels' decisions (not timed: their launches are short)
         "bytes_all_levels": nbytes("lm"),
+        "ms_per_step_median": statistics.median(step_ms),
+        "ms_per_step_std": statistics.pstdev(step_ms),
+        # the graph's upload and supra-CSR build, paid once per graph (not in value)
+        "ms_create": ms_create,
+        "value_incl_create": m_supra / ((ms_step + ms_create) * 1e-3),
         "phases_ms": {k: results[-1][k] for k in ("ms_colour", "ms_local_move", "ms_refine",
                                                   "ms_aggregate", "ms_finish")},
         "solve": {"Q": float(q), "n_communities": results[-1]["n_communities"],
@@ -364,6 +394,8 @@ def main():
                   "exact_fallbacks": results[-1]["exact_fallbacks"]},
     }
     rl = out["roofline"]
+    rl["copy_gbs"] = copy_gbs                 # a plain device copy on this GPU, same clock
+    rl["frac_of_copy"] = rl["achieved"] / copy_gbs if copy_gbs else None
     t = measured_traffic(tg.name, rl["launches_per_step"])
     if t is not None:
         rl["traffic"] = t

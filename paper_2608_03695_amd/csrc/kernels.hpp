@@ -1182,16 +1182,23 @@ struct JpLists {
   uint32_t *counts;   // [0..2] light counters, [3..5] heavy counters (round r uses r % 3)
 };
 
+// Rows longer than kJpCountThread entries are counted by a wave (k_jp_count_wide) instead
+// of a single thread.
+constexpr int kJpCountThread = 64;
+
 template <class V>
 __global__ __launch_bounds__(256) void k_jp_count(V g, SolveDev sd, const int32_t *work,
                                                   int64_t nwork, uint32_t *cnt, int32_t *front,
                                                   uint32_t *nfront, int32_t *hfront,
-                                                  uint32_t *nhfront, int it, int lvl) {
+                                                  uint32_t *nhfront, int32_t *wide,
+                                                  uint32_t *nwide, int it, int lvl) {
   // one thread per unit; ready units are appended once per wave
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool ready = false;
   int64_t v = 0;
-  if (idx < nwork) {
+  const bool long_row = idx < nwork && g.degree(work[idx]) > kJpCountThread;
+  wave_append(wide, nwide, long_row, idx < nwork ? work[idx] : 0);
+  if (idx < nwork && !long_row) {
     v = work[idx];
     const int j = g.usolve[v];
     const uint64_t sm = sd.seedmix[j];
@@ -1208,9 +1215,42 @@ __global__ __launch_bounds__(256) void k_jp_count(V g, SolveDev sd, const int32_
     cnt[v] = c;
     ready = c == 0;
   }
-  const bool heavy = idx < nwork && g.degree(v) > kJpHeavy;
+  const bool heavy = ready && g.degree(v) > kJpHeavy;
   wave_append(front, nfront, ready && !heavy, (int32_t)v);
-  wave_append(hfront, nhfront, ready && heavy, (int32_t)v);
+  wave_append(hfront, nhfront, heavy, (int32_t)v);
+}
+
+// The long rows set aside by k_jp_count, one wave each; their number is read on the device.
+template <class V>
+__global__ __launch_bounds__(256) void k_jp_count_wide(V g, SolveDev sd, const int32_t *wide,
+                                                       const uint32_t *nwide, uint32_t *cnt,
+                                                       int32_t *front, uint32_t *nfront,
+                                                       int32_t *hfront, uint32_t *nhfront, int it,
+                                                       int lvl) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = *nwide;
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nw;
+       idx += (int64_t)gridDim.x * 4) {
+    const int64_t v = wide[idx];
+    const int j = g.usolve[v];
+    const uint64_t sm = sd.seedmix[j];
+    const int64_t off = sd.uoff[j];
+    const uint64_t hv = priority(sm, it, lvl, 0, (uint32_t)(v - off));
+    typename V::Row row = g.row(v, sd);
+    int64_t c = 0;
+    for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+      int32_t x = g.col[e];
+      if (g.wt(row, e, x) == 0) continue;
+      uint64_t hx = priority(sm, it, lvl, 0, (uint32_t)(x - off));
+      if (outranks(hx, (uint32_t)x, hv, (uint32_t)v)) c++;
+    }
+    for (int m = 32; m >= 1; m >>= 1) c += shfl_xor64(c, m);
+    if (lane == 0) cnt[v] = (uint32_t)c;
+    const bool ready = lane == 0 && c == 0;
+    const bool heavy = ready && g.degree(v) > kJpHeavy;
+    wave_append(front, nfront, ready && !heavy, (int32_t)v);
+    wave_append(hfront, nhfront, heavy, (int32_t)v);
+  }
 }
 
 // Release the lower-priority neighbours of v over entries [lo, hi) with stride `step`
