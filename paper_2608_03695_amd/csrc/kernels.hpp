@@ -1014,20 +1014,63 @@ __global__ __launch_bounds__(256) void k_hub_clear(const int32_t *units, const i
   }
 }
 
+// A hub's entries mostly fall into few communities, so adding each one to the global table
+// would queue thousands of atomics on the same words: each block first sums its share of the
+// entries in an LDS table of at most kHubLdsKeys keys (entries of further keys go straight to
+// the global table), then adds each LDS key's sum to the global table once.
+constexpr int kHubLdsLg = 11;
+constexpr int kHubLdsKeys = 1 << (kHubLdsLg - 1);
+
 template <class V>
 __global__ __launch_bounds__(256) void k_hub_accum(V g, SolveDev sd, const int32_t *units,
                                                    const uint32_t *comm, const int64_t *goff,
                                                    const int32_t *glg, uint32_t *gk, int64_t *gv,
                                                    LmCounters pc) {
+  __shared__ uint32_t sk[1 << kHubLdsLg];
+  __shared__ int64_t sv[1 << kHubLdsLg];
+  __shared__ int s_claimed;
   const int64_t v = units[blockIdx.y];
   GTab tab{gk + goff[v], gv + goff[v], glg[v]};
   typename V::Row row = g.row(v, sd);
+  for (int i = threadIdx.x; i < (1 << kHubLdsLg); i += blockDim.x) {
+    sk[i] = 0;
+    sv[i] = 0;
+  }
+  if (threadIdx.x == 0) s_claimed = 0;
+  __syncthreads();
+  constexpr uint32_t mask = (1u << kHubLdsLg) - 1;
   for (int64_t e = row.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < row.hi;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t x = g.col[e];
     const int64_t w = g.wt(row, e, x);
-    if (w != 0) tab.add(comm[x], w);
+    if (w == 0) continue;
+    const uint32_t lab = comm[x], key = lab + 1;
+    uint32_t h = fib_hash(lab, 32 - kHubLdsLg);
+    bool done = false;
+    // at most kHubLdsKeys slots are ever claimed, so an empty slot is always reached
+    for (;;) {
+      const uint32_t k = sk[h];
+      if (k == key) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&sv[h]), (unsigned long long)w);
+        done = true;
+        break;
+      }
+      if (k == 0) {
+        if (atomicAdd(&s_claimed, 1) >= kHubLdsKeys) break;   // LDS table closed to new keys
+        const uint32_t prev = atomicCAS(&sk[h], 0u, key);
+        if (prev == 0 || prev == key) {
+          atomicAdd(reinterpret_cast<unsigned long long *>(&sv[h]), (unsigned long long)w);
+          done = true;
+          break;
+        }
+      }
+      h = (h + 1) & mask;
+    }
+    if (!done) tab.add(lab, w);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (1 << kHubLdsLg); i += blockDim.x)
+    if (sk[i] != 0) tab.add(sk[i] - 1, sv[i]);
   if (pc.c && blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd(pc.c + 0, 1ull);
     atomicAdd(pc.c + 1, (unsigned long long)(row.hi - row.lo));
