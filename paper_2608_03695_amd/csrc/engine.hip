@@ -82,6 +82,7 @@ struct Workspace {
   Buf b_src, b_dst, b_w, b_off, b_twom;   // graph build inputs and per-slice sums
   Buf hubpart;                            // per-block best candidates of hub units
   Buf jph0, jph1;                         // heavy frontier lists of the colouring
+  Buf sig_count;                          // profile entries per slice of a level
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };

@@ -700,12 +700,14 @@ __host__ __device__ inline uint32_t degree_bin(int64_t d) {
 }
 // Bin of a unit of degree d in m slices: by degree; a unit in kCoopMinM or more slices is
 // evaluated cooperatively by a wave, or by a block when its (candidate x slice) work exceeds
-// 64 turns of a wave.  A bin never receives a degree above its table's capacity
-// (bin_fits checks that on the host before the first solve).
+// 64 turns of a wave, and by the hub path (kHubBlocks blocks) when it exceeds 64 turns of a
+// 512-thread block.  A bin never receives a degree above its table's capacity (bin_fits
+// checks that on the host before the first solve).
+constexpr int64_t kHubWork = 512 * 64;
 __host__ __device__ inline uint32_t bin_of(int64_t d, int m) {
   if (m < kCoopMinM) return degree_bin(d);
   const int64_t work = d * coop_width(m);
-  if (d > kBlockMaxDeg) return 7u;
+  if (d > kBlockMaxDeg || work > kHubWork) return 7u;
   if (d <= kWaveMaxDeg && work <= 64 * 64) return 4u;
   if (d <= kSmallBlockMaxDeg && work <= 256 * 64) return 5u;
   return 6u;
@@ -1190,6 +1192,26 @@ __global__ void k_lm_apply(V g, const int32_t *units, int64_t count, const uint3
     }
   }
   wave_count(moved, j, mv);
+}
+
+// Profile entries per global slice (how many units of a level can hold a key in the slice's
+// Sigma sub-table): an LDS histogram per block when the slices fit, else global atomics.
+constexpr int kSliceHistMax = 4096;
+__global__ void k_profile_slice_count(const int32_t *ps, int64_t ne, int nslices, int64_t *cnt) {
+  __shared__ uint32_t h[kSliceHistMax];
+  const bool lds = nslices <= kSliceHistMax;
+  if (lds)
+    for (int i = threadIdx.x; i < nslices; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (lds) atomicAdd(&h[ps[i]], 1u);
+    else atomicAdd(reinterpret_cast<unsigned long long *>(cnt + ps[i]), 1ull);
+  }
+  __syncthreads();
+  if (lds)
+    for (int i = threadIdx.x; i < nslices; i += blockDim.x)
+      if (h[i]) atomicAdd(reinterpret_cast<unsigned long long *>(cnt + i), (unsigned long long)h[i]);
 }
 
 template <class V>
@@ -1909,21 +1931,50 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
   int64_t hW;
   uint32_t hL;
   group_heaviest(grp, tab, kNone, wcT, hW, hL, sredW, sredL);
-  if (hL != kNone) {
-    typename P::Score s = P::make(g, u, sd, sr, hL, hW, kTarget);
-    if (P::cmp(g, u, sd, sr, s, zero) > 0) best = s;
-  }
-  const int nc = tab.count();
-  for (int i = r; i < nc; i += gsz) {
-    const int h = tab.slot(i);
-    uint32_t key = tab.K[h];
-    if (key == 0) continue;
-    uint32_t T = key - 1;
-    if (T == hL || !wcT[T]) continue;
-    if (P::prunable(u, tab.V[h], best)) continue;
-    typename P::Score s = P::make(g, u, sd, sr, T, tab.V[h], kTarget);
-    if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
-    if (better<P>(g, u, sd, sr, s, best)) best = s;
+  bool coop = false;
+  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) coop = u.m >= kCoopMinM;
+  if (coop) {
+    if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) {
+      // one profile slice per lane, subgroups take the sub-communities in turn (every lane of
+      // a subgroup runs the same turns)
+      const CoopLane c = coop_lane(g, u, sd, sr, r);
+      const int sub = r / c.mp, nsub = gsz / c.mp;
+      if (hL != kNone) {
+        ScoreK s = coop_make(u, c, hL, hW, kTarget);
+        if (P::cmp(g, u, sd, sr, s, zero) > 0) best = s;
+      }
+      const int nc = tab.count();
+      for (int i0 = 0; i0 < nc; i0 += nsub) {
+        const int i = i0 + sub;
+        const int h = i < nc ? tab.slot(i) : 0;
+        const uint32_t key = i < nc ? tab.K[h] : 0u;
+        if (key == 0) continue;
+        const uint32_t T = key - 1;
+        if (T == hL || !wcT[T]) continue;
+        const int64_t W = tab.V[h];
+        if (P::prunable(u, W, best)) continue;
+        ScoreK s = coop_make(u, c, T, W, kTarget);
+        if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
+        if (better<P>(g, u, sd, sr, s, best)) best = s;
+      }
+    }
+  } else {
+    if (hL != kNone) {
+      typename P::Score s = P::make(g, u, sd, sr, hL, hW, kTarget);
+      if (P::cmp(g, u, sd, sr, s, zero) > 0) best = s;
+    }
+    const int nc = tab.count();
+    for (int i = r; i < nc; i += gsz) {
+      const int h = tab.slot(i);
+      uint32_t key = tab.K[h];
+      if (key == 0) continue;
+      uint32_t T = key - 1;
+      if (T == hL || !wcT[T]) continue;
+      if (P::prunable(u, tab.V[h], best)) continue;
+      typename P::Score s = P::make(g, u, sd, sr, T, tab.V[h], kTarget);
+      if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
+      if (better<P>(g, u, sd, sr, s, best)) best = s;
+    }
   }
   best = group_best<P>(grp, g, u, sd, sr, best, red);
   int64_t w = best.lab == kNone ? 0 : tab.get(best.lab);
