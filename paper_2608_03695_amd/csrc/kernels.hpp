@@ -236,6 +236,9 @@ struct PolicyK {
         val = val * u.S0 - (i128)u.pb * (i128)(u.k0 * y);
       }
       s.ex = val;
+    } else if (kind == kEmpty) {
+      // every null term of the empty community is 0: the value is q*W, no slice to visit
+      finish(u, W, 0.0, 0.0, s);
     } else {
       double acc = 0.0, mag = 0.0;
       for (int jj = 0; jj < u.m; jj++) {
@@ -522,9 +525,40 @@ __device__ inline CoopLane coop_lane(const V &g, const UnitCtx &u, const SolveDe
   return c;
 }
 
-// Score of one target, identical on every lane of the subgroup.
-__device__ inline ScoreK coop_make(const UnitCtx &u, const CoopLane &c, uint32_t lab, int64_t W,
-                                   int kind) {
+// This lane's slice Sigma of U targets (the raw table value, 0 when absent or when the lane
+// holds no slice); the U first probes are issued together so that their latencies overlap.
+template <int U>
+__device__ inline void coop_lookup(const CoopLane &c, const uint32_t *lab, const bool *ok,
+                                   int64_t *y) {
+  uint64_t e[U];
+  uint32_t h[U];
+  for (int k = 0; k < U; k++) {
+    const bool on = c.valid && ok[k];
+    h[k] = on ? fib_hash(lab[k], c.shift) : 0u;
+    e[k] = on ? c.sub[h[k]] : 0ull;
+  }
+  for (int k = 0; k < U; k++) {
+    int64_t yy = 0;
+    if (c.valid && ok[k]) {
+      const uint32_t key = lab[k] + 1;
+      for (;;) {
+        const uint32_t kk = (uint32_t)e[k];
+        if (kk == key) {
+          yy = (int32_t)(e[k] >> 32);
+          break;
+        }
+        if (kk == 0) break;
+        h[k] = (h[k] + 1) & c.mask;
+        e[k] = c.sub[h[k]];
+      }
+    }
+    y[k] = yy;
+  }
+}
+
+// Score of one target from this lane's Sigma y of it, identical on every lane of the subgroup.
+__device__ inline ScoreK coop_score(const UnitCtx &u, const CoopLane &c, uint32_t lab, int64_t W,
+                                    int64_t y, int kind) {
   ScoreK s;
   s.lab = kind == kEmpty ? kNone : lab;
   s.kind = kind;
@@ -532,19 +566,6 @@ __device__ inline ScoreK coop_make(const UnitCtx &u, const CoopLane &c, uint32_t
   s.ex = 0;
   double t = 0.0;
   if (c.valid && kind != kEmpty) {
-    const uint32_t key = lab + 1;
-    uint32_t h = fib_hash(lab, c.shift);
-    int64_t y = 0;
-    for (;;) {
-      const uint64_t e = c.sub[h];
-      const uint32_t kk = (uint32_t)e;
-      if (kk == key) {
-        y = (int32_t)(e >> 32);
-        break;
-      }
-      if (kk == 0) break;
-      h = (h + 1) & c.mask;
-    }
     if (kind == kStay) y -= c.k;
     t = (double)(c.k * y) / c.S;
   }
@@ -558,6 +579,17 @@ __device__ inline ScoreK coop_make(const UnitCtx &u, const CoopLane &c, uint32_t
   PolicyK::finish(u, W, acc, mag, s);
   return s;
 }
+
+__device__ inline ScoreK coop_make(const UnitCtx &u, const CoopLane &c, uint32_t lab, int64_t W,
+                                   int kind) {
+  const bool ok = kind != kEmpty;
+  int64_t y = 0;
+  coop_lookup<1>(c, &lab, &ok, &y);
+  return coop_score(u, c, lab, W, y, kind);
+}
+
+// Candidates evaluated per subgroup turn (their Sigma lookups in flight together).
+constexpr int kCoopBatch = 4;
 
 // ------------------------------------------------------------------ local moving
 // One unit: accumulate neighbour-community weights in the table, evaluate every candidate
@@ -584,18 +616,28 @@ __device__ inline uint32_t lm_unit_coop(Grp grp, Tab tab, const V &g, const Solv
     if (better<P>(g, u, sd, sig, s, best)) best = s;
     ncand = r == 0;
   }
-  // subgroups take table slots in turn; every lane runs the same number of turns
+  // subgroups take table slots kCoopBatch at a time; every lane runs the same turns
   const int nc = tab.count();
-  for (int i0 = 0; i0 < nc; i0 += nsub) {
-    const int i = i0 + sub;
-    const int h = i < nc ? tab.slot(i) : 0;
-    const uint32_t key = i < nc ? tab.K[h] : 0u;
-    if (key == 0 || key - 1 == u.D || key - 1 == hL) continue;
-    const int64_t W = tab.V[h];
-    if (P::prunable(u, W, best)) continue;
-    ncand += c.j == 0;
-    ScoreK s = coop_make(u, c, key - 1, W, kTarget);
-    if (better<P>(g, u, sd, sig, s, best)) best = s;
+  for (int i0 = 0; i0 < nc; i0 += nsub * kCoopBatch) {
+    uint32_t lab[kCoopBatch];
+    int64_t W[kCoopBatch], y[kCoopBatch];
+    bool ok[kCoopBatch];
+    for (int k = 0; k < kCoopBatch; k++) {
+      const int i = i0 + k * nsub + sub;
+      const int h = i < nc ? tab.slot(i) : 0;
+      const uint32_t key = i < nc ? tab.K[h] : 0u;
+      lab[k] = key - 1;
+      ok[k] = key != 0 && key - 1 != u.D && key - 1 != hL;
+      W[k] = ok[k] ? tab.V[h] : 0;
+      ok[k] = ok[k] && !P::prunable(u, W[k], best);
+    }
+    coop_lookup<kCoopBatch>(c, lab, ok, y);
+    for (int k = 0; k < kCoopBatch; k++) {
+      if (!ok[k]) continue;
+      ncand += c.j == 0;
+      ScoreK s = coop_score(u, c, lab[k], W[k], y[k], kTarget);
+      if (better<P>(g, u, sd, sig, s, best)) best = s;
+    }
   }
   if (pc.c) {
     if (ncand) atomicAdd(pc.c + 2, (unsigned long long)ncand);
@@ -700,14 +742,12 @@ __host__ __device__ inline uint32_t degree_bin(int64_t d) {
 }
 // Bin of a unit of degree d in m slices: by degree; a unit in kCoopMinM or more slices is
 // evaluated cooperatively by a wave, or by a block when its (candidate x slice) work exceeds
-// 64 turns of a wave, and by the hub path (kHubBlocks blocks) when it exceeds 64 turns of a
-// 512-thread block.  A bin never receives a degree above its table's capacity (bin_fits
-// checks that on the host before the first solve).
-constexpr int64_t kHubWork = 512 * 64;
+// 64 turns of a wave.  A bin never receives a degree above its table's capacity
+// (bin_fits checks that on the host before the first solve).
 __host__ __device__ inline uint32_t bin_of(int64_t d, int m) {
   if (m < kCoopMinM) return degree_bin(d);
   const int64_t work = d * coop_width(m);
-  if (d > kBlockMaxDeg || work > kHubWork) return 7u;
+  if (d > kBlockMaxDeg) return 7u;
   if (d <= kWaveMaxDeg && work <= 64 * 64) return 4u;
   if (d <= kSmallBlockMaxDeg && work <= 256 * 64) return 5u;
   return 6u;
@@ -1102,15 +1142,25 @@ __global__ __launch_bounds__(256) void k_hub_eval(V g, SolveDev sd, const int32_
     if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) {
       const CoopLane c = coop_lane(g, u, sd, sig, threadIdx.x);
       const int sub = threadIdx.x / c.mp, nsub = blockDim.x / c.mp;
-      for (int64_t i0 = s0; i0 < s1; i0 += nsub) {
-        const int64_t i = i0 + sub;
-        const uint32_t key = i < s1 ? K[i] : 0u;
-        if (key == 0 || key - 1 == D) continue;
-        const int64_t W = Wt[i];
-        if (P::prunable(u, W, best)) continue;
-        ncand += c.j == 0;
-        ScoreK sc = coop_make(u, c, key - 1, W, kTarget);
-        if (better<P>(g, u, sd, sig, sc, best)) best = sc;
+      for (int64_t i0 = s0; i0 < s1; i0 += (int64_t)nsub * kCoopBatch) {
+        uint32_t lab[kCoopBatch];
+        int64_t W[kCoopBatch], y[kCoopBatch];
+        bool ok[kCoopBatch];
+        for (int k = 0; k < kCoopBatch; k++) {
+          const int64_t i = i0 + (int64_t)k * nsub + sub;
+          const uint32_t key = i < s1 ? K[i] : 0u;
+          lab[k] = key - 1;
+          ok[k] = key != 0 && key - 1 != D;
+          W[k] = ok[k] ? Wt[i] : 0;
+          ok[k] = ok[k] && !P::prunable(u, W[k], best);
+        }
+        coop_lookup<kCoopBatch>(c, lab, ok, y);
+        for (int k = 0; k < kCoopBatch; k++) {
+          if (!ok[k]) continue;
+          ncand += c.j == 0;
+          ScoreK sc = coop_score(u, c, lab[k], W[k], y[k], kTarget);
+          if (better<P>(g, u, sd, sig, sc, best)) best = sc;
+        }
       }
     }
   } else {
@@ -1841,9 +1891,11 @@ __global__ __launch_bounds__(256) void k_ref_init(V g, SolveDev sd, int64_t n, c
 // Well-connectedness of sub-community T within its community K:
 //   q*ext(T) - p*b * sum_s x_s (K_s - x_s) / S_s >= 0,  x_s = Sigma_R(T, s), K_s = Sigma(K, s).
 template <class V>
-__global__ void k_ref_wc(V g, SolveDev sd, const int32_t *list, int64_t count, const uint32_t *comm,
-                         const int64_t *ext, const uint64_t *mask, SliceTable sr, SliceTable sig,
-                         uint8_t *wcT, uint8_t *active, uint32_t *changed) {
+__global__ __launch_bounds__(256) void k_ref_wc(V g, SolveDev sd, const int32_t *list,
+                                                int64_t count, const uint32_t *comm,
+                                                const int64_t *ext, const uint64_t *mask,
+                                                SliceTable sr, SliceTable sig, uint8_t *wcT,
+                                                uint8_t *active, uint32_t *changed) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const int64_t T = list ? list[i] : i;
@@ -1944,18 +1996,26 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
         if (P::cmp(g, u, sd, sr, s, zero) > 0) best = s;
       }
       const int nc = tab.count();
-      for (int i0 = 0; i0 < nc; i0 += nsub) {
-        const int i = i0 + sub;
-        const int h = i < nc ? tab.slot(i) : 0;
-        const uint32_t key = i < nc ? tab.K[h] : 0u;
-        if (key == 0) continue;
-        const uint32_t T = key - 1;
-        if (T == hL || !wcT[T]) continue;
-        const int64_t W = tab.V[h];
-        if (P::prunable(u, W, best)) continue;
-        ScoreK s = coop_make(u, c, T, W, kTarget);
-        if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
-        if (better<P>(g, u, sd, sr, s, best)) best = s;
+      for (int i0 = 0; i0 < nc; i0 += nsub * kCoopBatch) {
+        uint32_t lab[kCoopBatch];
+        int64_t W[kCoopBatch], y[kCoopBatch];
+        bool ok[kCoopBatch];
+        for (int k = 0; k < kCoopBatch; k++) {
+          const int i = i0 + k * nsub + sub;
+          const int h = i < nc ? tab.slot(i) : 0;
+          const uint32_t key = i < nc ? tab.K[h] : 0u;
+          lab[k] = key - 1;
+          ok[k] = key != 0 && key - 1 != hL && wcT[key - 1];
+          W[k] = ok[k] ? tab.V[h] : 0;
+          ok[k] = ok[k] && !P::prunable(u, W[k], best);
+        }
+        coop_lookup<kCoopBatch>(c, lab, ok, y);
+        for (int k = 0; k < kCoopBatch; k++) {
+          if (!ok[k]) continue;
+          ScoreK s = coop_score(u, c, lab[k], W[k], y[k], kTarget);
+          if (P::cmp(g, u, sd, sr, s, zero) <= 0) continue;
+          if (better<P>(g, u, sd, sr, s, best)) best = s;
+        }
       }
     }
   } else {
