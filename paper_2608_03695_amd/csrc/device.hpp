@@ -253,70 +253,66 @@ __device__ inline void big_mul_u32(Big &x, uint32_t m) {
     c = t >> 32;
   }
 }
-__device__ inline void big_add(Big &x, const Big &y) {
-  uint64_t c = 0;
-  for (int i = 0; i < kLimbs; i++) {
-    uint64_t t = (uint64_t)x.d[i] + y.d[i] + c;
+// x += y * m  (or x -= y * m when neg), m < 2^32, y read as kLimbs - shift unsigned limbs
+// placed shift limbs up; in place, modulo 2^2304
+__device__ inline void big_addmul_u32(Big &x, const Big &y, uint32_t m, int shift, bool neg) {
+  uint64_t pc = 0;   // carry of the product stream
+  int64_t ac = 0;    // carry or borrow of the sum, -1..1
+  for (int i = shift; i < kLimbs; i++) {
+    const uint64_t p = (uint64_t)y.d[i - shift] * m + pc;
+    pc = p >> 32;
+    const int64_t pl = (int64_t)(uint32_t)p;
+    const int64_t t = (int64_t)x.d[i] + (neg ? -pl : pl) + ac;
     x.d[i] = (uint32_t)t;
-    c = t >> 32;
+    ac = t >> 32;
   }
-}
-__device__ inline void big_neg(Big &x) {
-  uint64_t c = 1;
-  for (int i = 0; i < kLimbs; i++) {
-    uint64_t t = (uint64_t)(~x.d[i]) + c;
-    x.d[i] = (uint32_t)t;
-    c = t >> 32;
-  }
-}
-// x *= m for any int64 m (the product is taken modulo 2^2304; callers stay in range)
-__device__ inline void big_mul_i64(Big &x, int64_t m) {
-  bool neg = m < 0;
-  uint64_t u = neg ? (uint64_t)0 - (uint64_t)m : (uint64_t)m;
-  Big hi = x;
-  big_mul_u32(x, (uint32_t)u);
-  big_mul_u32(hi, (uint32_t)(u >> 32));
-  // x += hi << 32
-  uint64_t c = 0;
-  for (int i = 1; i < kLimbs; i++) {
-    uint64_t t = (uint64_t)x.d[i] + hi.d[i - 1] + c;
-    x.d[i] = (uint32_t)t;
-    c = t >> 32;
-  }
-  if (neg) big_neg(x);
-}
-__device__ inline int big_sign(const Big &x) {
-  if (x.d[kLimbs - 1] >> 31) return -1;
-  for (int i = 0; i < kLimbs; i++)
-    if (x.d[i]) return 1;
-  return 0;
 }
 
 // Streaming evaluator of  q*Wd*Pi - pb*sum_j c_j/S_j * Pi  where Pi is the product of the
-// denominators of the terms fed in (terms with c_j == 0 are skipped entirely).
+// denominators of the terms fed in (terms with c_j == 0 are skipped entirely).  Only the
+// running numerator and Pi are stored; every update works in place, limb by limb.
 struct ExactAcc {
   Big num, den;
   __device__ void init() {
     big_set(num, 0);
     big_set(den, 1);
   }
+  // S in [1, 2^31) (a slice's 2m, or 1 for an empty slice)
   __device__ void term(int64_t c, int64_t S) {
     if (c == 0) return;
     // num/den + c/S = (num*S + c*den) / (den*S)
-    Big t = den;
-    big_mul_i64(t, c);
-    big_mul_i64(num, S);
-    big_add(num, t);
-    big_mul_i64(den, S);
+    big_mul_u32(num, (uint32_t)S);
+    const bool neg = c < 0;
+    const uint64_t a = neg ? (uint64_t)0 - (uint64_t)c : (uint64_t)c;
+    big_addmul_u32(num, den, (uint32_t)a, 0, neg);
+    if (a >> 32) big_addmul_u32(num, den, (uint32_t)(a >> 32), 1, neg);
+    big_mul_u32(den, (uint32_t)S);
   }
+  // sign of q*Wd*den - pb*num, produced limb by limb with a 128-bit carry (|q*Wd| < 2^95,
+  // 0 <= pb < 2^64): the low 2304 bits of the exact value, whose top bit is its sign
   __device__ int sign(int64_t q, int64_t Wd, int64_t pb) {
-    Big lhs = den;
-    big_mul_i64(lhs, q);
-    big_mul_i64(lhs, Wd);
-    big_mul_i64(num, pb);
-    big_neg(num);
-    big_add(lhs, num);
-    return big_sign(lhs);
+    const __int128 a = (__int128)q * Wd;
+    const bool aneg = a < 0;
+    const unsigned __int128 ua = aneg ? (unsigned __int128)0 - (unsigned __int128)a
+                                      : (unsigned __int128)a;
+    const uint64_t A0 = (uint32_t)ua, A1 = (uint32_t)(ua >> 32), A2 = (uint32_t)(ua >> 64);
+    const uint64_t B0 = (uint32_t)(uint64_t)pb, B1 = (uint32_t)((uint64_t)pb >> 32);
+    __int128 acc = 0;
+    uint32_t any = 0, top = 0;
+    for (int i = 0; i < kLimbs; i++) {
+      __int128 sa = (__int128)(den.d[i] * A0);
+      __int128 sb = (__int128)(num.d[i] * B0);
+      if (i >= 1) {
+        sa += (__int128)(den.d[i - 1] * A1);
+        sb += (__int128)(num.d[i - 1] * B1);
+      }
+      if (i >= 2) sa += (__int128)(den.d[i - 2] * A2);
+      acc += (aneg ? -sa : sa) - sb;
+      top = (uint32_t)acc;
+      any |= top;
+      acc >>= 32;
+    }
+    return (top >> 31) ? -1 : (any ? 1 : 0);
   }
 };
 

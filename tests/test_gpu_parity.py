@@ -133,3 +133,23 @@ def test_config2_full_size_matches_oracle_record():
     assert f"{q.numerator}/{q.denominator}" == exp["q"]
     for k in STAT_KEYS:
         assert r[k] == exp["stats"][k], k
+
+
+def test_exact_comparisons_match_oracle():
+    """The batched workload's graph 44 (N=214, T=26): its solves meet many pairs of targets
+    whose double estimates cannot be told apart, settled by the 2304-bit evaluation.  The
+    exact path must run, and every result must equal the oracle's."""
+    import oracle
+    mslm = _mslm()
+    tg = gen.batch_graph(44)
+    g = mslm.Graph(tg, 1)
+    for gamma, omega in ((F(1, 2), F(1)), (F(1), F(1)), (F(1, 2), F(10))):
+        m, r = g.leiden(gamma, omega)
+        om, oc, ost = oracle.OracleGraph(tg, omega).leiden(gamma, max_levels=32,
+                                                           max_iterations=2, seed=0)
+        assert r["exact_fallbacks"] > 0, (gamma, omega)
+        assert np.array_equal(m, om), (gamma, omega)
+        assert np.array_equal(r["q_components"], oc), (gamma, omega)
+        for k in STAT_KEYS:
+            assert r[k] == ost[k], (gamma, omega, k)
+    g.close()
