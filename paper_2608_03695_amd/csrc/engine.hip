@@ -83,6 +83,7 @@ struct Workspace {
   Buf hubpart;                            // per-block best candidates of hub units
   Buf jph0, jph1;                         // heavy frontier lists of the colouring
   Buf sig_count;                          // profile entries per slice of a level
+  Buf comm_snap;                          // labels at the start of a sweep (for a redo)
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };

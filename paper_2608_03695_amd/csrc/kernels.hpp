@@ -217,7 +217,28 @@ __device__ inline int exact_cmp(const V &g, const UnitCtx &u, const SolveDev &sd
   return exact_big(g, u, sd, tab, la, ka, Wa, lb, kb, Wb);
 }
 
-struct PolicyK {
+// The same order for the sweeps that run without the big-integer path (it needs per-lane
+// scratch memory, which slows every launch of a kernel that contains it): equal per-slice
+// terms are settled here as well; a genuine near-tie raises the solve's redo flag and gets a
+// provisional answer, and the host takes the whole sweep again with the exact kernels.
+template <class V>
+__device__ inline int exact_cmp_flag(const V &g, const UnitCtx &u, const SolveDev &sd,
+                                     const SliceTable &tab, uint32_t la, int ka, int64_t Wa,
+                                     uint32_t lb, int kb, int64_t Wb) {
+  bool same = true;
+  for (int jj = 0; jj < u.m && same; jj++) {
+    int gs;
+    int64_t k;
+    g.pent(u.v, jj, gs, k);
+    same = target_y(tab, gs, k, la, ka) == target_y(tab, gs, k, lb, kb);
+  }
+  if (!same) atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks + 1), 1ull);
+  return Wa > Wb ? 1 : (Wa < Wb ? -1 : 0);
+}
+
+// Exact: near-ties go to the big-integer evaluation; otherwise they raise the redo flag.
+template <bool Exact>
+struct PolicyKT {
   typedef ScoreK Score;
   template <class V>
   __device__ static Score make(const V &g, const UnitCtx &u, const SolveDev &sd,
@@ -269,7 +290,10 @@ struct PolicyK {
     if ((a.kind & 4) && (b.kind & 4)) return a.W < b.W ? -1 : (a.W > b.W ? 1 : 0);   // both q*W
     double d = a.ap - b.ap;
     if (fabs(d) > 2.0 * (a.er + b.er)) return d > 0 ? 1 : -1;
-    return exact_cmp(g, u, sd, tab, a.lab, a.kind & 3, a.W, b.lab, b.kind & 3, b.W);
+    if constexpr (Exact)
+      return exact_cmp(g, u, sd, tab, a.lab, a.kind & 3, a.W, b.lab, b.kind & 3, b.W);
+    else
+      return exact_cmp_flag(g, u, sd, tab, a.lab, a.kind & 3, a.W, b.lab, b.kind & 3, b.W);
   }
   __device__ static bool prunable(const UnitCtx &u, int64_t W, const Score &best) {
     if (u.m <= 1) {
@@ -294,6 +318,13 @@ struct PolicyK {
     return o;
   }
 };
+using PolicyK = PolicyKT<true>;
+using PolicyKF = PolicyKT<false>;
+// policies of units spanning several slices (cooperative evaluation applies to them)
+template <class P>
+struct IsMulti : std::false_type {};
+template <bool E>
+struct IsMulti<PolicyKT<E>> : std::true_type {};
 
 // Aggregated levels, units in at most one slice: the same int128 value as PolicyK's
 // single-slice case without the multi-slice machinery (far fewer registers).
@@ -683,7 +714,7 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   int64_t hW;
   uint32_t hL;
   group_heaviest(grp, tab, D, (const uint8_t *)nullptr, hW, hL, sredW, sredL);
-  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) {
+  if constexpr (!V::kLevel0 && IsMulti<P>::value) {
     if (u.m >= kCoopMinM)
       return lm_unit_coop<P>(grp, tab, g, sd, u, sig, fresh_base, red, pc, best, hW, hL);
   }
@@ -991,9 +1022,9 @@ constexpr int kLatThreads = 512;
 // Block size of the 8192-slot table kernels: the multi-slice policy needs more than the 128
 // registers per lane that 1024-thread blocks allow
 template <class P>
-constexpr int kBlockThreads = std::is_same<P, PolicyK>::value ? 512 : 1024;
+constexpr int kBlockThreads = IsMulti<P>::value ? 512 : 1024;
 
-template <class V>
+template <class V, class PK>
 __global__ __launch_bounds__(kLatThreads) void k_lm_lat(V g, SolveDev sd, LatSegs ls,
                                                         const uint32_t *comm, SliceTable sig,
                                                         uint32_t fresh_base, LmCounters pc) {
@@ -1015,7 +1046,7 @@ __global__ __launch_bounds__(kLatThreads) void k_lm_lat(V g, SolveDev sd, LatSeg
     lat_bin<PolicyK1>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, red1, hw,
                       hl);
   else
-    lat_bin<PolicyK>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, redK, hw,
+    lat_bin<PK>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, redK, hw,
                      hl);
 }
 
@@ -1137,9 +1168,9 @@ __global__ __launch_bounds__(256) void k_hub_eval(V g, SolveDev sd, const int32_
   typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
   int ncand = 0;
   bool coop = false;
-  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) coop = u.m >= kCoopMinM;
+  if constexpr (!V::kLevel0 && IsMulti<P>::value) coop = u.m >= kCoopMinM;
   if (coop) {
-    if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) {
+    if constexpr (!V::kLevel0 && IsMulti<P>::value) {
       const CoopLane c = coop_lane(g, u, sd, sig, threadIdx.x);
       const int sub = threadIdx.x / c.mp, nsub = blockDim.x / c.mp;
       for (int64_t i0 = s0; i0 < s1; i0 += (int64_t)nsub * kCoopBatch) {
@@ -1200,9 +1231,9 @@ __global__ __launch_bounds__(64) void k_hub_final(V g, SolveDev sd, const int32_
   const int64_t wD = tab.get(D);
   typename P::Score stay;
   bool coop = false;
-  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) coop = u.m >= kCoopMinM;
+  if constexpr (!V::kLevel0 && IsMulti<P>::value) coop = u.m >= kCoopMinM;
   if (coop) {
-    if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value)
+    if constexpr (!V::kLevel0 && IsMulti<P>::value)
       stay = coop_make(u, coop_lane(g, u, sd, sig, lane), D, wD, kStay);
   } else {
     stay = P::make(g, u, sd, sig, D, wD, kStay);
@@ -1984,9 +2015,9 @@ __device__ inline void ref_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd
   uint32_t hL;
   group_heaviest(grp, tab, kNone, wcT, hW, hL, sredW, sredL);
   bool coop = false;
-  if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) coop = u.m >= kCoopMinM;
+  if constexpr (!V::kLevel0 && IsMulti<P>::value) coop = u.m >= kCoopMinM;
   if (coop) {
-    if constexpr (!V::kLevel0 && std::is_same<P, PolicyK>::value) {
+    if constexpr (!V::kLevel0 && IsMulti<P>::value) {
       // one profile slice per lane, subgroups take the sub-communities in turn (every lane of
       // a subgroup runs the same turns)
       const CoopLane c = coop_lane(g, u, sd, sr, r);

@@ -139,7 +139,6 @@ def test_exact_comparisons_match_oracle():
     """The batched workload's graph 44 (N=214, T=26): its solves meet many pairs of targets
     whose double estimates cannot be told apart, settled by the 2304-bit evaluation.  The
     exact path must run, and every result must equal the oracle's."""
-    import oracle
     mslm = _mslm()
     tg = gen.batch_graph(44)
     g = mslm.Graph(tg, 1)
