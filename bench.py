@@ -57,9 +57,9 @@ def cpu_baseline(args):
                        name="cfg3_first2_slices")
         omega, gamma, what = Fraction(1, 2), 1, "N=1M x T=2 snapshots of the config-3 generator"
     else:
-        tg = gen.dcsbm(100_000, 4, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=2,
-                       name="cfg2_first4_slices")
-        omega, gamma, what = 1, 1, "N=100k x T=4 snapshots of the config-2 generator"
+        tg = gen.dcsbm(100_000, 8, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=2,
+                       name="cfg2_first8_slices")
+        omega, gamma, what = 1, 1, "N=100k x T=8 snapshots of the config-2 generator"
     og = oracle.OracleGraph(tg, omega)
     rp, col, w, raw, twom = og.csr()
     m_supra = int(rp[-1]) // 2
