@@ -84,6 +84,7 @@ struct Workspace {
   Buf jph0, jph1;                         // heavy frontier lists of the colouring
   Buf sig_count;                          // profile entries per slice of a level
   Buf comm_snap;                          // labels at the start of a sweep (for a redo)
+  Buf s_redo;                             // per-solve redo flags of a sweep
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };

@@ -32,6 +32,7 @@ struct SolveDev {
   const int32_t *sfirst;               // first global slice of the solve
   const int64_t *S;                    // per global slice: 2m_s, or 1 for an empty slice
   int64_t *fallbacks;                  // exact-comparison counter
+  uint32_t *redo;                      // per solve: a sweep met a near-tie it could not settle
 };
 
 // ------------------------------------------------------------------ level views
@@ -219,8 +220,8 @@ __device__ inline int exact_cmp(const V &g, const UnitCtx &u, const SolveDev &sd
 
 // The same order for the sweeps that run without the big-integer path (it needs per-lane
 // scratch memory, which slows every launch of a kernel that contains it): equal per-slice
-// terms are settled here as well; a genuine near-tie raises the solve's redo flag and gets a
-// provisional answer, and the host takes the whole sweep again with the exact kernels.
+// terms are settled here as well; a genuine near-tie raises its solve's redo flag and gets a
+// provisional answer, and the host takes that solve's sweep again with the exact kernels.
 template <class V>
 __device__ inline int exact_cmp_flag(const V &g, const UnitCtx &u, const SolveDev &sd,
                                      const SliceTable &tab, uint32_t la, int ka, int64_t Wa,
@@ -232,7 +233,7 @@ __device__ inline int exact_cmp_flag(const V &g, const UnitCtx &u, const SolveDe
     g.pent(u.v, jj, gs, k);
     same = target_y(tab, gs, k, la, ka) == target_y(tab, gs, k, lb, kb);
   }
-  if (!same) atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks + 1), 1ull);
+  if (!same) atomicOr(sd.redo + u.j, 1u);
   return Wa > Wb ? 1 : (Wa < Wb ? -1 : 0);
 }
 
@@ -1293,6 +1294,14 @@ __global__ void k_profile_slice_count(const int32_t *ps, int64_t ne, int nslices
   if (lds)
     for (int i = threadIdx.x; i < nslices; i += blockDim.x)
       if (h[i]) atomicAdd(reinterpret_cast<unsigned long long *>(cnt + i), (unsigned long long)h[i]);
+}
+
+// Labels of the units of flagged solves back to their copy from the start of the sweep.
+template <class V>
+__global__ void k_restore_flagged(V g, int64_t n, const uint32_t *snap, const uint32_t *redo,
+                                  uint32_t *comm) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && redo[g.usolve[v]]) comm[v] = snap[v];
 }
 
 template <class V>
