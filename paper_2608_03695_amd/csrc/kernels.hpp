@@ -1548,16 +1548,15 @@ __global__ __launch_bounds__(256) void k_jp_round(V g, SolveDev sd, JpLists L, i
 }
 
 // sort key of a unit for batching: colour, then degree bin
-constexpr uint32_t kInactiveKey = 0xfffffffcu;
-
+// (inactive: the key of units of solves that sit this iteration out, above every real key)
 template <class V>
 __global__ void k_batch_keys(V g, int64_t n, const int32_t *colour, const uint8_t *sactive,
-                             uint32_t *keys, uint32_t *vals) {
+                             uint32_t inactive, uint32_t *keys, uint32_t *vals) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   vals[v] = (uint32_t)v;
   if (!sactive[g.usolve[v]]) {
-    keys[v] = kInactiveKey;
+    keys[v] = inactive;
     return;
   }
   keys[v] = ((uint32_t)colour[v] << kBatchShift) | batch_slot(g, v);
