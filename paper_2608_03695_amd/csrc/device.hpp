@@ -96,6 +96,37 @@ __device__ inline void wave_append(int32_t *out, uint32_t *ctr, bool flag, int32
   if (flag) out[base + __popcll(bal & ((1ull << lane) - 1))] = val;
 }
 
+// Appends gathered in a wave-private LDS buffer and written out in chunks: one global atomic
+// per chunk instead of one per call (a frontier counter is shared by the whole grid, and
+// atomics on one word serialise).  n is the same on every lane of the wave.
+constexpr int kStage = 512;
+struct WaveStage {
+  int32_t *buf;     // LDS, kStage entries, private to the wave
+  int32_t *out;     // global list
+  uint32_t *ctr;    // its length
+  uint32_t n;       // entries held
+  __device__ void flush() {
+    if (n == 0) return;
+    wave_sync();
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(ctr, n);
+    base = (uint32_t)__shfl((int)base, 0, 64);
+    for (uint32_t i = lane; i < n; i += 64) out[base + i] = buf[i];
+    wave_sync();
+    n = 0;
+  }
+  // every lane of the wave must call this
+  __device__ void append(bool flag, int32_t val) {
+    const uint64_t bal = __ballot(flag);
+    if (!bal) return;
+    const int lane = threadIdx.x & 63;
+    if (flag) buf[n + __popcll(bal & ((1ull << lane) - 1))] = val;
+    n += (uint32_t)__popcll(bal);
+    if (n > kStage - 64) flush();
+  }
+};
+
 // ------------------------------------------------------------------ Sigma table
 // Slot layout: 64-bit word, low half = key (label + 1, 0 = empty), high half = value.
 // Values are slice degrees (< 2^31 by the create-time precondition).

@@ -1249,12 +1249,21 @@ __global__ __launch_bounds__(64) void k_hub_final(V g, SolveDev sd, const int32_
 
 // Apply the decided moves of one colour batch: new label, Sigma delta for every profile slice.
 template <class V>
-__global__ void k_lm_apply(V g, const int32_t *units, int64_t count, const uint32_t *target,
-                           uint32_t *comm, SliceTable sig, uint32_t *moved,
-                           const uint8_t *frozen) {
+__global__ __launch_bounds__(256) void k_lm_apply(V g, const int32_t *units, int64_t count,
+                                                  const uint32_t *target, uint32_t *comm,
+                                                  SliceTable sig, uint32_t *moved,
+                                                  const uint8_t *frozen) {
+  __shared__ uint32_t s_moves;
+  __shared__ int s_j, s_mixed;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool mv = false;
   int j = 0;
+  if (threadIdx.x == 0) {
+    s_moves = 0;
+    s_mixed = 0;
+    s_j = g.usolve[units[i]];   // thread 0's unit always exists
+  }
+  __syncthreads();
   if (i < count) {
     const uint32_t C = target[i];
     const int64_t v = units[i];
@@ -1272,8 +1281,16 @@ __global__ void k_lm_apply(V g, const int32_t *units, int64_t count, const uint3
       comm[v] = C;
       mv = true;
     }
+    if (j != s_j) s_mixed = 1;
+    if (mv) atomicAdd(&s_moves, 1u);
   }
-  wave_count(moved, j, mv);
+  __syncthreads();
+  // one atomic per block when all its units belong to one solve (the usual case)
+  if (!s_mixed) {
+    if (threadIdx.x == 0 && s_moves) atomicAdd(moved + s_j, s_moves);
+  } else {
+    wave_count(moved, j, mv);
+  }
 }
 
 // Profile entries per global slice (how many units of a level can hold a key in the slice's
@@ -1414,8 +1431,7 @@ __global__ __launch_bounds__(256) void k_jp_count_wide(V g, SolveDev sd, const i
 template <class V>
 __device__ inline void jp_release(const V &g, const typename V::Row &row, int64_t first,
                                   int step, int64_t v, uint64_t sm, int64_t off, uint64_t hv,
-                                  uint32_t *cnt, int32_t *nl, uint32_t *cl, int32_t *nh,
-                                  uint32_t *ch, int it, int lvl) {
+                                  uint32_t *cnt, WaveStage &sl, WaveStage &sh, int it, int lvl) {
   for (int64_t e0 = row.lo; e0 < row.hi; e0 += step) {
     const int64_t e = e0 + first;
     bool ready = false;
@@ -1428,8 +1444,8 @@ __device__ inline void jp_release(const V &g, const typename V::Row &row, int64_
       }
     }
     const bool heavy = ready && g.degree(x) > kJpHeavy;
-    wave_append(nl, cl, ready && !heavy, x);
-    wave_append(nh, ch, heavy, x);
+    sl.append(ready && !heavy, x);
+    sh.append(heavy, x);
   }
 }
 
@@ -1490,8 +1506,8 @@ constexpr int kJpBlockWords = 64;
 // Colour one light frontier unit with one wave.
 template <class V>
 __device__ inline void jp_unit(const V &g, const SolveDev &sd, int64_t v, int32_t *colour,
-                               uint32_t *cnt, int32_t *nl, uint32_t *cl, int32_t *nh,
-                               uint32_t *ch, int it, int lvl, uint64_t *bits) {
+                               uint32_t *cnt, WaveStage &sl, WaveStage &sh, int it, int lvl,
+                               uint64_t *bits) {
   const int lane = threadIdx.x & 63;
   const int j = g.usolve[v];
   const uint64_t sm = sd.seedmix[j];
@@ -1501,14 +1517,14 @@ __device__ inline void jp_unit(const V &g, const SolveDev &sd, int64_t v, int32_
   const int result = jp_first_free<kJpLightWords>(g, row, lane, 64, v, sm, off, hv, colour, it,
                                                   lvl, bits, WaveLdsSync());
   if (lane == 0) colour[v] = result;
-  jp_release(g, row, lane, 64, v, sm, off, hv, cnt, nl, cl, nh, ch, it, lvl);
+  jp_release(g, row, lane, 64, v, sm, off, hv, cnt, sl, sh, it, lvl);
 }
 
 // Colour one heavy frontier unit with the whole block (all threads must call this).
 template <class V>
 __device__ inline void jp_unit_block(const V &g, const SolveDev &sd, int64_t v, int32_t *colour,
-                                     uint32_t *cnt, int32_t *nl, uint32_t *cl, int32_t *nh,
-                                     uint32_t *ch, int it, int lvl, uint64_t *bits) {
+                                     uint32_t *cnt, WaveStage &sl, WaveStage &sh, int it,
+                                     int lvl, uint64_t *bits) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int j = g.usolve[v];
   const uint64_t sm = sd.seedmix[j];
@@ -1518,7 +1534,7 @@ __device__ inline void jp_unit_block(const V &g, const SolveDev &sd, int64_t v, 
   const int result = jp_first_free<kJpBlockWords>(g, row, tid, nt, v, sm, off, hv, colour, it,
                                                   lvl, bits, BlockLdsSync());
   if (tid == 0) colour[v] = result;
-  jp_release(g, row, tid, nt, v, sm, off, hv, cnt, nl, cl, nh, ch, it, lvl);
+  jp_release(g, row, tid, nt, v, sm, off, hv, cnt, sl, sh, it, lvl);
 }
 
 // One Jones-Plassmann round with its frontier sizes read on the device, so rounds can be
@@ -1531,20 +1547,23 @@ __global__ __launch_bounds__(256) void k_jp_round(V g, SolveDev sd, JpLists L, i
                                                   uint32_t *cnt, int r, int it, int lvl) {
   __shared__ uint64_t s_light[4][kJpLightWords];
   __shared__ uint64_t s_block[kJpBlockWords];
+  __shared__ int32_t s_stage[4][2][kStage];
   const int64_t nf = L.counts[r % 3], nh = L.counts[3 + r % 3];
   const int p = r & 1;
-  int32_t *nl = L.light[p ^ 1], *nhv = L.heavy[p ^ 1];
-  uint32_t *cl = L.counts + (r + 1) % 3, *ch = L.counts + 3 + (r + 1) % 3;
+  const int wv = threadIdx.x >> 6;
+  // released units are staged per wave and written out in chunks
+  WaveStage sl{s_stage[wv][0], L.light[p ^ 1], L.counts + (r + 1) % 3, 0};
+  WaveStage sh{s_stage[wv][1], L.heavy[p ^ 1], L.counts + 3 + (r + 1) % 3, 0};
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     L.counts[(r + 2) % 3] = 0;
     L.counts[3 + (r + 2) % 3] = 0;
   }
-  for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nf;
-       idx += (int64_t)gridDim.x * 4)
-    jp_unit(g, sd, (int64_t)L.light[p][idx], colour, cnt, nl, cl, nhv, ch, it, lvl,
-            s_light[threadIdx.x >> 6]);
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + wv; idx < nf; idx += (int64_t)gridDim.x * 4)
+    jp_unit(g, sd, (int64_t)L.light[p][idx], colour, cnt, sl, sh, it, lvl, s_light[wv]);
   for (int64_t idx = blockIdx.x; idx < nh; idx += gridDim.x)
-    jp_unit_block(g, sd, (int64_t)L.heavy[p][idx], colour, cnt, nl, cl, nhv, ch, it, lvl, s_block);
+    jp_unit_block(g, sd, (int64_t)L.heavy[p][idx], colour, cnt, sl, sh, it, lvl, s_block);
+  sl.flush();
+  sh.flush();
 }
 
 // sort key of a unit for batching: colour, then degree bin
