@@ -85,6 +85,7 @@ struct Workspace {
   Buf sig_count;                          // profile entries per slice of a level
   Buf comm_snap;                          // labels at the start of a sweep (for a redo)
   Buf s_redo;                             // per-solve redo flags of a sweep
+  Buf ref_wide, ref_wcnt;                 // refinement units with long rows, and their count
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };

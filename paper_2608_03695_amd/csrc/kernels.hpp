@@ -2244,72 +2244,96 @@ __global__ __launch_bounds__(256) void k_ref_prop_gtab(V g, SolveDev sd, const i
 //  (b) the proposer outranks every proposing neighbour of its community, and the target's
 //      founder proposes to a target whose own founder proposes (so the founder cannot move).
 // Proposals and eligibility carry the round's stamp instead of being cleared.
+// Rows up to kRefThreadRow entries are scanned by the unit's own thread; longer ones are set
+// aside for a wave each (most listed units need no scan at all).
+constexpr int kRefThreadRow = 64;
+
 template <class V>
-__global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, Segs segs,
-                                                      const uint32_t *comm, const uint32_t *prop,
-                                                      const uint32_t *propr, uint32_t stamp,
-                                                      uint32_t *elig, int it, int lvl) {
-  const int lane = threadIdx.x & 63;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= segs.total()) return;
-  const int64_t v = segs.unit(idx);
-  if (propr[v] != stamp) return;
-  const uint32_t T = prop[v];
-  if (propr[T] != stamp) {
-    if (lane == 0) elig[v] = stamp;
-    return;
-  }
-  if (propr[prop[T]] != stamp) return;
+__device__ inline bool ref_beaten(const V &g, const SolveDev &sd, int64_t v, const uint32_t *comm,
+                                  const uint32_t *propr, uint32_t stamp, int first, int step,
+                                  int it, int lvl) {
   const int j = g.usolve[v];
   const uint64_t sm = sd.seedmix[j];
   const int64_t off = sd.uoff[j];
   const uint64_t hv = priority(sm, it, lvl, 1, (uint32_t)(v - off));
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
-  int beaten = 0;
-  for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+  bool beaten = false;
+  for (int64_t e = row.lo + first; e < row.hi; e += step) {
     int32_t x = g.col[e];
     if (comm[x] != D || propr[x] != stamp) continue;
     if (g.wt(row, e, x) == 0) continue;
     uint64_t hx = priority(sm, it, lvl, 1, (uint32_t)(x - off));
-    if (outranks(hx, (uint32_t)x, hv, (uint32_t)v)) beaten = 1;
+    if (outranks(hx, (uint32_t)x, hv, (uint32_t)v)) beaten = true;
   }
-  for (int m = 32; m >= 1; m >>= 1) beaten |= __shfl_xor(beaten, m, 64);
-  if (lane == 0 && !beaten) elig[v] = stamp;
+  return beaten;
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_eligible(V g, SolveDev sd, Segs segs,
+                                                      const uint32_t *comm, const uint32_t *prop,
+                                                      const uint32_t *propr, uint32_t stamp,
+                                                      uint32_t *elig, int32_t *wide,
+                                                      uint32_t *nwide, int it, int lvl) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool defer = false;
+  int64_t v = 0;
+  if (idx < segs.total()) {
+    v = segs.unit(idx);
+    if (propr[v] == stamp) {
+      const uint32_t T = prop[v];
+      if (propr[T] != stamp) {
+        elig[v] = stamp;
+      } else if (propr[prop[T]] == stamp) {
+        if (g.degree(v) > kRefThreadRow) defer = true;
+        else if (!ref_beaten(g, sd, v, comm, propr, stamp, 0, 1, it, lvl)) elig[v] = stamp;
+      }
+    }
+  }
+  wave_append(wide, nwide, defer, (int32_t)v);
+}
+
+// the long rows set aside above, one wave each (their number is read on the device)
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_eligible_wide(V g, SolveDev sd, const int32_t *wide,
+                                                           const uint32_t *nwide,
+                                                           const uint32_t *comm,
+                                                           const uint32_t *propr, uint32_t stamp,
+                                                           uint32_t *elig, int it, int lvl) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = *nwide;
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nw;
+       idx += (int64_t)gridDim.x * 4) {
+    const int64_t v = wide[idx];
+    int beaten = ref_beaten(g, sd, v, comm, propr, stamp, lane, 64, it, lvl) ? 1 : 0;
+    for (int m = 32; m >= 1; m >>= 1) beaten |= __shfl_xor(beaten, m, 64);
+    if (lane == 0 && !beaten) elig[v] = stamp;
+  }
 }
 
 // Merge every eligible proposer into its target; edges between co-joiners of the same target
-// become internal as well.  The first merge into T queues T for a fresh well-connectedness
-// check.
+// become internal as well.
 template <class V>
-__global__ __launch_bounds__(256) void k_ref_apply(V g, SolveDev sd, Segs segs, const uint32_t *prop,
-                                                   const int64_t *propw, const uint32_t *elig,
-                                                   uint32_t stamp, uint32_t *R, int64_t *ext,
-                                                   uint64_t *mask, uint8_t *active,
-                                                   uint32_t *changed, int32_t *clist,
-                                                   uint32_t *ccount, uint32_t *nelig,
-                                                   SliceTable sr) {
-  const int lane = threadIdx.x & 63;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= segs.total()) return;
-  const int64_t v = segs.unit(idx);
-  if (elig[v] != stamp) return;
+__device__ inline void ref_merge(const V &g, const SolveDev &sd, int64_t v, const uint32_t *prop,
+                                 const int64_t *propw, const uint32_t *elig, uint32_t stamp,
+                                 uint32_t *R, int64_t *ext, uint64_t *mask, uint8_t *active,
+                                 SliceTable sr, int first, int step, bool wave) {
   const uint32_t T = prop[v];
   typename V::Row row = g.row(v, sd);
   int64_t corr = 0;
-  for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+  for (int64_t e = row.lo + first; e < row.hi; e += step) {
     int32_t x = g.col[e];
     if (elig[x] == stamp && prop[x] == T) corr += g.wt(row, e, x);
   }
-  corr = wave_sum64(corr);
+  if (wave) corr = wave_sum64(corr);
   const int m = g.plen(v);
-  for (int jj = lane; jj < m; jj += 64) {
+  for (int jj = first; jj < m; jj += step) {
     int gs;
     int64_t k;
     g.pent(v, jj, gs, k);
     tab_add(sr, gs, T, (int32_t)k, false);
   }
-  if (lane == 0) {
+  if (first == 0) {
     R[v] = T;
     active[v] = 0;
     active[T] = 0;
@@ -2317,10 +2341,41 @@ __global__ __launch_bounds__(256) void k_ref_apply(V g, SolveDev sd, Segs segs, 
               (unsigned long long)(ext[v] - 2 * propw[v] - corr));
     atomicOr(reinterpret_cast<unsigned long long *>(mask + T), (unsigned long long)mask[v]);
   }
-  (void)changed;
-  (void)clist;
-  (void)ccount;
-  (void)nelig;
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_apply(V g, SolveDev sd, Segs segs, const uint32_t *prop,
+                                                   const int64_t *propw, const uint32_t *elig,
+                                                   uint32_t stamp, uint32_t *R, int64_t *ext,
+                                                   uint64_t *mask, uint8_t *active,
+                                                   int32_t *wide, uint32_t *nwide, SliceTable sr) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool defer = false;
+  int64_t v = 0;
+  if (idx < segs.total()) {
+    v = segs.unit(idx);
+    if (elig[v] == stamp) {
+      if (g.degree(v) > kRefThreadRow || g.plen(v) > kRefThreadRow) defer = true;
+      else ref_merge(g, sd, v, prop, propw, elig, stamp, R, ext, mask, active, sr, 0, 1, false);
+    }
+  }
+  wave_append(wide, nwide, defer, (int32_t)v);
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_apply_wide(V g, SolveDev sd, const int32_t *wide,
+                                                        const uint32_t *nwide,
+                                                        const uint32_t *prop,
+                                                        const int64_t *propw,
+                                                        const uint32_t *elig, uint32_t stamp,
+                                                        uint32_t *R, int64_t *ext, uint64_t *mask,
+                                                        uint8_t *active, SliceTable sr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = *nwide;
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nw;
+       idx += (int64_t)gridDim.x * 4)
+    ref_merge(g, sd, (int64_t)wide[idx], prop, propw, elig, stamp, R, ext, mask, active, sr, lane,
+              64, true);
 }
 
 // merges per solve and the queue of sub-communities that received members (convergent)
