@@ -86,6 +86,7 @@ struct Workspace {
   Buf comm_snap;                          // labels at the start of a sweep (for a redo)
   Buf s_redo;                             // per-solve redo flags of a sweep
   Buf ref_wide, ref_wcnt;                 // refinement units with long rows, and their count
+  Buf ref_snap_a, ref_snap_p;             // active flags and proposal stamps before a round
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };
