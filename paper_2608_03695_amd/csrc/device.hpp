@@ -127,6 +127,28 @@ struct WaveStage {
   }
 };
 
+// Appends of a whole block written with one global atomic: every thread of the block calls
+// this (s holds blockDim.x / 64 + 1 words of LDS).
+__device__ inline void block_append(int32_t *out, uint32_t *ctr, bool flag, int32_t val,
+                                    uint32_t *s) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint64_t bal = __ballot(flag);
+  if (lane == 0) s[wv] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < nw; w++) {
+      const uint32_t c = s[w];
+      s[w] = tot;
+      tot += c;
+    }
+    s[nw] = tot ? atomicAdd(ctr, tot) : 0u;
+  }
+  __syncthreads();
+  if (flag) out[s[nw] + s[wv] + __popcll(bal & ((1ull << lane) - 1))] = val;
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ Sigma table
 // Slot layout: 64-bit word, low half = key (label + 1, 0 = empty), high half = value.
 // Values are slice degrees (< 2^31 by the create-time precondition).

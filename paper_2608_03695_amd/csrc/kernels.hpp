@@ -1891,11 +1891,13 @@ struct SegOut {
 };
 
 // keep the units whose flag is still set, segment by segment
-__global__ void k_compact_segs(Segs in, const uint8_t *flag, SegOut out, uint32_t *cnt) {
+__global__ __launch_bounds__(256) void k_compact_segs(Segs in, const uint8_t *flag, SegOut out,
+                                                      uint32_t *cnt) {
+  __shared__ uint32_t s_app[256 / 64 + 1];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < in.total();
   const int ks = live ? in.seg(i) : -1;
-  // a wave may straddle segments: append segment by segment
+  // a block may straddle segments: append segment by segment, one atomic per block and list
   for (int k = 0; k < kRefLists; k++) {
     bool keep = false;
     int32_t v = 0;
@@ -1903,7 +1905,7 @@ __global__ void k_compact_segs(Segs in, const uint8_t *flag, SegOut out, uint32_
       v = (int32_t)in.unit(i);
       keep = flag[v] != 0;
     }
-    wave_append(out.p[k], cnt + k, keep, v);
+    if (__syncthreads_or(ks == k)) block_append(out.p[k], cnt + k, keep, v, s_app);
   }
 }
 
@@ -2380,13 +2382,23 @@ __global__ __launch_bounds__(256) void k_ref_apply_wide(V g, SolveDev sd, const 
 
 // merges per solve and the queue of sub-communities that received members (convergent)
 template <class V>
-__global__ void k_ref_post(V g, Segs segs, const uint32_t *prop, const uint32_t *elig,
-                           uint32_t stamp, uint32_t *changed, int32_t *clist, uint32_t *ccount,
-                           uint32_t *nelig) {
+__global__ __launch_bounds__(256) void k_ref_post(V g, Segs segs, const uint32_t *prop,
+                                                  const uint32_t *elig, uint32_t stamp,
+                                                  uint32_t *changed, int32_t *clist,
+                                                  uint32_t *ccount, uint32_t *nelig) {
+  __shared__ uint32_t s_app[256 / 64 + 1];
+  __shared__ uint32_t s_merges;
+  __shared__ int s_j, s_mixed;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool merged = false, first = false;
   int j = 0;
   uint32_t T = 0;
+  if (threadIdx.x == 0) {
+    s_merges = 0;
+    s_mixed = 0;
+    s_j = -1;
+  }
+  __syncthreads();
   if (i < segs.total()) {
     const int64_t v = segs.unit(i);
     if (elig[v] == stamp) {
@@ -2394,10 +2406,19 @@ __global__ void k_ref_post(V g, Segs segs, const uint32_t *prop, const uint32_t 
       j = g.usolve[v];
       T = prop[v];
       first = atomicExch(changed + T, 1u) == 0u;
+      atomicAdd(&s_merges, 1u);
+      const int prev = atomicCAS(&s_j, -1, j);
+      if (prev != -1 && prev != j) s_mixed = 1;
     }
   }
-  wave_count(nelig, j, merged);
-  wave_append(clist, ccount, first, (int32_t)T);
+  __syncthreads();
+  // one atomic per block when its merges all belong to one solve (the usual case)
+  if (!s_mixed) {
+    if (threadIdx.x == 0 && s_merges) atomicAdd(nelig + s_j, s_merges);
+  } else {
+    wave_count(nelig, j, merged);
+  }
+  block_append(clist, ccount, first, (int32_t)T, s_app);
 }
 
 // ------------------------------------------------------------------ aggregation helpers
