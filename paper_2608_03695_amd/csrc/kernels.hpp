@@ -1293,6 +1293,35 @@ __global__ __launch_bounds__(256) void k_lm_apply(V g, const int32_t *units, int
   }
 }
 
+// The moves of a small batch, one wave per unit with the lanes over its profile slices (a
+// unit of an aggregated level spans up to 64 slices, two Sigma atomics each).
+template <class V>
+__global__ __launch_bounds__(256) void k_lm_apply_wave(V g, const int32_t *units, int64_t count,
+                                                       const uint32_t *target, uint32_t *comm,
+                                                       SliceTable sig, uint32_t *moved,
+                                                       const uint8_t *frozen) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= count) return;
+  const uint32_t C = target[i];
+  const int64_t v = units[i];
+  const int j = g.usolve[v];
+  if (C == kNone || frozen[j]) return;
+  const uint32_t D = comm[v];
+  const int m = g.plen(v);
+  for (int jj = lane; jj < m; jj += 64) {
+    int gs;
+    int64_t k;
+    g.pent(v, jj, gs, k);
+    tab_add(sig, gs, D, -(int32_t)k);
+    tab_add(sig, gs, C, (int32_t)k);
+  }
+  if (lane == 0) {
+    comm[v] = C;
+    atomicAdd(moved + j, 1u);
+  }
+}
+
 // Profile entries per global slice (how many units of a level can hold a key in the slice's
 // Sigma sub-table): an LDS histogram per block when the slices fit, else global atomics.
 constexpr int kSliceHistMax = 4096;
@@ -1916,21 +1945,26 @@ __global__ __launch_bounds__(256) void k_compact_segs(Segs in, const uint8_t *fl
 // its community, so each merge joins a frozen sub-community along an edge and
 // sub-communities stay connected.
 
+// Rows up to kRefThreadRow entries are scanned by the unit's own thread; longer ones are set
+// aside for a wave each (most units of a refinement pass need no scan at all).
+constexpr int kRefThreadRow = 64;
+
+// Refinement starts from singletons: R = id, ext = weight to the own community, slice mask,
+// and each unit's Sigma in the refined table.  first/step: this thread's share of the row
+// and profile (a thread for a short row, a wave's lanes for a long one).
 template <class V>
-__global__ __launch_bounds__(256) void k_ref_init(V g, SolveDev sd, int64_t n, const uint32_t *comm,
-                                                  uint32_t *R, int64_t *ext, uint64_t *mask,
-                                                  SliceTable sr) {
-  const int lane = threadIdx.x & 63;
-  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (v >= n) return;
+__device__ inline void ref_init_unit(const V &g, const SolveDev &sd, int64_t v,
+                                     const uint32_t *comm, uint32_t *R, int64_t *ext,
+                                     uint64_t *mask, SliceTable sr, int first, int step,
+                                     bool wave) {
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
   int64_t s = 0;
-  for (int64_t e = row.lo + lane; e < row.hi; e += 64) {
+  for (int64_t e = row.lo + first; e < row.hi; e += step) {
     int32_t x = g.col[e];
     if (comm[x] == D) s += g.wt(row, e, x);
   }
-  s = wave_sum64(s);
+  if (wave) s = wave_sum64(s);
   const int m = g.plen(v);
   const int j = g.usolve[v];
   uint64_t mk = 0;
@@ -1939,13 +1973,37 @@ __global__ __launch_bounds__(256) void k_ref_init(V g, SolveDev sd, int64_t n, c
     int64_t k;
     g.pent(v, jj, gs, k);
     mk |= 1ull << (gs - sd.sfirst[j]);
-    if (jj % 64 == lane) tab_add(sr, gs, (uint32_t)v, (int32_t)k, false);
+    if (jj % step == first) tab_add(sr, gs, (uint32_t)v, (int32_t)k, false);
   }
-  if (lane == 0) {
+  if (first == 0) {
     R[v] = (uint32_t)v;
     ext[v] = s;
     mask[v] = mk;
   }
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_init(V g, SolveDev sd, int64_t n, const uint32_t *comm,
+                                                  uint32_t *R, int64_t *ext, uint64_t *mask,
+                                                  SliceTable sr, int32_t *wide, uint32_t *nwide) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = v < n;
+  const bool defer = live && (g.degree(v) > kRefThreadRow || g.plen(v) > kRefThreadRow);
+  if (live && !defer) ref_init_unit(g, sd, v, comm, R, ext, mask, sr, 0, 1, false);
+  wave_append(wide, nwide, defer, (int32_t)v);
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_ref_init_wide(V g, SolveDev sd, const int32_t *wide,
+                                                       const uint32_t *nwide,
+                                                       const uint32_t *comm, uint32_t *R,
+                                                       int64_t *ext, uint64_t *mask,
+                                                       SliceTable sr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = *nwide;
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nw;
+       idx += (int64_t)gridDim.x * 4)
+    ref_init_unit(g, sd, (int64_t)wide[idx], comm, R, ext, mask, sr, lane, 64, true);
 }
 
 // Well-connectedness of sub-community T within its community K:
@@ -2246,9 +2304,6 @@ __global__ __launch_bounds__(256) void k_ref_prop_gtab(V g, SolveDev sd, const i
 //  (b) the proposer outranks every proposing neighbour of its community, and the target's
 //      founder proposes to a target whose own founder proposes (so the founder cannot move).
 // Proposals and eligibility carry the round's stamp instead of being cleared.
-// Rows up to kRefThreadRow entries are scanned by the unit's own thread; longer ones are set
-// aside for a wave each (most listed units need no scan at all).
-constexpr int kRefThreadRow = 64;
 
 template <class V>
 __device__ inline bool ref_beaten(const V &g, const SolveDev &sd, int64_t v, const uint32_t *comm,
