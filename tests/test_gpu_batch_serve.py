@@ -134,3 +134,24 @@ def test_same_handle_parameter_sweep_matches_oracle():
     assert np.array_equal(r["q_components"], oc)
     for k in STAT_KEYS:
         assert r[k] == ost[k], k
+
+
+def test_batch_with_exact_redo_equals_plain():
+    """Solves that meet near-ties needing the exact evaluation (the batched workload's graphs
+    43 and 44) batched with solves that do not: the sweeps and refinement rounds taken again
+    for the flagged solves alone must leave every result equal to a plain call."""
+    mslm = _mslm()
+    tgs = [gen.batch_graph(44), gen.batch_graph(43), _graphs()[0]]
+    handles = [mslm.Graph(tg, 1) for tg in tgs]
+    solves = [(0, F(1, 2), F(1), 32, 2, 0), (1, F(1), F(1, 10), 32, 2, 0),
+              (2, F(1), F(1), 32, 2, 0), (0, F(1), F(1), 32, 2, 0),
+              (1, F(1, 2), F(10), 32, 2, 0), (0, F(1, 2), F(10), 32, 2, 0)]
+    got = mslm.batch_leiden(handles, solves)
+    fallbacks = 0
+    for (gi, gamma, omega, lv, it, seed), out in zip(solves, got):
+        plain = handles[gi].leiden(gamma, omega, max_levels=lv, max_iterations=it, seed=seed)
+        fallbacks += plain[1]["exact_fallbacks"]
+        _same(out, plain, f"{tgs[gi].name} gamma={gamma} omega={omega}")
+    assert fallbacks > 0
+    for h in handles:
+        h.close()
