@@ -304,7 +304,7 @@ def main():
                     help="cfg4: time plain calls on every k-th solve of the grid")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
               f"multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
 
