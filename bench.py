@@ -4,10 +4,17 @@ One step = one complete solve (mslm_leiden: every Leiden iteration, level, sweep
 refinement round, aggregation, split and the Q components) on a supra-graph that is
 already resident in HBM.  Prints one JSON line (see the keys below).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3|cfg2|cfg1]
                     [--no-cpu-baseline]
     python bench.py --workload cfg4 [--graphs 512]         # batched grid vs plain calls
     python bench.py --workload cfg5 [--requests 1000]      # served Poisson trace vs plain FIFO
+    python bench.py --copy-calibration                     # 3 plain 1 GiB device copies
+
+The default workload is config 3 (T=64 x N=1M DC-SBM, omega=1/2), the largest instance that
+fits one GPU.  The timed steps run without instrumentation; the roofline comes from one extra
+solve whose level-0 decision launches are bracketed by HIP events on the solve stream, and the
+algorithmic bytes from one counting solve (the schedule is deterministic, so both do exactly the
+work of every timed step).
 """
 from __future__ import annotations
 
@@ -47,29 +54,66 @@ def workload(name, workers):
     raise SystemExit(f"unknown workload {name}")
 
 
+def host_cpu():
+    """CPU model and the host threads this process may use (for the baseline's label)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def full_size_oracle(workload):
+    """The oracle's full-size solve time recorded with the committed expected result of this
+    workload (taken once on a build host, not on the benchmark host), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload.split('_')[0]}_expected.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    t = rec.get("oracle_timing")
+    return t
+
+
 def cpu_baseline(args):
-    """The oracle, as it stands, on a bounded sample of the same workload family: the
-    workload's generator restricted to its first snapshots (same N, degree law, churn)."""
+    """The oracle, as it stands, on a bounded sample of the same workload: the workload's
+    generator at a smaller size (same degree law, mixing, churn, weights, omega and gamma).
+    Config 2 is small enough to run whole."""
     import oracle
     from paper_2608_03695_amd import gen
     if args.workload == "cfg3":
-        tg = gen.dcsbm(1_000_000, 2, 10, 1000, 0.4, 2.1, 0.02, weights_max=1, seed=3,
-                       name="cfg3_first2_slices")
-        omega, gamma, what = Fraction(1, 2), 1, "N=1M x T=2 snapshots of the config-3 generator"
+        tg = gen.dcsbm(250_000, 4, 10, 250, 0.4, 2.1, 0.02, weights_max=1, seed=3,
+                       name="cfg3_law_N250k_T4")
+        omega, gamma = Fraction(1, 2), 1
+        what = ("config-3 generator law (exponent 2.1, mean degree 10, mu 0.4, churn 0.02, "
+                "unit weights, omega 1/2) at N=250k x T=4, 250 communities")
+    elif args.workload == "cfg2":
+        tg = gen.config2(args.gen_workers)
+        omega, gamma, what = 1, 1, "config 2 itself (N=100k x T=16), the whole workload"
     else:
-        tg = gen.dcsbm(100_000, 8, 16, 100, 0.3, 2.5, 0.05, weights_max=8, seed=2,
-                       name="cfg2_first8_slices")
-        omega, gamma, what = 1, 1, "N=100k x T=8 snapshots of the config-2 generator"
+        tg = gen.config1()
+        omega, gamma, what = 1, 1, "config 1 itself, the whole workload"
     og = oracle.OracleGraph(tg, omega)
     rp, col, w, raw, twom = og.csr()
     m_supra = int(rp[-1]) // 2
     t0 = time.perf_counter()
     og.leiden(gamma, max_levels=32, max_iterations=2, seed=0)
     dt = time.perf_counter() - t0
-    return {"value": m_supra / dt, "unit": "supra-edges/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{tg.name}: {what}, {m_supra} supra-edges, one full solve "
-                      f"(2 iterations) in {dt:.1f} s"}
+    model, avail = host_cpu()
+    out = {"value": m_supra / dt, "unit": "supra-edges/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"{tg.name}: {what}; {m_supra} supra-edges, one full solve "
+                     f"(2 iterations) in {dt:.1f} s",
+           "host_cpu": model, "host_threads_available": avail}
+    full = full_size_oracle(args.workload)
+    if full is not None:
+        out["full_size_oracle"] = full
+    return out
 
 
 def roofline(nbytes, ms, launches, kernel):
@@ -286,15 +330,30 @@ def bench_served(args):
     }
 
 
+def copy_calibration():
+    """Three plain 1 GiB device-to-device copies (2^30 bytes read and 2^30 written each): the
+    run that calibrates the FETCH_SIZE / WRITE_SIZE counters under rocprofv3 --pmc."""
+    import torch
+    n = 1 << 28                      # 2^28 int32 = 1 GiB
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied 3 x {b.numel() * 4} bytes")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true",
-                    help="skip the extra counting solve (keeps profiler traces to the timed steps)")
+                    help="skip the profiled and the counting solve (keeps profiler traces to "
+                         "the timed steps)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes drawing the synthetic snapshots (1 under a profiler)")
     ap.add_argument("--graphs", type=int, default=512, help="cfg4/cfg5: batched-workload graphs")
@@ -302,11 +361,16 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="cfg5: server worker slots")
     ap.add_argument("--plain-sample", type=int, default=8,
                     help="cfg4: time plain calls on every k-th solve of the grid")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
               f"multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     if args.workload in ("cfg4", "cfg5"):
         out = bench_batched(args) if args.workload == "cfg4" else bench_served(args)
@@ -340,7 +404,7 @@ def main():
     step_ms = []
     for i in range(args.steps):
         ts = time.perf_counter()
-        _, r = g.leiden(profile=True, **kw)   # synchronous: the membership is on the host
+        _, r = g.leiden(**kw)   # synchronous: the membership is on the host when it returns
         step_ms.append((time.perf_counter() - ts) * 1000.0)
         results.append(r)
         log(f"step {i} done")
@@ -349,19 +413,26 @@ def main():
     log("timed steps done")
     ms_step = (t1 - t0) * 1000.0 / args.steps
     copy_gbs = device_copy_gbs(torch)
-    # the schedule is deterministic: one counting run gives the exact work of every step
+    # the schedule is deterministic: one profiled solve times the level-0 decision launches
+    # (HIP events on the solve stream) and one counting solve gives the exact work of a step
+    zero = {k: 0 for k in ("lm_units", "lm_entries", "lm_candidates", "lm0_units",
+                           "lm0_entries", "lm0_candidates", "lm0_kernel_ms", "lm0_launches")}
     if args.no_count:
-        rc = {k: 0 for k in ("lm_units", "lm_entries", "lm_candidates", "lm0_units",
-                             "lm0_entries", "lm0_candidates")}
+        rp = rc = zero
     else:
+        _, rp = g.leiden(profile=True, **kw)
+        log("profiled solve done")
         _, rc = g.leiden(count=True, **kw)
+        log("counting solve done")
+        if rp["q_components"].tolist() != results[-1]["q_components"].tolist() or \
+                rc["q_components"].tolist() != results[-1]["q_components"].tolist():
+            raise SystemExit("profiled or counting solve differs from the timed solves")
     weighted = tg.weight is not None
 
     def nbytes(pre):
         return (rc[pre + "_units"] * BYTES_UNIT
                 + rc[pre + "_entries"] * (BYTES_ENTRY + (BYTES_WEIGHT if weighted else 0))
                 + rc[pre + "_candidates"] * BYTES_CAND)
-    mean = lambda key: sum(r[key] for r in results) / len(results)  # noqa: E731
     q = mslm.q_exact(results[-1]["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
     out = {
         "metric": METRIC,
@@ -376,7 +447,7 @@ def main():
                    "gamma": str(spec.gamma), "omega": str(spec.omega),
                    "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
         # the HBM-bound loop: level-0 local-moving decisions (every sweep of every iteration)
-        "roofline": roofline(nbytes("lm0"), mean("lm0_kernel_ms"), results[0]["lm0_launches"],
+        "roofline": roofline(nbytes("lm0"), rp["lm0_kernel_ms"], rp["lm0_launches"],
                              "level-0 decision launches: k_lm_multi<Policy0, View0> (bins up "
                              "to 1024 entries) and k_lm_block<Policy0, View0, 1024> (larger)"),
         # the work of the aggregated levels' decisions (not timed: their launches are short)
@@ -396,11 +467,11 @@ def main():
     rl = out["roofline"]
     rl["copy_gbs"] = copy_gbs                 # a plain device copy on this GPU, same clock
     rl["frac_of_copy"] = rl["achieved"] / copy_gbs if copy_gbs else None
+    rl["bytes_per_launch"] = rl["bytes_per_step"] / max(rl["launches_per_step"], 1)
     t = measured_traffic(tg.name, rl["launches_per_step"])
     if t is not None:
         rl["traffic"] = t
         rl["traffic_gbs"] = t * rl["launches_per_step"] / (rl["kernel_ms_per_step"] * 1e-3) / 1e9
-        rl["bytes_per_launch"] = rl["bytes_per_step"] / max(rl["launches_per_step"], 1)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args)

@@ -33,7 +33,7 @@ typedef enum {
   MSLM_EINVAL = -1,       /* invalid argument or malformed graph                        */
   MSLM_ENOMEM = -2,       /* device or host allocation failed                           */
   MSLM_EOVERFLOW = -3,    /* exact integer head-room precondition violated              */
-  MSLM_EUNSUPPORTED = -4, /* outside this version's limits (T > 64, N*T >= 2^27 * 0.97) */
+  MSLM_EUNSUPPORTED = -4, /* outside this version's limits (T > 64, N*T*33 >= 2^32)         */
   MSLM_EHIP = -5,         /* HIP runtime error                                          */
   MSLM_EBUSY = -6         /* server: result not ready before the timeout                */
 } mslm_status;

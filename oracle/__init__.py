@@ -10,6 +10,7 @@ It holds two tiers that share no code with the HIP library:
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
 import os
 import subprocess
 from fractions import Fraction
@@ -18,18 +19,34 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mslm_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "libmslm_oracle.so")
+_LIB_PATH = os.environ.get("MSLM_ORACLE_LIB") or os.path.join(_HERE, "libmslm_oracle.so")
+_SHA_PATH = _LIB_PATH + ".sha256"
 _lib = None
 
 
+def _source_sha() -> str:
+    with open(_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (OpenMP inside a colour batch; results do not depend on it)."""
-    if force or not os.path.exists(_LIB_PATH):
+    """Compile the C oracle with gcc (OpenMP inside a colour batch; results do not depend on it).
+    The sha256 of the source is written beside the library, so a stale build is detected."""
+    if force or not _is_current():
         tmp = _LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB_PATH)
+        with open(_SHA_PATH, "w") as fh:
+            fh.write(_source_sha() + "\n")
     return _LIB_PATH
+
+
+def _is_current() -> bool:
+    if not (os.path.exists(_LIB_PATH) and os.path.exists(_SHA_PATH)):
+        return False
+    with open(_SHA_PATH) as fh:
+        return fh.read().strip() == _source_sha()
 
 
 class Stats(C.Structure):
@@ -46,8 +63,11 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        build(force=True)
+    # never compiles here: a process that already drives the GPU must not start a compiler
+    # (build() and the test session's start do that); a missing or stale library is an error
+    if os.environ.get("MSLM_ORACLE_LIB") is None and not _is_current():
+        raise RuntimeError(f"oracle library {_LIB_PATH} is missing or older than its source; "
+                           "run oracle.build() (or __graft_entry__.build()) first")
     lib = C.CDLL(_LIB_PATH)
     P = C.c_void_p
     lib.orc_create.argtypes = [C.c_int32, C.c_int32, P, P, P, P, C.c_int64, C.c_int64,

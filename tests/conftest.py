@@ -11,3 +11,12 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU-side case")
+
+
+def pytest_sessionstart(session):
+    # The oracle is compiled here, at the start of the session and before any test touches
+    # the GPU, when its library is missing or older than its source; the loader itself never
+    # compiles (a process that drives the GPU must not start a compiler).
+    import oracle
+    if not oracle._is_current():
+        oracle.build(force=True)
