@@ -91,6 +91,7 @@ def _load():
     lib.orc_trace_count.restype = C.c_int
     lib.orc_trace_info.argtypes = [C.c_int, P]
     lib.orc_trace_get.argtypes = [C.c_int] + [P] * 11 + [C.c_int64]
+    lib.orc_trace_refine.argtypes = [C.c_int, P, P]
     lib.orc_num_threads.restype = C.c_int
     _lib = lib
     return lib
@@ -214,5 +215,10 @@ def trace_levels(n0):
         lib.orc_trace_get(i, *[_ptr(rec[k]) for k in ("rp", "col", "w", "pp", "ps", "pk",
                                                      "colour", "p_in", "p_lm")],
                           _ptr(rec["r"]) if has_r else None, _ptr(rec["map0"]), n0)
+        rec["ext"] = rec["wc"] = None
+        if has_r:
+            rec["ext"] = np.zeros(n, np.int64)
+            rec["wc"] = np.zeros(n, np.int8)
+            lib.orc_trace_refine(i, _ptr(rec["ext"]), _ptr(rec["wc"]))
         out.append(rec)
     return out

@@ -448,6 +448,7 @@ typedef struct {
   int it, lvl; int64_t n, nnz; int32_t ncol, sweeps;
   int64_t *rp; int32_t *col; int64_t *w; int64_t *pp; int32_t *ps; int64_t *pk;
   int32_t *colour; uint32_t *p_in, *p_lm, *r; int64_t *map0; int has_r;
+  int64_t *ext; char *wc;     /* refinement bookkeeping at its end (valid for founders) */
 } trace_level_t;
 
 typedef struct { int on; int count, cap; trace_level_t *lv; } trace_t;
@@ -458,6 +459,7 @@ void orc_trace_enable(int on) {
     trace_level_t *t = &g_trace.lv[i];
     free(t->rp); free(t->col); free(t->w); free(t->pp); free(t->ps); free(t->pk);
     free(t->colour); free(t->p_in); free(t->p_lm); free(t->r); free(t->map0);
+    free(t->ext); free(t->wc);
   }
   free(g_trace.lv);
   memset(&g_trace, 0, sizeof(g_trace));
@@ -477,6 +479,13 @@ void orc_trace_get(int i, int64_t *rp, int32_t *col, int64_t *w, int64_t *pp, in
   memcpy(colour, t->colour, t->n * 4); memcpy(p_in, t->p_in, t->n * 4); memcpy(p_lm, t->p_lm, t->n * 4);
   if (t->has_r) memcpy(r, t->r, t->n * 4);
   memcpy(map0, t->map0, n0 * 8);
+}
+/* the refinement's running edge weight to the rest of the community and its
+ * well-connectedness flag, per founder of a refined sub-community (scaled weights) */
+void orc_trace_refine(int i, int64_t *ext, char *wc) {
+  trace_level_t *t = &g_trace.lv[i];
+  if (!t->has_r) return;
+  memcpy(ext, t->ext, t->n * 8); memcpy(wc, t->wc, t->n);
 }
 static void *dupmem(const void *p, size_t bytes) { void *q = malloc(bytes ? bytes : 1); memcpy(q, p, bytes); return q; }
 static trace_level_t *trace_push(int it, int lvl, const level_t *g, const int64_t *map0, int64_t n0) {
@@ -630,7 +639,8 @@ static void set_profile(const map_t *sr, uint32_t T, uint64_t mask, int32_t *sl,
 }
 
 static int64_t refine(const ctx_t *cx, const level_t *g, const uint32_t *P, const map_t *sigP,
-                      const uint32_t *local, uint64_t seed, int it, int lvl, uint32_t *R, orc_stats *st) {
+                      const uint32_t *local, uint64_t seed, int it, int lvl, uint32_t *R, orc_stats *st,
+                      int64_t *ext_out, char *wc_out) {
   int64_t n = g->n;
   map_t sr; map_init(&sr, g->pp[n]);
   int64_t *ext = calloc(n ? n : 1, sizeof(int64_t));
@@ -727,6 +737,8 @@ static int64_t refine(const ctx_t *cx, const level_t *g, const uint32_t *P, cons
     }
   }
   st->merges += merges;
+  if (ext_out) memcpy(ext_out, ext, n * sizeof(int64_t));
+  if (wc_out) memcpy(wc_out, wcT, n);
   map_free(&sr); free(ext); free(mask); free(single); free(active); free(wcT); free(elig); free(changed);
   free(prop); free(propw); free(pri);
   return merges;
@@ -897,9 +909,11 @@ int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t
       free(colour);
       if (ncomm == n || lvl == max_levels - 1) { map_free(&sig); free(local); break; }
       uint32_t *R = malloc((n ? n : 1) * sizeof(uint32_t));
-      refine(&cx, &g, P, &sig, local, seed, it, lvl, R, st);
+      int64_t *ext_t = tr ? malloc((n ? n : 1) * sizeof(int64_t)) : NULL;
+      char *wc_t = tr ? malloc(n ? n : 1) : NULL;
+      refine(&cx, &g, P, &sig, local, seed, it, lvl, R, st, ext_t, wc_t);
       map_free(&sig); free(local);
-      if (tr) { tr->r = dupmem(R, n * 4); tr->has_r = 1; }
+      if (tr) { tr->r = dupmem(R, n * 4); tr->has_r = 1; tr->ext = ext_t; tr->wc = wc_t; }
       uint32_t *tmp2 = malloc((n ? n : 1) * sizeof(uint32_t));
       int64_t nref = canon(n, R, tmp2);
       free(tmp2);
