@@ -43,8 +43,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name, workers):
+def workload(name, workers, cache=None):
+    """The named workload's graph and solve parameters.  cache: a .npz path holding the graph
+    drawn by an earlier run of the same workload (written there when absent), so that profiled
+    runs can skip the multi-process generator."""
     from paper_2608_03695_amd import gen
+    if cache:
+        import numpy as np
+        spec = {"cfg1": gen.CONFIG_SOLVE[1], "cfg2": gen.CONFIG_SOLVE[2],
+                "cfg3": gen.CONFIG_SOLVE[3]}[name]
+        if os.path.exists(cache):
+            z = np.load(cache, allow_pickle=False)
+            if str(z["name"]).startswith(name + "_"):
+                w = z["weight"] if z["weight"].size else None
+                tg = gen.TemporalGraph(int(z["n_nodes"]), int(z["n_slices"]), z["offsets"],
+                                       z["src"], z["dst"], w, None, str(z["name"]))
+                return tg, spec
+        tg, _ = workload(name, workers)
+        np.savez(cache, n_nodes=tg.n_nodes, n_slices=tg.n_slices, offsets=tg.offsets,
+                 src=tg.src, dst=tg.dst,
+                 weight=tg.weight if tg.weight is not None else np.zeros(0, np.int32),
+                 name=tg.name)
+        return tg, spec
     if name == "cfg1":
         return gen.config1(), gen.CONFIG_SOLVE[1]
     if name == "cfg2":
@@ -76,8 +96,7 @@ def full_size_oracle(workload):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    t = rec.get("oracle_timing")
-    return t
+    return rec.get("oracle_timing")
 
 
 def cpu_baseline(args):
@@ -363,6 +382,10 @@ def main():
                     help="cfg4: time plain calls on every k-th solve of the grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (counter calibration)")
+    ap.add_argument("--graph-cache", default=None,
+                    help=".npz file holding the drawn graph (read when present, else written)")
+    ap.add_argument("--gen-only", action="store_true",
+                    help="draw the workload's graph (into --graph-cache) and stop")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
@@ -378,7 +401,10 @@ def main():
         return
     # inputs are drawn before anything touches the GPU (the generator may use child processes)
     log(f"generating {args.workload}")
-    tg, spec = workload(args.workload, args.gen_workers)
+    tg, spec = workload(args.workload, args.gen_workers, args.graph_cache)
+    if args.gen_only:
+        log(f"drew {tg.name}: N={tg.n_nodes} T={tg.n_slices} E={tg.n_edges}")
+        return
     import torch
     from paper_2608_03695_amd import mslm
 
@@ -448,8 +474,8 @@ def main():
                    "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
         # the HBM-bound loop: level-0 local-moving decisions (every sweep of every iteration)
         "roofline": roofline(nbytes("lm0"), rp["lm0_kernel_ms"], rp["lm0_launches"],
-                             "level-0 decision launches: k_lm_multi<Policy0, View0> (bins up "
-                             "to 1024 entries) and k_lm_block<Policy0, View0, 1024> (larger)"),
+                             "level-0 decision launches: k_lm_multi<Policy0, ViewP> (bins up "
+                             "to 1024 entries), k_lm_block<Policy0, ViewP, 1024> (to 4096) and the hub kernels"),
         # the work of the aggregated levels' decisions (not timed: their launches are short)
         "bytes_all_levels": nbytes("lm"),
         "ms_per_step_median": statistics.median(step_ms),

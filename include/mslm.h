@@ -88,7 +88,10 @@ typedef struct {
 typedef struct {
   double q;                       /* Q rounded to double                                    */
   int32_t n_communities, levels_run, iterations_run, colours_level0;
-  int64_t sweeps, moves, sweep_cap_hits, refine_rounds, merges, splits, exact_fallbacks;
+  int64_t sweeps, moves, sweep_cap_hits, refine_rounds, merges, splits;
+  int64_t exact_fallbacks;        /* big-integer evaluations this solve's units needed; how many
+                                     depends on the order in which the kernels meet candidates
+                                     (batching may change it), the result never does           */
   double ms_total;                /* host wall clock of the call                            */
   double ms_colour, ms_local_move, ms_refine, ms_aggregate, ms_finish;   /* device, by phase */
   double lm_kernel_ms;            /* summed durations of the timed decision launches
@@ -134,6 +137,18 @@ mslm_status mslm_graph_info(const mslm_graph *g, int64_t *n_supra, int64_t *nnz,
 /* Text of the last error on this thread (valid until the next call on this thread). */
 const char *mslm_last_error(void);
 
+/* Route the library's device allocations through a caller's allocator, for example PyTorch's
+ * caching allocator (the package's Python binding installs one); alloc == release == NULL
+ * restores hipMalloc/hipFree.  alloc(bytes, ctx) returns device memory of the current device
+ * (NULL = out of memory, reported as MSLM_ENOMEM); release(ptr, ctx) takes back a block alloc
+ * returned.  Every buffer is released through the pair that allocated it, so the pair may be
+ * changed while graphs exist.  Before a release the library waits for all device work
+ * (hipDeviceSynchronize), so a block can be handed to other work at once.  The pair is global
+ * to the process; the callbacks may run on any thread that calls into the library (including
+ * the request loop's workers).  Errors: EINVAL (one of the two is NULL). */
+mslm_status mslm_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                               void (*release)(void *ptr, void *ctx), void *ctx);
+
 /* ------------------------------------------------------------------ batching */
 /* Many solves (graph x gamma x omega) run as one disjoint-union solve: every kernel launch
  * covers all solves that are still active, and each solve's result is bit-identical to a
@@ -151,19 +166,40 @@ mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs,
                               const mslm_solve *solves, int32_t n_solves, void *hip_stream);
 
 /* ------------------------------------------------------------------ serving */
-/* A request loop that admits clustering requests while the device-memory footprint of
- * admitted work stays within hbm_budget_bytes and at most max_slots requests are in
- * flight.  Requests that arrive while others run are admitted as room frees up and run
- * concurrently on their own streams.  Results equal plain mslm_create + mslm_leiden. */
-mslm_status mslm_server_create(size_t hbm_budget_bytes, int32_t max_slots, mslm_server **out);
-/* Copies the graph (host pointers only) and queues it.  EINVAL if the request alone exceeds
- * the budget. */
+/* A continuous-batching request loop (no counterpart in the paper: a systems layer around the
+ * solve).  Requests are admitted in arrival order; each of max_slots worker slots takes all
+ * admitted requests waiting when it becomes free (up to 64 per group) and runs them as one
+ * batched solve, so up to max_slots groups are on the device at once and requests that arrive
+ * meanwhile join the next free slot.  Device memory: a slot keeps its buffers between groups,
+ * and the sum over slots of the larger of (bytes a slot holds, footprint estimate of the group
+ * it runs) never exceeds hbm_budget_bytes; an idle slot whose buffers keep the queue's head
+ * out releases them.  hip_stream: NULL gives every slot a stream of its own (created on the
+ * current device); otherwise all slots queue their device work on that stream (groups are
+ * still formed concurrently, their device work runs in stream order).  Every result equals
+ * plain mslm_create + mslm_leiden on the same request.  Errors: EINVAL (max_slots outside
+ * 1..16, zero budget), EHIP, ENOMEM. */
+mslm_status mslm_server_create(size_t hbm_budget_bytes, int32_t max_slots, void *hip_stream,
+                               mslm_server **out);
+/* Copies the graph (host pointers only) and queues it.  Errors, before anything is queued:
+ * EINVAL (the graph as for mslm_create, device inputs, parameters, or a footprint above the
+ * budget), EOVERFLOW (2m_s >= 2^31 in a slice or the int64 gain head-room of these gamma and
+ * omega), EUNSUPPORTED.  A request that is accepted cannot fail on these later; should its
+ * group fail on the device, its requests are run again one at a time, so one request's error
+ * is never another's result. */
 mslm_status mslm_server_submit(mslm_server *s, const mslm_graph_desc *desc,
                                const mslm_params *params, uint64_t *ticket);
-/* Waits up to timeout_ms (< 0: forever) for a ticket; EBUSY on timeout.  latency_s is the
- * time from submit to completion. */
+/* Waits up to timeout_ms (< 0: forever) for a ticket; EBUSY on timeout (the ticket stays
+ * valid), EINVAL for an unknown ticket (each ticket is collected once).  latency_s is the time
+ * from submit to completion. */
 mslm_status mslm_server_wait(mslm_server *s, uint64_t ticket, int32_t timeout_ms,
                              int32_t *membership, mslm_result *res, double *latency_s);
+/* Device bytes the slots hold now; the largest total seen at any group's start or end; the
+ * largest total charged against the budget (never above it). */
+mslm_status mslm_server_memory(mslm_server *s, size_t *held_bytes, size_t *peak_held_bytes,
+                               size_t *peak_charged_bytes);
+/* Stops the loop: queued requests end with EINVAL ("server destroyed"), running groups
+ * finish, threads blocked in mslm_server_wait return, then the server is freed.  No call on
+ * the server may start once destroy has begun. */
 void mslm_server_destroy(mslm_server *s);
 
 #ifdef __cplusplus

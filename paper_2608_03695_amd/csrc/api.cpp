@@ -9,365 +9,52 @@
 
 #include "../../include/mslm.h"
 #include "engine.hpp"
+#include "handles.hpp"
+#include "host.hpp"
 #include "server.hpp"
 
 using namespace mslm;
 
-struct mslm_graph {
-  GraphDev g;
-  hipStream_t st = nullptr;
-  Workspace *ws = nullptr;
-  ~mslm_graph() { workspace_free(ws); }
-};
-
-namespace {
-
-thread_local std::string g_err;
-
-mslm_status fail(mslm_status s, const std::string &m) {
-  g_err = m;
-  return s;
-}
-
-int64_t gcd64(int64_t a, int64_t b) {
-  while (b) {
-    int64_t t = a % b;
-    a = b;
-    b = t;
-  }
-  return a;
-}
-
-constexpr int64_t kLim31 = (int64_t)1 << 31;
-
-mslm_status check_fraction(int64_t num, int64_t den, const char *what) {
-  if (num < 0 || den < 1) return fail(MSLM_EINVAL, std::string(what) + ": need numerator >= 0, denominator >= 1");
-  if (num >= kLim31 || den >= kLim31) return fail(MSLM_EOVERFLOW, std::string(what) + ": numerator and denominator must be below 2^31");
-  return MSLM_OK;
-}
-
-// Shape checks that need no device and no edge data.
-mslm_status check_desc_shape(const mslm_graph_desc *d) {
-  if (!d) return fail(MSLM_EINVAL, "desc is NULL");
-  if (d->n_nodes < 1 || d->n_slices < 1) return fail(MSLM_EINVAL, "need n_nodes >= 1 and n_slices >= 1");
-  if (d->n_slices > 64) return fail(MSLM_EUNSUPPORTED, "at most 64 snapshots are supported");
-  if (!d->slice_offsets) return fail(MSLM_EINVAL, "slice_offsets is NULL");
-  if (d->slice_offsets[0] != 0) return fail(MSLM_EINVAL, "slice_offsets[0] must be 0");
-  for (int s = 0; s < d->n_slices; s++)
-    if (d->slice_offsets[s + 1] < d->slice_offsets[s]) return fail(MSLM_EINVAL, "slice_offsets must be non-decreasing");
-  const int64_t E = d->slice_offsets[d->n_slices];
-  if (E > 0 && (!d->src || !d->dst)) return fail(MSLM_EINVAL, "src/dst are NULL");
-  const int64_t n = (int64_t)d->n_nodes * d->n_slices;
-  if ((uint64_t)n * 33u >= 0xffffffffull) return fail(MSLM_EUNSUPPORTED, "N*T*33 must stay below 2^32");
-  if (2 * E + 2 * (int64_t)d->n_nodes * (d->n_slices - 1) >= ((int64_t)1 << 40))
-    return fail(MSLM_EUNSUPPORTED, "too many edges");
-  mslm_status s = check_fraction(d->omega_num, d->omega_den, "omega");
-  if (s != MSLM_OK) return s;
-  return MSLM_OK;
-}
-
-// Edge checks on host inputs (device inputs are checked by a kernel during the build).
-mslm_status check_desc_edges(const mslm_graph_desc *d) {
-  if (d->flags & MSLM_INPUT_ON_DEVICE) return MSLM_OK;
-  const int64_t E = d->slice_offsets[d->n_slices];
-  for (int64_t e = 0; e < E; e++) {
-    int32_t u = d->src[e], x = d->dst[e];
-    if (u < 0 || u >= d->n_nodes || x < 0 || x >= d->n_nodes)
-      return fail(MSLM_EINVAL, "edge " + std::to_string(e) + ": node id out of range");
-    if (u == x) return fail(MSLM_EINVAL, "edge " + std::to_string(e) + ": self-loop");
-    if (d->weight && d->weight[e] < 1) return fail(MSLM_EINVAL, "edge " + std::to_string(e) + ": weight < 1");
-  }
-  return MSLM_OK;
-}
-
-mslm_status make_spec(const mslm_params *p, int64_t def_on, int64_t def_od, SolveSpec &sp) {
-  if (!p) return fail(MSLM_EINVAL, "params is NULL");
-  mslm_status s = check_fraction(p->gamma_num, p->gamma_den, "gamma");
-  if (s != MSLM_OK) return s;
-  int64_t on = def_on, od = def_od;
-  if (p->omega_den != 0) {
-    s = check_fraction(p->omega_num, p->omega_den, "omega");
-    if (s != MSLM_OK) return s;
-    on = p->omega_num;
-    od = p->omega_den;
-  }
-  if (p->max_levels < 1) return fail(MSLM_EINVAL, "max_levels must be >= 1");
-  if (p->max_levels > 1024) return fail(MSLM_EINVAL, "max_levels must be <= 1024");
-  int64_t gg = p->gamma_num ? gcd64(p->gamma_num, p->gamma_den) : p->gamma_den;
-  sp.p = p->gamma_num / gg;
-  sp.q = p->gamma_den / gg;
-  int64_t go = on ? gcd64(on, od) : od;
-  sp.a = on / go;
-  sp.b = od / go;
-  sp.max_levels = p->max_levels;
-  sp.max_iterations = p->max_iterations > 0 ? std::min(p->max_iterations, 32) : 32;
-  sp.max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 32;
-  if (sp.max_sweeps > 32) return fail(MSLM_EINVAL, "max_sweeps must be <= 32");
-  sp.seed = p->seed;
-  return MSLM_OK;
-}
-
-// ------------------------------------------------------------------ exact rational Q
-// Small arbitrary-precision integers for the host-side reduction of Q.
-struct BigU {
-  std::vector<uint32_t> d;   // little endian, no leading zeros
-  void trim() {
-    while (!d.empty() && d.back() == 0) d.pop_back();
-  }
-  bool zero() const { return d.empty(); }
-  static BigU from(uint64_t v) {
-    BigU r;
-    while (v) {
-      r.d.push_back((uint32_t)v);
-      v >>= 32;
-    }
-    return r;
-  }
-  void mul(uint64_t m) {
-    if (m == 0 || d.empty()) {
-      d.clear();
-      return;
-    }
-    unsigned __int128 c = 0;
-    for (auto &x : d) {
-      unsigned __int128 t = (unsigned __int128)x * m + c;
-      x = (uint32_t)t;
-      c = t >> 32;
-    }
-    while (c) {
-      d.push_back((uint32_t)c);
-      c >>= 32;
-    }
-  }
-};
-int cmpu(const BigU &a, const BigU &b) {
-  if (a.d.size() != b.d.size()) return a.d.size() < b.d.size() ? -1 : 1;
-  for (size_t i = a.d.size(); i-- > 0;)
-    if (a.d[i] != b.d[i]) return a.d[i] < b.d[i] ? -1 : 1;
-  return 0;
-}
-BigU addu(const BigU &a, const BigU &b) {
-  BigU r;
-  size_t n = std::max(a.d.size(), b.d.size());
-  r.d.resize(n + 1);
-  uint64_t c = 0;
-  for (size_t i = 0; i < n; i++) {
-    uint64_t t = c + (i < a.d.size() ? a.d[i] : 0) + (i < b.d.size() ? b.d[i] : 0);
-    r.d[i] = (uint32_t)t;
-    c = t >> 32;
-  }
-  r.d[n] = (uint32_t)c;
-  r.trim();
-  return r;
-}
-BigU subu(const BigU &a, const BigU &b) {   // a >= b
-  BigU r;
-  r.d.resize(a.d.size());
-  int64_t br = 0;
-  for (size_t i = 0; i < a.d.size(); i++) {
-    int64_t t = (int64_t)a.d[i] - (i < b.d.size() ? b.d[i] : 0) - br;
-    br = t < 0;
-    if (t < 0) t += (int64_t)1 << 32;
-    r.d[i] = (uint32_t)t;
-  }
-  r.trim();
-  return r;
-}
-// quotient and remainder by shift-subtract long division
-void divmodu(const BigU &a, const BigU &b, BigU &q, BigU &r) {
-  q.d.assign(a.d.size(), 0);
-  r.d.clear();
-  for (size_t i = a.d.size() * 32; i-- > 0;) {
-    // r = 2r + bit
-    uint32_t carry = (a.d[i / 32] >> (i % 32)) & 1u;
-    for (auto &x : r.d) {
-      uint32_t nc = x >> 31;
-      x = (x << 1) | carry;
-      carry = nc;
-    }
-    if (carry) r.d.push_back(carry);
-    if (cmpu(r, b) >= 0) {
-      r = subu(r, b);
-      q.d[i / 32] |= 1u << (i % 32);
-    }
-  }
-  q.trim();
-  r.trim();
-}
-BigU gcdu(BigU a, BigU b) {
-  while (!b.zero()) {
-    BigU q, r;
-    divmodu(a, b, q, r);
-    a = b;
-    b = r;
-  }
-  return a;
-}
-std::string decimal(BigU a) {
-  if (a.zero()) return "0";
-  std::string s;
-  while (!a.zero()) {
-    uint64_t rem = 0;
-    for (size_t i = a.d.size(); i-- > 0;) {
-      uint64_t cur = (rem << 32) | a.d[i];
-      a.d[i] = (uint32_t)(cur / 1000000000u);
-      rem = cur % 1000000000u;
-    }
-    a.trim();
-    char buf[16];
-    snprintf(buf, sizeof buf, a.zero() ? "%llu" : "%09llu", (unsigned long long)rem);
-    s = std::string(buf) + s;
-  }
-  return s;
-}
-struct BigS {   // signed
-  bool neg = false;
-  BigU m;
-};
-BigS adds(const BigS &a, const BigS &b) {
-  BigS r;
-  if (a.neg == b.neg) {
-    r.m = addu(a.m, b.m);
-    r.neg = a.neg;
-  } else if (cmpu(a.m, b.m) >= 0) {
-    r.m = subu(a.m, b.m);
-    r.neg = a.neg;
-  } else {
-    r.m = subu(b.m, a.m);
-    r.neg = b.neg;
-  }
-  if (r.m.zero()) r.neg = false;
-  return r;
-}
-BigS mk(int64_t v) {
-  BigS r;
-  r.neg = v < 0;
-  r.m = BigU::from(v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v);
-  return r;
-}
-double to_double(const BigU &a) {
-  double x = 0;
-  for (size_t i = a.d.size(); i-- > 0;) x = x * 4294967296.0 + a.d[i];
-  return x;
-}
-
-// Q = (sum_s [W_s - gamma SS_s / 2m_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1)),
-// multiplied through by b*q*prod(2m_s != 0) and reduced.
-mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa, int64_t ob,
-                    std::string &num, std::string &den, double &qd) {
-  std::vector<int64_t> nzm;
-  for (int s = 0; s < T; s++)
-    if (c[2 * T + s] > 0) nzm.push_back(c[2 * T + s]);
-  BigU L = BigU::from(1);
-  for (int64_t m : nzm) L.mul((uint64_t)m);
-  BigS sumN;   // numerator
-  int64_t sumW = 0, sum2m = 0;
-  for (int s = 0; s < T; s++) {
-    sumW += c[s];
-    sum2m += c[2 * T + s];
-  }
-  BigS t = mk(sumW);
-  t.m.mul((uint64_t)ob);
-  t.m.mul((uint64_t)gq);
-  t.m = [&] { BigU x = t.m; for (int64_t m : nzm) x.mul((uint64_t)m); return x; }();
-  sumN = adds(sumN, t);
-  for (int s = 0; s < T; s++) {
-    int64_t m2 = c[2 * T + s];
-    if (m2 <= 0) continue;
-    BigS u = mk(c[T + s]);
-    u.m.mul((uint64_t)ob);
-    u.m.mul((uint64_t)gp);
-    bool skipped = false;
-    for (int64_t m : nzm) {
-      if (!skipped && m == m2) {
-        skipped = true;
-        continue;
-      }
-      u.m.mul((uint64_t)m);
-    }
-    u.neg = !u.m.zero();
-    sumN = adds(sumN, u);
-  }
-  BigS iv = mk(c[3 * T]);
-  iv.m.mul((uint64_t)oa);
-  iv.m.mul((uint64_t)gq);
-  for (int64_t m : nzm) iv.m.mul((uint64_t)m);
-  sumN = adds(sumN, iv);
-  // denominator: b*q*L*sum 2m_s + 2*a*q*L*N*(T-1)
-  BigU d1 = BigU::from((uint64_t)sum2m);
-  d1.mul((uint64_t)ob);
-  d1.mul((uint64_t)gq);
-  for (int64_t m : nzm) d1.mul((uint64_t)m);
-  BigU d2 = BigU::from(2);
-  d2.mul((uint64_t)oa);
-  d2.mul((uint64_t)gq);
-  d2.mul((uint64_t)N);
-  d2.mul((uint64_t)(T - 1));
-  for (int64_t m : nzm) d2.mul((uint64_t)m);
-  BigU D = addu(d1, d2);
-  if (D.zero()) {   // empty supra-graph: Q = 0 by convention
-    num = "0";
-    den = "1";
-    qd = 0.0;
-    return MSLM_OK;
-  }
-  BigU g = gcdu(sumN.m, D);
-  BigU qn, rn, qdn, rdn;
-  if (sumN.m.zero()) {
-    num = "0";
-    den = "1";
-    qd = 0.0;
-    return MSLM_OK;
-  }
-  divmodu(sumN.m, g, qn, rn);
-  divmodu(D, g, qdn, rdn);
-  num = (sumN.neg ? "-" : "") + decimal(qn);
-  den = decimal(qdn);
-  // double: scale both to their top 64 bits
-  size_t sh = std::max(qn.d.size(), qdn.d.size());
-  sh = sh > 2 ? sh - 2 : 0;
-  BigU a = qn, b = qdn;
-  a.d.erase(a.d.begin(), a.d.begin() + std::min(sh, a.d.size()));
-  b.d.erase(b.d.begin(), b.d.begin() + std::min(sh, b.d.size()));
-  qd = (sumN.neg ? -1.0 : 1.0) * to_double(a) / to_double(b);
-  return MSLM_OK;
-}
-
-}  // namespace
-
 namespace mslm {
-// shared with the request loop in server.cpp
-mslm_status api_fail(mslm_status s, const std::string &m) { return fail(s, m); }
-mslm_status api_check_desc(const mslm_graph_desc *d) {
-  mslm_status s = check_desc_shape(d);
-  return s != MSLM_OK ? s : check_desc_edges(d);
-}
-mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, SolveSpec &sp) {
-  return make_spec(p, on, od, sp);
-}
 void api_finish(const GraphDev &g, const SolveSpec &sp, SolveOut &o, mslm_result *res) {
   std::string a, b;
   double qd = 0;
-  q_exact(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
+  api_q_exact(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
   o.res.q = qd;
   if (res) *res = o.res;
 }
 }  // namespace mslm
 
+namespace {
+inline mslm_status fail(mslm_status s, const std::string &m) { return api_fail(s, m); }
+}  // namespace
+
 // ------------------------------------------------------------------ exported functions
 extern "C" {
 
-const char *mslm_last_error(void) { return g_err.c_str(); }
+const char *mslm_last_error(void) { return api_error_text(); }
+
+mslm_status mslm_set_allocator(void *(*alloc)(size_t, void *), void (*release)(void *, void *),
+                               void *ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(MSLM_EINVAL, "alloc and release must both be set or both be NULL");
+  DevAlloc a;
+  a.alloc = alloc;
+  a.release = release;
+  a.ctx = alloc ? ctx : nullptr;
+  set_allocator(a);
+  api_clear_error();
+  return MSLM_OK;
+}
 
 mslm_status mslm_create(const mslm_graph_desc *desc, void *hip_stream, mslm_graph **out) {
   if (!out) return fail(MSLM_EINVAL, "out is NULL");
   *out = nullptr;
-  mslm_status s = check_desc_shape(desc);
-  if (s != MSLM_OK) return s;
-  s = check_desc_edges(desc);
+  mslm_status s = api_check_desc(desc);
   if (s != MSLM_OK) return s;
   std::unique_ptr<mslm_graph> h(new mslm_graph());
   h->st = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&h->device) != hipSuccess) return fail(MSLM_EHIP, "no HIP device");
   try {
     h->ws = workspace_new();
     h->g.omega_num = desc->omega_num;
@@ -381,7 +68,7 @@ mslm_status mslm_create(const mslm_graph_desc *desc, void *hip_stream, mslm_grap
     return fail(MSLM_ENOMEM, e.what());
   }
   *out = h.release();
-  g_err.clear();
+  api_clear_error();
   return MSLM_OK;
 }
 
@@ -407,30 +94,22 @@ mslm_status mslm_q_exact(const int64_t *qc, int32_t T, int32_t N, int64_t gamma_
                          int64_t gamma_den, int64_t omega_num, int64_t omega_den, char *num,
                          size_t num_cap, char *den, size_t den_cap) {
   if (!qc || !num || !den || T < 1 || T > 64 || N < 1) return fail(MSLM_EINVAL, "bad arguments");
-  mslm_status s = check_fraction(gamma_num, gamma_den, "gamma");
+  mslm_status s = api_check_fraction(gamma_num, gamma_den, "gamma");
   if (s != MSLM_OK) return s;
-  s = check_fraction(omega_num, omega_den, "omega");
+  s = api_check_fraction(omega_num, omega_den, "omega");
   if (s != MSLM_OK) return s;
-  int64_t gg = gamma_num ? gcd64(gamma_num, gamma_den) : gamma_den;
-  int64_t go = omega_num ? gcd64(omega_num, omega_den) : omega_den;
+  int64_t gg = gamma_num ? api_gcd(gamma_num, gamma_den) : gamma_den;
+  int64_t go = omega_num ? api_gcd(omega_num, omega_den) : omega_den;
   std::string a, b;
   double qd;
-  q_exact(qc, T, N, gamma_num / gg, gamma_den / gg, omega_num / go, omega_den / go, a, b, qd);
+  api_q_exact(qc, T, N, gamma_num / gg, gamma_den / gg, omega_num / go, omega_den / go, a, b, qd);
   if (a.size() + 1 > num_cap || b.size() + 1 > den_cap) return fail(MSLM_EINVAL, "buffer too small");
   memcpy(num, a.c_str(), a.size() + 1);
   memcpy(den, b.c_str(), b.size() + 1);
   return MSLM_OK;
 }
 
-size_t mslm_footprint_bytes(const mslm_graph_desc *d) {
-  if (check_desc_shape(d) != MSLM_OK) return 0;
-  const int64_t n = (int64_t)d->n_nodes * d->n_slices;
-  const int64_t E = d->slice_offsets[d->n_slices];
-  const int64_t nnz = 2 * E + 2 * (int64_t)d->n_nodes * (d->n_slices - 1);
-  // resident graph + peak of one solve (aggregation keys and values double-buffered,
-  // sort scratch, two aggregated levels, per-unit state and the Sigma tables)
-  return (size_t)(8 * (n + 1) + 8 * nnz + 4 * n) + (size_t)(88 * nnz + 320 * n) + (64u << 20);
-}
+size_t mslm_footprint_bytes(const mslm_graph_desc *d) { return footprint_estimate(d); }
 
 static mslm_status finish_result(const GraphDev &g, const SolveSpec &sp, SolveOut &o,
                                  mslm_result *res) {
@@ -443,7 +122,7 @@ mslm_status mslm_leiden(mslm_graph *g, const mslm_params *params, int32_t *membe
   if (!g) return fail(MSLM_EINVAL, "graph is NULL");
   if (!membership) return fail(MSLM_EINVAL, "membership is NULL");
   SolveSpec sp;
-  mslm_status s = make_spec(params, g->g.omega_num, g->g.omega_den, sp);
+  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, sp);
   if (s != MSLM_OK) return s;
   std::vector<SolveOut> outs(1);
   if (params->flags & MSLM_OUTPUT_ON_DEVICE) outs[0].dev_membership = membership;
@@ -458,7 +137,7 @@ mslm_status mslm_leiden(mslm_graph *g, const mslm_params *params, int32_t *membe
   if (!(params->flags & MSLM_OUTPUT_ON_DEVICE))
     memcpy(membership, outs[0].membership.data(), sizeof(int32_t) * g->g.n);
   finish_result(g->g, sp, outs[0], res);
-  g_err.clear();
+  api_clear_error();
   return MSLM_OK;
 }
 
@@ -472,7 +151,7 @@ mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs, const
     int gi = solves[i].graph;
     if (gi < 0 || gi >= n_graphs || !graphs[gi]) return fail(MSLM_EINVAL, "solve names an invalid graph");
     if (!solves[i].membership) return fail(MSLM_EINVAL, "solve has no membership buffer");
-    mslm_status s = make_spec(&solves[i].params, graphs[gi]->g.omega_num, graphs[gi]->g.omega_den, specs[i]);
+    mslm_status s = api_make_spec(&solves[i].params, graphs[gi]->g.omega_num, graphs[gi]->g.omega_den, specs[i]);
     if (s != MSLM_OK) return s;
     gs[i] = &graphs[gi]->g;
   }
@@ -509,7 +188,7 @@ mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs, const
     return fail(MSLM_ENOMEM, e.what());
   }
   workspace_free(ws);
-  g_err.clear();
+  api_clear_error();
   return MSLM_OK;
 }
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "engine.hpp"
@@ -56,6 +57,29 @@ void d2h(T *dst, const T *src, int64_t n, hipStream_t st) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ device memory source
+namespace {
+std::mutex g_alloc_mu;
+DevAlloc g_alloc;
+}  // namespace
+
+DevAlloc current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+void set_allocator(const DevAlloc &a) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = a;
+}
+Arena *&thread_arena() {
+  static thread_local Arena *a = nullptr;
+  return a;
+}
+std::atomic<int64_t> *&thread_account() {
+  static thread_local std::atomic<int64_t> *a = nullptr;
+  return a;
+}
+
 // ------------------------------------------------------------------ workspace
 struct LevelBufs {
   Buf rp, col, w, pp, ps, pk, usolve;
@@ -87,6 +111,10 @@ struct Workspace {
   Buf s_redo;                             // per-solve redo flags of a sweep
   Buf ref_wide, ref_wcnt;                 // refinement units with long rows, and their count
   Buf ref_snap_a, ref_snap_p;             // active flags and proposal stamps before a round
+  Buf ref_keep;                           // active flags of solves that skip a round's redo
+  // level 0 in colour-batch order (local-moving sweeps)
+  Buf p_pos, p_deg, p_rp, p_col, p_w, p_k, p_slice, p_solve, p_iota, p_comm, p_goff, p_glg,
+      p_wide, p_nwide;
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };

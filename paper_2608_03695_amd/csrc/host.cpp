@@ -1,0 +1,383 @@
+// Host-side checks and exact arithmetic of the C ABI: input validation, parameter reduction,
+// the int64 head-room preconditions, the exact reduced fraction Q of Eq. 6 from its integer
+// components, and the thread-local error text.  No HIP: this file also builds for the host
+// alone (the sanitizer test compiles it with g++).
+#include "host.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace mslm;
+
+namespace {
+
+thread_local std::string g_err;
+
+mslm_status fail(mslm_status s, const std::string &m) {
+  g_err = m;
+  return s;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+constexpr int64_t kLim31 = (int64_t)1 << 31;
+
+mslm_status check_fraction(int64_t num, int64_t den, const char *what) {
+  if (num < 0 || den < 1) return fail(MSLM_EINVAL, std::string(what) + ": need numerator >= 0, denominator >= 1");
+  if (num >= kLim31 || den >= kLim31) return fail(MSLM_EOVERFLOW, std::string(what) + ": numerator and denominator must be below 2^31");
+  return MSLM_OK;
+}
+
+// Shape checks that need no device and no edge data.
+mslm_status check_desc_shape(const mslm_graph_desc *d) {
+  if (!d) return fail(MSLM_EINVAL, "desc is NULL");
+  if (d->n_nodes < 1 || d->n_slices < 1) return fail(MSLM_EINVAL, "need n_nodes >= 1 and n_slices >= 1");
+  if (d->n_slices > 64) return fail(MSLM_EUNSUPPORTED, "at most 64 snapshots are supported");
+  if (!d->slice_offsets) return fail(MSLM_EINVAL, "slice_offsets is NULL");
+  if (d->slice_offsets[0] != 0) return fail(MSLM_EINVAL, "slice_offsets[0] must be 0");
+  for (int s = 0; s < d->n_slices; s++)
+    if (d->slice_offsets[s + 1] < d->slice_offsets[s]) return fail(MSLM_EINVAL, "slice_offsets must be non-decreasing");
+  const int64_t E = d->slice_offsets[d->n_slices];
+  if (E > 0 && (!d->src || !d->dst)) return fail(MSLM_EINVAL, "src/dst are NULL");
+  const int64_t n = (int64_t)d->n_nodes * d->n_slices;
+  if ((uint64_t)n * 33u >= 0xffffffffull) return fail(MSLM_EUNSUPPORTED, "N*T*33 must stay below 2^32");
+  if (2 * E + 2 * (int64_t)d->n_nodes * (d->n_slices - 1) >= ((int64_t)1 << 40))
+    return fail(MSLM_EUNSUPPORTED, "too many edges");
+  mslm_status s = check_fraction(d->omega_num, d->omega_den, "omega");
+  if (s != MSLM_OK) return s;
+  return MSLM_OK;
+}
+
+// Edge checks on host inputs (device inputs are checked by a kernel during the build).
+mslm_status check_desc_edges(const mslm_graph_desc *d) {
+  if (d->flags & MSLM_INPUT_ON_DEVICE) return MSLM_OK;
+  const int64_t E = d->slice_offsets[d->n_slices];
+  for (int64_t e = 0; e < E; e++) {
+    int32_t u = d->src[e], x = d->dst[e];
+    if (u < 0 || u >= d->n_nodes || x < 0 || x >= d->n_nodes)
+      return fail(MSLM_EINVAL, "edge " + std::to_string(e) + ": node id out of range");
+    if (u == x) return fail(MSLM_EINVAL, "edge " + std::to_string(e) + ": self-loop");
+    if (d->weight && d->weight[e] < 1) return fail(MSLM_EINVAL, "edge " + std::to_string(e) + ": weight < 1");
+  }
+  return MSLM_OK;
+}
+
+mslm_status make_spec(const mslm_params *p, int64_t def_on, int64_t def_od, SolveSpec &sp) {
+  if (!p) return fail(MSLM_EINVAL, "params is NULL");
+  mslm_status s = check_fraction(p->gamma_num, p->gamma_den, "gamma");
+  if (s != MSLM_OK) return s;
+  int64_t on = def_on, od = def_od;
+  if (p->omega_den != 0) {
+    s = check_fraction(p->omega_num, p->omega_den, "omega");
+    if (s != MSLM_OK) return s;
+    on = p->omega_num;
+    od = p->omega_den;
+  }
+  if (p->max_levels < 1) return fail(MSLM_EINVAL, "max_levels must be >= 1");
+  if (p->max_levels > 1024) return fail(MSLM_EINVAL, "max_levels must be <= 1024");
+  int64_t gg = p->gamma_num ? gcd64(p->gamma_num, p->gamma_den) : p->gamma_den;
+  sp.p = p->gamma_num / gg;
+  sp.q = p->gamma_den / gg;
+  int64_t go = on ? gcd64(on, od) : od;
+  sp.a = on / go;
+  sp.b = od / go;
+  sp.max_levels = p->max_levels;
+  sp.max_iterations = p->max_iterations > 0 ? std::min(p->max_iterations, 32) : 32;
+  sp.max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 32;
+  if (sp.max_sweeps > 32) return fail(MSLM_EINVAL, "max_sweeps must be <= 32");
+  sp.seed = p->seed;
+  return MSLM_OK;
+}
+
+// ------------------------------------------------------------------ exact rational Q
+// Small arbitrary-precision integers for the host-side reduction of Q.
+struct BigU {
+  std::vector<uint32_t> d;   // little endian, no leading zeros
+  void trim() {
+    while (!d.empty() && d.back() == 0) d.pop_back();
+  }
+  bool zero() const { return d.empty(); }
+  static BigU from(uint64_t v) {
+    BigU r;
+    while (v) {
+      r.d.push_back((uint32_t)v);
+      v >>= 32;
+    }
+    return r;
+  }
+  void mul(uint64_t m) {
+    if (m == 0 || d.empty()) {
+      d.clear();
+      return;
+    }
+    unsigned __int128 c = 0;
+    for (auto &x : d) {
+      unsigned __int128 t = (unsigned __int128)x * m + c;
+      x = (uint32_t)t;
+      c = t >> 32;
+    }
+    while (c) {
+      d.push_back((uint32_t)c);
+      c >>= 32;
+    }
+  }
+};
+int cmpu(const BigU &a, const BigU &b) {
+  if (a.d.size() != b.d.size()) return a.d.size() < b.d.size() ? -1 : 1;
+  for (size_t i = a.d.size(); i-- > 0;)
+    if (a.d[i] != b.d[i]) return a.d[i] < b.d[i] ? -1 : 1;
+  return 0;
+}
+BigU addu(const BigU &a, const BigU &b) {
+  BigU r;
+  size_t n = std::max(a.d.size(), b.d.size());
+  r.d.resize(n + 1);
+  uint64_t c = 0;
+  for (size_t i = 0; i < n; i++) {
+    uint64_t t = c + (i < a.d.size() ? a.d[i] : 0) + (i < b.d.size() ? b.d[i] : 0);
+    r.d[i] = (uint32_t)t;
+    c = t >> 32;
+  }
+  r.d[n] = (uint32_t)c;
+  r.trim();
+  return r;
+}
+BigU subu(const BigU &a, const BigU &b) {   // a >= b
+  BigU r;
+  r.d.resize(a.d.size());
+  int64_t br = 0;
+  for (size_t i = 0; i < a.d.size(); i++) {
+    int64_t t = (int64_t)a.d[i] - (i < b.d.size() ? b.d[i] : 0) - br;
+    br = t < 0;
+    if (t < 0) t += (int64_t)1 << 32;
+    r.d[i] = (uint32_t)t;
+  }
+  r.trim();
+  return r;
+}
+// quotient and remainder by shift-subtract long division
+void divmodu(const BigU &a, const BigU &b, BigU &q, BigU &r) {
+  q.d.assign(a.d.size(), 0);
+  r.d.clear();
+  for (size_t i = a.d.size() * 32; i-- > 0;) {
+    // r = 2r + bit
+    uint32_t carry = (a.d[i / 32] >> (i % 32)) & 1u;
+    for (auto &x : r.d) {
+      uint32_t nc = x >> 31;
+      x = (x << 1) | carry;
+      carry = nc;
+    }
+    if (carry) r.d.push_back(carry);
+    if (cmpu(r, b) >= 0) {
+      r = subu(r, b);
+      q.d[i / 32] |= 1u << (i % 32);
+    }
+  }
+  q.trim();
+  r.trim();
+}
+BigU gcdu(BigU a, BigU b) {
+  while (!b.zero()) {
+    BigU q, r;
+    divmodu(a, b, q, r);
+    a = b;
+    b = r;
+  }
+  return a;
+}
+std::string decimal(BigU a) {
+  if (a.zero()) return "0";
+  std::string s;
+  while (!a.zero()) {
+    uint64_t rem = 0;
+    for (size_t i = a.d.size(); i-- > 0;) {
+      uint64_t cur = (rem << 32) | a.d[i];
+      a.d[i] = (uint32_t)(cur / 1000000000u);
+      rem = cur % 1000000000u;
+    }
+    a.trim();
+    char buf[16];
+    snprintf(buf, sizeof buf, a.zero() ? "%llu" : "%09llu", (unsigned long long)rem);
+    s = std::string(buf) + s;
+  }
+  return s;
+}
+struct BigS {   // signed
+  bool neg = false;
+  BigU m;
+};
+BigS adds(const BigS &a, const BigS &b) {
+  BigS r;
+  if (a.neg == b.neg) {
+    r.m = addu(a.m, b.m);
+    r.neg = a.neg;
+  } else if (cmpu(a.m, b.m) >= 0) {
+    r.m = subu(a.m, b.m);
+    r.neg = a.neg;
+  } else {
+    r.m = subu(b.m, a.m);
+    r.neg = b.neg;
+  }
+  if (r.m.zero()) r.neg = false;
+  return r;
+}
+BigS mk(int64_t v) {
+  BigS r;
+  r.neg = v < 0;
+  r.m = BigU::from(v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v);
+  return r;
+}
+double to_double(const BigU &a) {
+  double x = 0;
+  for (size_t i = a.d.size(); i-- > 0;) x = x * 4294967296.0 + a.d[i];
+  return x;
+}
+
+// Q = (sum_s [W_s - gamma SS_s / 2m_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1)),
+// multiplied through by b*q*prod(2m_s != 0) and reduced.
+mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa, int64_t ob,
+                    std::string &num, std::string &den, double &qd) {
+  std::vector<int64_t> nzm;
+  for (int s = 0; s < T; s++)
+    if (c[2 * T + s] > 0) nzm.push_back(c[2 * T + s]);
+  BigU L = BigU::from(1);
+  for (int64_t m : nzm) L.mul((uint64_t)m);
+  BigS sumN;   // numerator
+  int64_t sumW = 0, sum2m = 0;
+  for (int s = 0; s < T; s++) {
+    sumW += c[s];
+    sum2m += c[2 * T + s];
+  }
+  BigS t = mk(sumW);
+  t.m.mul((uint64_t)ob);
+  t.m.mul((uint64_t)gq);
+  t.m = [&] { BigU x = t.m; for (int64_t m : nzm) x.mul((uint64_t)m); return x; }();
+  sumN = adds(sumN, t);
+  for (int s = 0; s < T; s++) {
+    int64_t m2 = c[2 * T + s];
+    if (m2 <= 0) continue;
+    BigS u = mk(c[T + s]);
+    u.m.mul((uint64_t)ob);
+    u.m.mul((uint64_t)gp);
+    bool skipped = false;
+    for (int64_t m : nzm) {
+      if (!skipped && m == m2) {
+        skipped = true;
+        continue;
+      }
+      u.m.mul((uint64_t)m);
+    }
+    u.neg = !u.m.zero();
+    sumN = adds(sumN, u);
+  }
+  BigS iv = mk(c[3 * T]);
+  iv.m.mul((uint64_t)oa);
+  iv.m.mul((uint64_t)gq);
+  for (int64_t m : nzm) iv.m.mul((uint64_t)m);
+  sumN = adds(sumN, iv);
+  // denominator: b*q*L*sum 2m_s + 2*a*q*L*N*(T-1)
+  BigU d1 = BigU::from((uint64_t)sum2m);
+  d1.mul((uint64_t)ob);
+  d1.mul((uint64_t)gq);
+  for (int64_t m : nzm) d1.mul((uint64_t)m);
+  BigU d2 = BigU::from(2);
+  d2.mul((uint64_t)oa);
+  d2.mul((uint64_t)gq);
+  d2.mul((uint64_t)N);
+  d2.mul((uint64_t)(T - 1));
+  for (int64_t m : nzm) d2.mul((uint64_t)m);
+  BigU D = addu(d1, d2);
+  if (D.zero()) {   // empty supra-graph: Q = 0 by convention
+    num = "0";
+    den = "1";
+    qd = 0.0;
+    return MSLM_OK;
+  }
+  BigU g = gcdu(sumN.m, D);
+  BigU qn, rn, qdn, rdn;
+  if (sumN.m.zero()) {
+    num = "0";
+    den = "1";
+    qd = 0.0;
+    return MSLM_OK;
+  }
+  divmodu(sumN.m, g, qn, rn);
+  divmodu(D, g, qdn, rdn);
+  num = (sumN.neg ? "-" : "") + decimal(qn);
+  den = decimal(qdn);
+  // double: scale both to their top 64 bits
+  size_t sh = std::max(qn.d.size(), qdn.d.size());
+  sh = sh > 2 ? sh - 2 : 0;
+  BigU a = qn, b = qdn;
+  a.d.erase(a.d.begin(), a.d.begin() + std::min(sh, a.d.size()));
+  b.d.erase(b.d.begin(), b.d.begin() + std::min(sh, b.d.size()));
+  qd = (sumN.neg ? -1.0 : 1.0) * to_double(a) / to_double(b);
+  return MSLM_OK;
+}
+
+}  // namespace
+
+namespace mslm {
+
+mslm_status api_fail(mslm_status s, const std::string &m) { return fail(s, m); }
+void api_clear_error() { g_err.clear(); }
+const char *api_error_text() { return g_err.c_str(); }
+size_t solve_scratch_estimate(int64_t n, int64_t nnz) {
+  // aggregation keys and values double-buffered, sort scratch, two aggregated levels,
+  // per-unit state and the Sigma tables
+  return (size_t)(88 * nnz + 320 * n) + ((size_t)1 << 20);
+}
+size_t footprint_estimate(const mslm_graph_desc *d) {
+  if (check_desc_shape(d) != MSLM_OK) return 0;
+  const int64_t n = (int64_t)d->n_nodes * d->n_slices;
+  const int64_t E = d->slice_offsets[d->n_slices];
+  const int64_t nnz = 2 * E + 2 * (int64_t)d->n_nodes * (d->n_slices - 1);
+  // resident graph + peak of one solve
+  return (size_t)(8 * (n + 1) + 8 * nnz + 4 * n) + solve_scratch_estimate(n, nnz) + (64u << 20);
+}
+mslm_status api_check_shape(const mslm_graph_desc *d) { return check_desc_shape(d); }
+mslm_status api_check_desc(const mslm_graph_desc *d) {
+  mslm_status s = check_desc_shape(d);
+  return s != MSLM_OK ? s : check_desc_edges(d);
+}
+mslm_status api_check_fraction(int64_t num, int64_t den, const char *what) {
+  return check_fraction(num, den, what);
+}
+int64_t api_gcd(int64_t a, int64_t b) { return gcd64(a, b); }
+mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, SolveSpec &sp) {
+  return make_spec(p, on, od, sp);
+}
+mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
+                        int64_t ob, std::string &num, std::string &den, double &qd) {
+  return q_exact(c, T, N, gp, gq, oa, ob, num, den, qd);
+}
+// The int64 head-room preconditions of a solve on host edge lists, taken before any device
+// work: every slice's total degree 2m_s < 2^31 (build) and q*S*(b*S + 2a) < 2^62,
+// p*b*S^2 < 2^62 with S = max(2m_s, 1) (level-0 gains); the same checks the device path
+// makes, so a request that passes them cannot fail on them later.
+mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp) {
+  for (int s = 0; s < d->n_slices; s++) {
+    int64_t two_m = 0;
+    for (int64_t e = d->slice_offsets[s]; e < d->slice_offsets[s + 1]; e++) {
+      two_m += 2 * (int64_t)(d->weight ? d->weight[e] : 1);
+      if (two_m >= kLim31) return fail(MSLM_EOVERFLOW, "a slice's total degree 2m_s reaches 2^31");
+    }
+    const __int128 S = two_m > 0 ? two_m : 1;
+    const __int128 a1 = (__int128)sp.q * S * ((__int128)sp.b * S + 2 * sp.a);
+    const __int128 a2 = (__int128)sp.p * sp.b * S * S;
+    if (a1 >= ((__int128)1 << 62) || a2 >= ((__int128)1 << 62))
+      return fail(MSLM_EOVERFLOW, "gain head-room: q*2m_s*w or p*b*k*Sigma reaches 2^62");
+  }
+  return MSLM_OK;
+}
+
+}  // namespace mslm

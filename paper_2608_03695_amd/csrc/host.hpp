@@ -1,0 +1,38 @@
+// Host-side checks and exact arithmetic of the C ABI (host.cpp); no HIP.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mslm.h"
+
+namespace mslm {
+
+// One solve's reduced parameters: gamma = p/q, omega = a/b.
+struct SolveSpec {
+  int64_t p = 1, q = 1, a = 1, b = 1;
+  int32_t max_levels = 32, max_iterations = 2, max_sweeps = 32;
+  uint64_t seed = 0;
+};
+
+mslm_status api_fail(mslm_status s, const std::string &m);   // sets the error text
+void api_clear_error();
+const char *api_error_text();
+mslm_status api_check_shape(const mslm_graph_desc *d);
+mslm_status api_check_desc(const mslm_graph_desc *d);        // shape, then host edge lists
+mslm_status api_check_fraction(int64_t num, int64_t den, const char *what);
+int64_t api_gcd(int64_t a, int64_t b);
+mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, SolveSpec &sp);
+// The int64 head-room preconditions of a solve on host edge lists (2m_s < 2^31 per slice,
+// q*S*(b*S + 2a) < 2^62 and p*b*S^2 < 2^62 with S = max(2m_s, 1)).
+mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp);
+// Q of Eq. 6 from its 3T+1 components as a reduced decimal fraction and the nearest double.
+mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
+                        int64_t ob, std::string &num, std::string &den, double &qd);
+// Device bytes of one solve's work buffers on a resident graph (upper estimate), and of a
+// graph plus one solve.
+size_t solve_scratch_estimate(int64_t n, int64_t nnz);
+size_t footprint_estimate(const mslm_graph_desc *d);
+
+}  // namespace mslm

@@ -31,7 +31,7 @@ struct SolveDev {
   const int64_t *uoff;                 // first unit of the solve at the current level
   const int32_t *sfirst;               // first global slice of the solve
   const int64_t *S;                    // per global slice: 2m_s, or 1 for an empty slice
-  int64_t *fallbacks;                  // exact-comparison counter
+  int64_t *fallbacks;                  // exact-comparison counter per solve
   uint32_t *redo;                      // per solve: a sweep met a near-tie it could not settle
 };
 
@@ -47,23 +47,85 @@ struct View0 {
   const int32_t *uslice;   // global slice of each unit
   const int64_t *sstart;   // [slices + 1] first unit of each global slice
   const int32_t *usolve;   // solve of each unit
+  int64_t N1 = 0;          // one solve: nodes per slice (slice and solve follow from the id)
+  double invN1 = 0.0;      // 1 / N1
   struct Row {
     int64_t lo, hi, slo, shi, a, b;
   };
+  // slice of unit v: v / N1 for one solve (a double estimate corrected by one step either
+  // way, exact for every v < 2^32), else the stored slice
+  __device__ int slice_of(int64_t v) const {
+    if (N1 == 0) return uslice[v];
+    int64_t q = (int64_t)((double)v * invN1);
+    if (q * N1 > v) q--;
+    else if ((q + 1) * N1 <= v) q++;
+    return (int)q;
+  }
+  __device__ int solve_of(int64_t v) const { return N1 ? 0 : usolve[v]; }
   __device__ Row row(int64_t v, const SolveDev &sd) const {
-    int gs = uslice[v];
-    int j = usolve[v];
-    return Row{rp[v], rp[v + 1], sstart[gs], sstart[gs + 1], sd.a[j], sd.b[j]};
+    const int gs = slice_of(v);
+    const int j = solve_of(v);
+    const int64_t slo = N1 ? (int64_t)gs * N1 : sstart[gs];
+    const int64_t shi = N1 ? slo + N1 : sstart[gs + 1];
+    return Row{rp[v], rp[v + 1], slo, shi, sd.a[j], sd.b[j]};
   }
   __device__ int64_t wt(const Row &r, int64_t e, int32_t x) const {
     return (x >= r.slo && x < r.shi) ? r.b * (w ? (int64_t)w[e] : 1) : r.a;
   }
+  // neighbour of entry e and its scaled weight
+  __device__ int64_t nbr(const Row &r, int64_t e, int64_t &ww) const {
+    const int32_t x = col[e];
+    ww = wt(r, e, x);
+    return x;
+  }
+  __device__ int64_t orig(int64_t v) const { return v; }
   __device__ int plen(int64_t v) const { return k[v] > 0 ? 1 : 0; }
   __device__ void pent(int64_t v, int, int &gs, int64_t &kk) const {
-    gs = uslice[v];
+    gs = slice_of(v);
     kk = k[v];
   }
   __device__ int64_t degree(int64_t v) const { return rp[v + 1] - rp[v]; }
+};
+
+// Level 0 in colour-batch order, for the local-moving sweeps: the level's units are stored in
+// the order of their colour batches (colour, degree bin, id), so a batch is one contiguous
+// range of positions whose rows, degrees, slices and labels are read in sequence; only the
+// neighbours' labels and the Sigma probes stay random.  Entries hold neighbour positions,
+// with bit 31 set on the coupling entries (scaled weight a); labels and priorities keep the
+// unit ids (orig), so every decision is the one the id-ordered level makes.
+struct ViewP {
+  static constexpr bool kLevel0 = true;
+  const int64_t *rp;       // [n+1] rows by position
+  const int32_t *col;      // neighbour position | coupling << 31
+  const int32_t *w;        // raw intra weight per entry, or nullptr for unit weights
+  const int32_t *k;        // intra degree by position
+  const int32_t *slice;    // global slice by position
+  const int32_t *solve;    // solve by position, or nullptr (one solve)
+  const int32_t *uid;      // unit id by position
+  struct Row {
+    int64_t lo, hi, a, b;
+  };
+  __device__ int solve_of(int64_t i) const { return solve ? solve[i] : 0; }
+  __device__ Row row(int64_t i, const SolveDev &sd) const {
+    const int j = solve_of(i);
+    return Row{rp[i], rp[i + 1], sd.a[j], sd.b[j]};
+  }
+  __device__ int64_t nbr(const Row &r, int64_t e, int64_t &ww) const {
+    const int32_t raw = col[e];
+    if (raw < 0) {
+      ww = r.a;
+      return raw & 0x7fffffff;
+    }
+    ww = r.b * (w ? (int64_t)w[e] : 1);
+    return raw;
+  }
+  __device__ int64_t orig(int64_t i) const { return uid[i]; }
+  __device__ int plen(int64_t i) const { return k[i] > 0 ? 1 : 0; }
+  __device__ void pent(int64_t i, int, int &gs, int64_t &kk) const {
+    gs = slice[i];
+    kk = k[i];
+  }
+  __device__ int64_t degree(int64_t i) const { return rp[i + 1] - rp[i]; }
 };
 
 // Aggregated levels: scaled int64 weights, per-unit slice profiles (global slice, degree).
@@ -81,6 +143,12 @@ struct ViewK {
   };
   __device__ Row row(int64_t v, const SolveDev &) const { return Row{rp[v], rp[v + 1]}; }
   __device__ int64_t wt(const Row &, int64_t e, int32_t) const { return w[e]; }
+  __device__ int64_t nbr(const Row &, int64_t e, int64_t &ww) const {
+    ww = w[e];
+    return col[e];
+  }
+  __device__ int64_t orig(int64_t v) const { return v; }
+  __device__ int solve_of(int64_t v) const { return usolve[v]; }
   __device__ int plen(int64_t v) const { return (int)(pp[v + 1] - pp[v]); }
   __device__ void pent(int64_t v, int j, int &gs, int64_t &kk) const {
     gs = ps[pp[v] + j];
@@ -111,7 +179,7 @@ template <class V>
 __device__ inline UnitCtx unit_ctx(const V &g, const SolveDev &sd, int64_t v, uint32_t D) {
   UnitCtx u;
   u.v = v;
-  u.j = g.usolve[v];
+  u.j = g.solve_of(v);
   u.D = D;
   u.m = g.plen(v);
   u.gs0 = 0;
@@ -168,6 +236,13 @@ struct Policy0 {
     o.lab = shfl_xor32(s.lab, m);
     return o;
   }
+  // the score of staying when the Sigma of the unit's own community is already known
+  __device__ static Score stay_from(const UnitCtx &u, uint32_t D, int64_t W, int64_t yD) {
+    Score s;
+    s.lab = D;
+    s.g = u.m == 0 ? u.q * W : u.q * u.S0 * W - u.pb * (u.k0 * (yD - u.k0));
+    return s;
+  }
 };
 
 // Aggregated levels: int128 when the unit lies in one slice, otherwise a double estimate
@@ -185,7 +260,7 @@ template <class V>
 __device__ __noinline__ int exact_big(const V &g, const UnitCtx &u, const SolveDev &sd,
                                       const SliceTable &tab, uint32_t la, int ka, int64_t Wa,
                                       uint32_t lb, int kb, int64_t Wb) {
-  atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
+  atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks + u.j), 1ull);
   ExactAcc acc;
   acc.init();
   for (int jj = 0; jj < u.m; jj++) {
@@ -683,7 +758,7 @@ __device__ inline uint32_t lm_unit_coop(Grp grp, Tab tab, const V &g, const Solv
   const ScoreK stay = coop_make(u, c, u.D, wD, kStay);
   uint32_t out = kNone;
   if (P::cmp(g, u, sd, sig, best, stay) > 0)
-    out = best.lab == kNone ? fresh_base + (uint32_t)u.v : best.lab;
+    out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(u.v) : best.lab;
   grp.sync();
   return out;
 }
@@ -703,8 +778,8 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
   for (int64_t e = row.lo + r; e < row.hi; e += gsz) {
-    int32_t x = g.col[e];
-    int64_t w = g.wt(row, e, x);
+    int64_t w;
+    const int64_t x = g.nbr(row, e, w);
     if (w == 0) continue;
     tab.add(comm[x], w);
   }
@@ -746,7 +821,8 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   int64_t wD = tab.get(D);
   typename P::Score stay = P::make(g, u, sd, sig, D, wD, kStay);
   uint32_t out = kNone;
-  if (P::cmp(g, u, sd, sig, best, stay) > 0) out = best.lab == kNone ? fresh_base + (uint32_t)v : best.lab;
+  if (P::cmp(g, u, sd, sig, best, stay) > 0)
+    out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(v) : best.lab;
   grp.sync();
   return out;
 }
@@ -814,12 +890,16 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
   const int64_t v = units[idx];
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
+  UnitCtx u = unit_ctx(g, sd, v, D);
+  // level 0: the lookup of the own community's Sigma goes out with the neighbour gathers
+  int64_t yD = 0;
+  if constexpr (std::is_same<P, Policy0>::value)
+    if (gl == 0 && u.m > 0) yD = tab_get(sig, u.gs0, D);
   const int64_t e = row.lo + gl;
   uint32_t c = kNone;
   int64_t w = 0;
   if (e < row.hi) {
-    int32_t x = g.col[e];
-    w = g.wt(row, e, x);
+    const int64_t x = g.nbr(row, e, w);
     if (w != 0) c = comm[x];
   }
   int64_t wsum = 0, wD = 0;
@@ -833,7 +913,6 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
     }
     if (cj == D) wD += wj;
   }
-  UnitCtx u = unit_ctx(g, sd, v, D);
   typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
   const bool cand = leader && c != D;
   if (cand) {
@@ -853,10 +932,12 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
     }
   }
   if (gl == 0) {
-    typename P::Score stay = P::make(g, u, sd, sig, D, wD, kStay);
+    typename P::Score stay;
+    if constexpr (std::is_same<P, Policy0>::value) stay = Policy0::stay_from(u, D, wD, yD);
+    else stay = P::make(g, u, sd, sig, D, wD, kStay);
     uint32_t out = kNone;
     if (P::cmp(g, u, sd, sig, best, stay) > 0)
-      out = best.lab == kNone ? fresh_base + (uint32_t)v : best.lab;
+      out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(v) : best.lab;
     target[idx] = out;
   }
 }
@@ -1115,8 +1196,8 @@ __global__ __launch_bounds__(256) void k_hub_accum(V g, SolveDev sd, const int32
   constexpr uint32_t mask = (1u << kHubLdsLg) - 1;
   for (int64_t e = row.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < row.hi;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t x = g.col[e];
-    const int64_t w = g.wt(row, e, x);
+    int64_t w;
+    const int64_t x = g.nbr(row, e, w);
     if (w == 0) continue;
     const uint32_t lab = comm[x], key = lab + 1;
     uint32_t h = fib_hash(lab, 32 - kHubLdsLg);
@@ -1242,7 +1323,7 @@ __global__ __launch_bounds__(64) void k_hub_final(V g, SolveDev sd, const int32_
   if (lane == 0) {
     uint32_t out = kNone;
     if (P::cmp(g, u, sd, sig, best, stay) > 0)
-      out = best.lab == kNone ? fresh_base + (uint32_t)v : best.lab;
+      out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(v) : best.lab;
     target[idx] = out;
   }
 }
@@ -1261,13 +1342,13 @@ __global__ __launch_bounds__(256) void k_lm_apply(V g, const int32_t *units, int
   if (threadIdx.x == 0) {
     s_moves = 0;
     s_mixed = 0;
-    s_j = g.usolve[units[i]];   // thread 0's unit always exists
+    s_j = g.solve_of(units[i]);   // thread 0's unit always exists
   }
   __syncthreads();
   if (i < count) {
     const uint32_t C = target[i];
     const int64_t v = units[i];
-    j = g.usolve[v];
+    j = g.solve_of(v);
     if (C != kNone && !frozen[j]) {
       const uint32_t D = comm[v];
       const int m = g.plen(v);
@@ -1305,7 +1386,7 @@ __global__ __launch_bounds__(256) void k_lm_apply_wave(V g, const int32_t *units
   if (i >= count) return;
   const uint32_t C = target[i];
   const int64_t v = units[i];
-  const int j = g.usolve[v];
+  const int j = g.solve_of(v);
   if (C == kNone || frozen[j]) return;
   const uint32_t D = comm[v];
   const int m = g.plen(v);
@@ -1348,6 +1429,114 @@ __global__ void k_restore_flagged(V g, int64_t n, const uint32_t *snap, const ui
                                   uint32_t *comm) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n && redo[g.usolve[v]]) comm[v] = snap[v];
+}
+
+// ------------------------------------------------------------------ level 0 by position
+// The level-0 sweeps read the supra-CSR in colour-batch order (ViewP): position i holds unit
+// units[i] of the level's sorted batch list.  These kernels lay it out once per level-0 visit.
+__global__ void k_pos_of(const int32_t *units, int64_t n, int32_t *pos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pos[units[i]] = (int32_t)i;
+}
+
+// per position: degree (for the row starts), intra degree, slice, solve, labels
+__global__ void k_pos_meta(View0 g, const int32_t *units, int64_t n, int64_t *deg, int32_t *pk,
+                           int32_t *pslice, int32_t *psolve, int32_t *iota,
+                           const uint32_t *comm, uint32_t *pcomm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (i == n) {
+    deg[n] = 0;
+    return;
+  }
+  const int64_t v = units[i];
+  deg[i] = g.degree(v);
+  pk[i] = g.k[v];
+  pslice[i] = g.slice_of(v);
+  if (psolve) psolve[i] = g.solve_of(v);
+  iota[i] = (int32_t)i;
+  pcomm[i] = comm[v];
+}
+
+// entries of one position: neighbour positions with the coupling flag, raw weights
+__device__ inline void pos_row(const View0 &g, const SolveDev &sd, int64_t v, int64_t out,
+                               const int32_t *pos, int32_t *pcol, int32_t *pw, int first,
+                               int step) {
+  const typename View0::Row r = g.row(v, sd);
+  for (int64_t e = r.lo + first; e < r.hi; e += step) {
+    const int32_t x = g.col[e];
+    const bool coupling = !(x >= r.slo && x < r.shi);
+    pcol[out + (e - r.lo)] = pos[x] | (coupling ? (int32_t)0x80000000 : 0);
+    if (pw) pw[out + (e - r.lo)] = g.w[e];
+  }
+}
+
+// rows of at most 32 entries one thread each; longer rows are listed for a wave each
+__global__ void k_pos_rows(View0 g, SolveDev sd, const int32_t *units, int64_t n,
+                           const int64_t *prp, const int32_t *pos, int32_t *pcol, int32_t *pw,
+                           int32_t *wide, uint32_t *nwide) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = units[i];
+  if (g.degree(v) > 32) {
+    wide[atomicAdd(nwide, 1u)] = (int32_t)i;
+    return;
+  }
+  pos_row(g, sd, v, prp[i], pos, pcol, pw, 0, 1);
+}
+
+__global__ void k_pos_rows_wide(View0 g, SolveDev sd, const int32_t *units, const int64_t *prp,
+                                const int32_t *pos, int32_t *pcol, int32_t *pw,
+                                const int32_t *wide, const uint32_t *nwide) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < *nwide;
+       k += nw) {
+    const int64_t i = wide[k];
+    pos_row(g, sd, units[i], prp[i], pos, pcol, pw, lane, 64);
+  }
+}
+
+// global-table slots of the hub units, by position
+__global__ void k_pos_gtab(const int32_t *hubs, int64_t cnt, const int32_t *pos,
+                           const int64_t *goff, const int32_t *glg, int64_t *goffP,
+                           int32_t *glgP) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t u = hubs[i];
+  goffP[pos[u]] = goff[u];
+  glgP[pos[u]] = glg[u];
+}
+
+__global__ void k_pos_labels_back(const int32_t *units, int64_t n, const uint32_t *pcomm,
+                                  uint32_t *comm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) comm[units[i]] = pcomm[i];
+}
+
+// A refinement round taken again exactly for the solves that raised their redo flag only:
+// their units get back the active flags and proposal stamps of the round's start; the other
+// solves' units are set aside (inactive, so the proposal kernels skip them) and get their
+// flags back afterwards (k_ref_redo_done), keeping their proposals of the first pass.
+template <class V>
+__global__ void k_ref_redo_prep(V g, int64_t n, const uint32_t *redo, uint8_t *active,
+                                const uint8_t *snap_a, uint32_t *propr, const uint32_t *snap_p,
+                                uint8_t *keep) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (redo[g.solve_of(v)]) {
+    active[v] = snap_a[v];
+    propr[v] = snap_p[v];
+  } else {
+    keep[v] = active[v];
+    active[v] = 0;
+  }
+}
+template <class V>
+__global__ void k_ref_redo_done(V g, int64_t n, const uint32_t *redo, uint8_t *active,
+                                const uint8_t *keep) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && !redo[g.solve_of(v)]) active[v] = keep[v];
 }
 
 template <class V>
@@ -2054,7 +2243,7 @@ __global__ __launch_bounds__(256) void k_ref_wc(V g, SolveDev sd, const int32_t 
     if (fabs(ap) > er) {
       sign = ap > 0 ? 1 : -1;
     } else {
-      atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks), 1ull);
+      atomicAdd(reinterpret_cast<unsigned long long *>(sd.fallbacks + j), 1ull);
       ExactAcc ea;
       ea.init();
       for (uint64_t b = mk; b; b &= b - 1) {

@@ -1,5 +1,7 @@
-// Library primitives used between the hand-written kernels: stable LSD radix sorts,
-// exclusive scans and reduce-by-key (hipCUB on rocPRIM, compiled for gfx950).
+// Device-wide primitives between the method's kernels, written for gfx950 (prims.hip): stable
+// LSD radix sorts of key/value pairs over the key bits in use, exclusive scans and
+// reduce-by-key over sorted keys.  All work runs on the given stream; temporary storage comes
+// from the callback (one request per call).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -21,8 +21,14 @@ MSLM_OK, MSLM_EINVAL, MSLM_ENOMEM, MSLM_EOVERFLOW, MSLM_EUNSUPPORTED, MSLM_EHIP,
 MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE, MSLM_COUNT = 1, 2, 4, 8
 
 EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_footprint_bytes",
-            "mslm_graph_info", "mslm_last_error", "mslm_batch_leiden", "mslm_server_create",
-            "mslm_server_submit", "mslm_server_wait", "mslm_server_destroy"]
+            "mslm_graph_info", "mslm_last_error", "mslm_set_allocator", "mslm_batch_leiden",
+            "mslm_server_create", "mslm_server_submit", "mslm_server_wait",
+            "mslm_server_memory", "mslm_server_destroy"]
+
+
+_ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_RELEASE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_allocators = []   # every installed callback pair stays alive: buffers release through theirs
 
 
 class MslmError(RuntimeError):
@@ -82,6 +88,15 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2608_03695_amd/build.py")
+    # PyTorch carries its own HIP runtime beside the system one this library links; torch's
+    # did not come up on a device the library's runtime had already brought up in the same
+    # process, so torch is brought up first whenever it is importable and sees a GPU
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     lib.mslm_create.argtypes = [C.POINTER(GraphDesc), P, C.POINTER(C.c_void_p)]
@@ -102,7 +117,9 @@ def load():
     lib.mslm_batch_leiden.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Solve),
                                       C.c_int32, P]
     lib.mslm_batch_leiden.restype = C.c_int
-    lib.mslm_server_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]
+    lib.mslm_set_allocator.argtypes = [_ALLOC_T, _RELEASE_T, P]
+    lib.mslm_set_allocator.restype = C.c_int
+    lib.mslm_server_create.argtypes = [C.c_size_t, C.c_int32, P, C.POINTER(C.c_void_p)]
     lib.mslm_server_create.restype = C.c_int
     lib.mslm_server_submit.argtypes = [P, C.POINTER(GraphDesc), C.POINTER(Params),
                                        C.POINTER(C.c_uint64)]
@@ -110,6 +127,9 @@ def load():
     lib.mslm_server_wait.argtypes = [P, C.c_uint64, C.c_int32, P, C.POINTER(Result),
                                      C.POINTER(C.c_double)]
     lib.mslm_server_wait.restype = C.c_int
+    lib.mslm_server_memory.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                       C.POINTER(C.c_size_t)]
+    lib.mslm_server_memory.restype = C.c_int
     lib.mslm_server_destroy.argtypes = [P]
     lib.mslm_server_destroy.restype = None
     _lib = lib
@@ -220,14 +240,40 @@ def footprint_bytes(tg, omega=Fraction(1)) -> int:
     return int(load().mslm_footprint_bytes(C.byref(d)))
 
 
+def use_torch_allocator(device=None):
+    """Route the library's device allocations through PyTorch's caching allocator
+    (mslm_set_allocator with torch.cuda.caching_allocator_alloc / _delete)."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+        except RuntimeError:
+            return None
+
+    def release(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    pair = (_ALLOC_T(alloc), _RELEASE_T(release))
+    _allocators.append(pair)
+    _check(load().mslm_set_allocator(pair[0], pair[1], None))
+
+
+def use_hip_allocator():
+    """Back to hipMalloc / hipFree for new buffers."""
+    _check(load().mslm_set_allocator(_ALLOC_T(), _RELEASE_T(), None))
+
+
 class Server:
     """Continuous-batching request loop (mslm_server_*): submit() copies the graph and
     returns a ticket; wait() returns (membership, result dict, latency seconds)."""
 
-    def __init__(self, hbm_budget_bytes, max_slots=4):
+    def __init__(self, hbm_budget_bytes, max_slots=4, stream=None):
         lib = load()
         h = C.c_void_p()
-        _check(lib.mslm_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        _check(lib.mslm_server_create(int(hbm_budget_bytes), int(max_slots), stream_handle(stream),
+                                      C.byref(h)))
         self._h = h
         self._shape = {}
 
@@ -249,6 +295,12 @@ class Server:
                                        C.byref(res), C.byref(lat)))
         self._shape.pop(ticket, None)
         return memb, res.as_dict(n_slices), lat.value
+
+    def memory(self):
+        """(bytes the slots hold, peak held, peak charged against the budget)."""
+        a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(load().mslm_server_memory(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -4,7 +4,12 @@ Runs only the oracle (oracle/), never the HIP library: for each workload it reco
 sha256 of the oracle's int32 membership, its Q components and schedule statistics.  The
 GPU parity tests compare the HIP path's output against these files.
 
-    python tests/golden/make_expected.py [cfg2]
+    python tests/golden/make_expected.py [cfg2] [cfg3] [cfg4]
+
+Config 3 needs about 45 GB of host memory and tens of minutes on 8 threads.  cfg4 records the
+oracle's digest (sha256 of the int32 membership and the int64 Q components) and statistics of
+every solve of the batched workload's grid (gamma in {1/2, 1, 2} x omega in {1/10, 1, 10}) on
+every 8th of its 512 graphs: 576 solves, run in parallel processes.
 """
 import hashlib
 import json
@@ -21,27 +26,84 @@ import oracle  # noqa: E402
 from paper_2608_03695_amd import gen  # noqa: E402
 
 WORKLOADS = {
-    "cfg2": (gen.config2, gen.CONFIG_SOLVE[2]),
+    "cfg2": (lambda: gen.config2(8), gen.CONFIG_SOLVE[2]),
+    "cfg3": (lambda: gen.config3(8), gen.CONFIG_SOLVE[3]),
 }
+
+
+CFG4_GRAPHS = range(0, 512, 8)
+
+
+def _digest(memb, comps):
+    h = hashlib.sha256(np.ascontiguousarray(memb, dtype=np.int32).tobytes())
+    h.update(np.ascontiguousarray(comps, dtype=np.int64).tobytes())
+    return h.hexdigest()
+
+
+def _cfg4_graph(g):
+    """Every grid solve of batched-workload graph g (one process; oracle threads 1)."""
+    tg = gen.batch_graph(g)
+    out = []
+    for gamma in gen.GAMMA_GRID:
+        for omega in gen.OMEGA_GRID:
+            memb, comps, st = oracle.OracleGraph(tg, omega).leiden(gamma, max_levels=32,
+                                                                    max_iterations=2, seed=0)
+            out.append(dict(graph=g, gamma=str(gamma), omega=str(omega),
+                            digest=_digest(memb, comps),
+                            stats={k: int(v) for k, v in st.items()}))
+    return out
+
+
+def make_cfg4():
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    os.environ["OMP_NUM_THREADS"] = "1"
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(max_workers=8, mp_context=mp.get_context("spawn")) as ex:
+        per = list(ex.map(_cfg4_graph, CFG4_GRAPHS))
+    solves = [s for grp in per for s in grp]
+    out = dict(workload="cfg4 sample: every 8th of the 512 batched-workload graphs x the "
+                        "3x3 (gamma, omega) grid", graphs=list(CFG4_GRAPHS),
+               max_levels=32, max_iterations=2, seed=0, solves=solves,
+               oracle_seconds=round(time.time() - t0, 1))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg4_expected.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+    print("cfg4", len(solves), "solves", out["oracle_seconds"], "s")
 
 
 def main(names):
     for name in names:
+        if name == "cfg4":
+            make_cfg4()
+            continue
         make, spec = WORKLOADS[name]
         t0 = time.time()
         tg = make()
+        t1 = time.time()
         og = oracle.OracleGraph(tg, spec.omega)
+        m_supra = int(oracle._load().orc_nnz(og._h)) // 2
+        meta = dict(name=tg.name, n_nodes=tg.n_nodes, n_slices=tg.n_slices, n_edges=tg.n_edges)
+        # the oracle holds its own copy of the graph: drop the edge lists before solving
+        tg.src = tg.dst = tg.weight = None
+        og._keep = None
+        t2 = time.time()
         memb, comps, st = og.leiden(spec.gamma, max_levels=spec.max_levels,
                                     max_iterations=spec.max_iterations, seed=spec.seed)
-        q = oracle.q_from_components(comps, tg.n_nodes, tg.n_slices, spec.gamma, spec.omega)
-        out = dict(workload=tg.name, n_nodes=tg.n_nodes, n_slices=tg.n_slices,
-                   n_edges=int(tg.n_edges), gamma=str(spec.gamma), omega=str(spec.omega),
+        t3 = time.time()
+        q = oracle.q_from_components(comps, meta["n_nodes"], meta["n_slices"], spec.gamma,
+                                     spec.omega)
+        out = dict(workload=meta["name"], n_nodes=meta["n_nodes"], n_slices=meta["n_slices"],
+                   n_edges=int(meta["n_edges"]), gamma=str(spec.gamma), omega=str(spec.omega),
                    max_levels=spec.max_levels, max_iterations=spec.max_iterations, seed=spec.seed,
                    membership_sha256=hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest(),
                    q_components=[int(x) for x in comps], q=f"{q.numerator}/{q.denominator}",
                    stats={k: int(v) for k, v in st.items()},
-                   oracle_seconds=round(time.time() - t0, 1),
-                   oracle_threads=oracle.num_threads())
+                   oracle_timing=dict(generate_s=round(t1 - t0, 1), create_s=round(t2 - t1, 1),
+                                      solve_s=round(t3 - t2, 1), threads=oracle.num_threads(),
+                                      supra_edges=m_supra,
+                                      supra_edges_per_s=round(m_supra / (t3 - t2)),
+                                      host="the build container, not the benchmark host"))
         path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_expected.json")
         with open(path, "w") as f:
             json.dump(out, f, indent=1)
@@ -49,4 +111,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(WORKLOADS))
+    main(sys.argv[1:] or list(WORKLOADS) + ["cfg4"])
