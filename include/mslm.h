@@ -149,6 +149,24 @@ const char *mslm_last_error(void);
 mslm_status mslm_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
                                void (*release)(void *ptr, void *ctx), void *ctx);
 
+/* ------------------------------------------------------------------ allocation-free solve */
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  mslm_leiden on a resident graph, same arguments
+ * and same results, except that every work buffer of the solve is carved from a static device
+ * array of MSLM_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on from load
+ * until the process ends; no hipMalloc, hipFree or allocating library routine is called (the
+ * graph and the caller's outputs are the only other device memory touched).  The array keeps
+ * the last call's contents; every call clears what it needs.  Calls on one GPU share its
+ * array: the library runs them one at a time (a per-device lock), and a call's device work is
+ * finished when it returns, so calls from several threads never overlap on the array.
+ * Errors: EUNSUPPORTED when the solve needs more than the array holds (estimate: 96 bytes per
+ * CSR entry plus 384 per supra-node plus 1 MiB: about 400k supra-nodes with 1M entries), EINVAL for
+ * MSLM_PROFILE (it records HIP events) or when the current device is not the graph's, and as
+ * mslm_leiden otherwise. */
+#define MSLM_STATIC_SCRATCH_BYTES (256ull << 20)
+mslm_status mslm_leiden_static(mslm_graph *g, const mslm_params *params, int32_t *membership,
+                               mslm_result *res);
+
 /* ------------------------------------------------------------------ batching */
 /* Many solves (graph x gamma x omega) run as one disjoint-union solve: every kernel launch
  * covers all solves that are still active, and each solve's result is bit-identical to a

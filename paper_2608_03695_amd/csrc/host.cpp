@@ -333,8 +333,8 @@ void api_clear_error() { g_err.clear(); }
 const char *api_error_text() { return g_err.c_str(); }
 size_t solve_scratch_estimate(int64_t n, int64_t nnz) {
   // aggregation keys and values double-buffered, sort scratch, two aggregated levels,
-  // per-unit state and the Sigma tables
-  return (size_t)(88 * nnz + 320 * n) + ((size_t)1 << 20);
+  // per-unit state, the Sigma tables and level 0 laid out in colour-batch order
+  return (size_t)(96 * nnz + 384 * n) + ((size_t)1 << 20);
 }
 size_t footprint_estimate(const mslm_graph_desc *d) {
   if (check_desc_shape(d) != MSLM_OK) return 0;

@@ -21,7 +21,8 @@ MSLM_OK, MSLM_EINVAL, MSLM_ENOMEM, MSLM_EOVERFLOW, MSLM_EUNSUPPORTED, MSLM_EHIP,
 MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE, MSLM_COUNT = 1, 2, 4, 8
 
 EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_footprint_bytes",
-            "mslm_graph_info", "mslm_last_error", "mslm_set_allocator", "mslm_batch_leiden",
+            "mslm_graph_info", "mslm_last_error", "mslm_set_allocator", "mslm_leiden_static",
+            "mslm_batch_leiden",
             "mslm_server_create", "mslm_server_submit", "mslm_server_wait",
             "mslm_server_memory", "mslm_server_destroy"]
 
@@ -103,6 +104,8 @@ def load():
     lib.mslm_create.restype = C.c_int
     lib.mslm_leiden.argtypes = [P, C.POINTER(Params), P, C.POINTER(Result)]
     lib.mslm_leiden.restype = C.c_int
+    lib.mslm_leiden_static.argtypes = [P, C.POINTER(Params), P, C.POINTER(Result)]
+    lib.mslm_leiden_static.restype = C.c_int
     lib.mslm_destroy.argtypes = [P]
     lib.mslm_destroy.restype = None
     lib.mslm_q_exact.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
@@ -205,9 +208,10 @@ class Graph:
         return dict(n_supra=n.value, nnz=m.value, two_m=t.value)
 
     def leiden(self, gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0,
-               seed=0, profile=False, count=False, out=None):
+               seed=0, profile=False, count=False, out=None, no_alloc=False):
         """Returns (membership int32[T*N], result dict).  `out` may be a device tensor
-        (torch, int32, T*N elements) to receive the membership on the device."""
+        (torch, int32, T*N elements) to receive the membership on the device.  no_alloc
+        calls the allocation-free entry point (mslm_leiden_static)."""
         lib = load()
         flags = (MSLM_PROFILE if profile else 0) | (MSLM_COUNT if count else 0)
         if out is not None:
@@ -219,7 +223,8 @@ class Graph:
             dest = _ptr(memb)
         p = params(gamma, omega, max_levels, max_iterations, max_sweeps, seed, flags)
         res = Result()
-        _check(lib.mslm_leiden(self._h, C.byref(p), dest, C.byref(res)))
+        entry = lib.mslm_leiden_static if no_alloc else lib.mslm_leiden
+        _check(entry(self._h, C.byref(p), dest, C.byref(res)))
         return memb, res.as_dict(self.n_slices)
 
 
