@@ -78,9 +78,10 @@ def _load():
     lib.orc_nnz.restype = C.c_int64
     lib.orc_csr.argtypes = [P, P, P, P, P, P]
     lib.orc_leiden.argtypes = [P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
-                               C.c_uint64, P, P, C.POINTER(Stats)]
+                               C.c_uint64, C.c_int32, P, P, C.POINTER(Stats)]
     lib.orc_leiden.restype = C.c_int
     lib.orc_q_components.argtypes = [P, P, P]
+    lib.orc_q_components_global.argtypes = [P, P, P]
     lib.orc_mix64.argtypes = [C.c_uint64]
     lib.orc_mix64.restype = C.c_uint64
     lib.orc_priority.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_uint32]
@@ -158,23 +159,27 @@ class OracleGraph:
         lib.orc_csr(self._h, _ptr(rp), _ptr(col), _ptr(w), _ptr(raw), _ptr(twom))
         return rp, col, w, raw, twom
 
-    def leiden(self, gamma=Fraction(1), max_levels=32, max_iterations=2, max_sweeps=0, seed=0):
+    def leiden(self, gamma=Fraction(1), max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
+               null_model=0):
+        """null_model 0: the multislice modularity of Eq. 6 (per-slice null model);
+        1: the global modularity of the supra-graph (Eq. 5 over all supra-nodes)."""
         lib = _load()
         gamma = Fraction(gamma)
         memb = np.zeros(self.g.n_supra, np.int32)
         comps = np.zeros(3 * self.g.n_slices + 1, np.int64)
         st = Stats()
         rc = lib.orc_leiden(self._h, gamma.numerator, gamma.denominator, max_levels,
-                            max_iterations, max_sweeps, seed, _ptr(memb), _ptr(comps),
-                            C.byref(st))
+                            max_iterations, max_sweeps, seed, null_model, _ptr(memb),
+                            _ptr(comps), C.byref(st))
         if rc != 0:
             raise ValueError(f"oracle leiden failed: {rc}")
         return memb, comps, st.as_dict()
 
-    def q_components(self, membership):
+    def q_components(self, membership, null_model=0):
         memb = np.ascontiguousarray(membership, dtype=np.int32)
         comps = np.zeros(3 * self.g.n_slices + 1, np.int64)
-        _load().orc_q_components(self._h, _ptr(memb), _ptr(comps))
+        fn = _load().orc_q_components_global if null_model == 1 else _load().orc_q_components
+        fn(self._h, _ptr(memb), _ptr(comps))
         return comps
 
 
@@ -191,6 +196,21 @@ def q_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
     num += omega * int(I)
     den = sum(int(x) for x in tm) + 2 * omega * n_nodes * (T - 1)
     return num / den if den else Fraction(0)
+
+
+def q_global_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
+    """Global modularity of the supra-graph from its components: with 2mu = sum_s 2m_s +
+    2 omega N (T-1), Q = (sum_s W_s + omega I - gamma (comps[T] / b^2) / 2mu) / 2mu, where
+    comps[T] = sum_C (sum_v kappa'_v)^2 in units scaled by the coupling denominator b."""
+    T = n_slices
+    gamma, omega = Fraction(gamma), Fraction(omega)
+    b = omega.denominator
+    W, SS, tm, I = comps[:T], int(comps[T]), comps[2 * T:3 * T], comps[3 * T]
+    two_mu = sum(int(x) for x in tm) + 2 * omega * n_nodes * (T - 1)
+    if two_mu == 0:
+        return Fraction(0)
+    num = sum(int(x) for x in W) + omega * int(I) - gamma * Fraction(SS, b * b) / two_mu
+    return num / two_mu
 
 
 def trace_enable(on: bool = True):

@@ -213,6 +213,78 @@ def q_newman_static(g, gamma, membership):
                 for cl in set(int(v) for v in c)), Fraction(0))
 
 
+# --------------------------------------------------------------------------- global null model
+# Eq. 5 (undirected, so d_out = d_in) applied to the supra-adjacency of Eq. 3 as one graph:
+# kappa_u = sum_v A_uv (intra degree plus coupling weight), 2mu = sum_u kappa_u, and
+#   Q_G = (1/2mu) sum_{uv} [A_uv - gamma kappa_u kappa_v / 2mu] delta(c_u, c_v).
+# The paper's GPU path optimised this on the supra-graph as a stand-in for Eq. 6.
+
+def supra_degrees(g, omega):
+    A = supra_adjacency(g, omega)
+    return [sum(row, Fraction(0)) for row in A]
+
+
+def global_modularity_matrix(g, gamma, omega):
+    A = supra_adjacency(g, omega)
+    kap = [sum(row, Fraction(0)) for row in A]
+    tm = sum(kap, Fraction(0))
+    gamma = Fraction(gamma)
+    size = len(A)
+    if tm == 0:
+        return A
+    return [[A[u][v] - gamma * kap[u] * kap[v] / tm for v in range(size)] for u in range(size)]
+
+
+def q_global_pair_sum(g, gamma, omega, membership):
+    """Q_G by the literal double sum over supra-node pairs."""
+    A = supra_adjacency(g, omega)
+    kap = [sum(row, Fraction(0)) for row in A]
+    tm = sum(kap, Fraction(0))
+    if tm == 0:
+        return Fraction(0)
+    gamma = Fraction(gamma)
+    c = np.asarray(membership).ravel()
+    total = Fraction(0)
+    for u in range(len(A)):
+        for v in range(len(A)):
+            if c[u] == c[v]:
+                total += A[u][v] - gamma * kap[u] * kap[v] / tm
+    return total / tm
+
+
+def q_global_trace_form(g, gamma, omega, membership):
+    """Tr(C^T B C) / 2mu with B the global modularity matrix of the supra-graph."""
+    B = global_modularity_matrix(g, gamma, omega)
+    tm = sum(supra_degrees(g, omega), Fraction(0))
+    if tm == 0:
+        return Fraction(0)
+    c = np.asarray(membership).ravel()
+    groups = {}
+    for u, lab in enumerate(c):
+        groups.setdefault(int(lab), []).append(u)
+    tr = sum((B[u][v] for mem in groups.values() for u in mem for v in mem), Fraction(0))
+    return tr / tm
+
+
+def q_global_all_singletons(g, gamma, omega):
+    """Every supra-node alone: -gamma sum_u kappa_u^2 / (2mu)^2."""
+    kap = supra_degrees(g, omega)
+    tm = sum(kap, Fraction(0))
+    return -Fraction(gamma) * sum(x * x for x in kap) / (tm * tm) if tm else Fraction(0)
+
+
+def q_global_one_community(g, gamma, omega):
+    """All supra-nodes together: 1 - gamma (0 for an empty supra-graph)."""
+    tm = sum(supra_degrees(g, omega), Fraction(0))
+    return 1 - Fraction(gamma) if tm else Fraction(0)
+
+
+def brute_force_max_global(g, gamma, omega):
+    """Maximum of Q_G over every set partition of at most 10 supra-nodes."""
+    best, mems = _brute_force(global_modularity_matrix(g, gamma, omega))
+    return _over_two_mu(best, g, omega), mems
+
+
 # --------------------------------------------------------------------------- closed forms
 
 def q_all_singletons(g, gamma, omega):
@@ -242,7 +314,13 @@ def brute_force_max(g, gamma, omega):
 
     Returns (Q*, list of optimal memberships).  Sizes up to 10 supra-nodes (Bell(10) = 115975).
     """
-    M = modularity_matrix(g, gamma, omega)
+    best, mems = _brute_force(modularity_matrix(g, gamma, omega))
+    return _over_two_mu(best, g, omega), mems
+
+
+def _brute_force(M):
+    """Maximum over all set partitions of the sum of M_uv over pairs in one block, and every
+    membership reaching it (restricted growth strings)."""
     size = len(M)
     assert size <= 10, "brute force is for tiny graphs only"
     L = 1
@@ -273,7 +351,7 @@ def brute_force_max(g, gamma, omega):
                 blocks.pop()
 
     rec(0, 0)
-    return _over_two_mu(Fraction(best[0], L), g, omega), best[1]
+    return Fraction(best[0], L), best[1]
 
 
 # --------------------------------------------------------------------------- invariant helpers

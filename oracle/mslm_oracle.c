@@ -854,6 +854,28 @@ int orc_q_components(const orc_graph *G, const int32_t *memb, int64_t *comps) {
   return ORC_OK;
 }
 
+/* Components of the global modularity: comps[0..T-1] = W_s as above, comps[T] = the sum over
+ * communities of the squared scaled supra-degree sum (sum_C (sum_{v in C} kappa'_v)^2, with
+ * kappa' = b * (intra degree) + a * (coupling count)), comps[T+1..2T-1] = 0, comps[2T..3T-1] =
+ * 2m_s, comps[3T] = I. */
+int orc_q_components_global(const orc_graph *G, const int32_t *memb, int64_t *comps) {
+  int32_t T = G->T;
+  const level_t *g = &G->g0;
+  orc_q_components(G, memb, comps);
+  map_t sig; map_init(&sig, g->n);
+  for (int64_t v = 0; v < g->n; v++) {
+    int64_t kap = 0;
+    for (int64_t e = g->rp[v]; e < g->rp[v + 1]; e++) kap += g->w[e];
+    if (kap) map_add(&sig, (uint32_t)memb[v], 0, kap);
+  }
+  i128 ss = 0;
+  for (uint64_t h = 0; h < sig.cap; h++) if (sig.key[h] != MAP_EMPTY) ss += (i128)sig.val[h] * sig.val[h];
+  map_free(&sig);
+  for (int32_t s = T; s < 2 * T; s++) comps[s] = 0;
+  comps[T] = (int64_t)ss;
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ driver */
 static int level_copy(const level_t *src, level_t *dst) {
   int64_t n = src->n, m = src->nnz, np = src->pp[n];
@@ -863,16 +885,59 @@ static int level_copy(const level_t *src, level_t *dst) {
   return ORC_OK;
 }
 
+/* The global null model (Eq. 5 on the supra-graph): every unit's profile is the single
+ * entry (slice 0, kappa'_v) with kappa'_v its scaled supra-degree (intra and coupling
+ * weights), and the one denominator is 2mu' = sum of kappa'.  With the coupling denominator
+ * b folded into kappa', the comparison value q*W*2mu' - p*kappa'*Sigma' orders targets as
+ * the change of the global modularity does. */
+static level_t global_level(const level_t *g0, int64_t *two_mu) {
+  level_t g; level_copy(g0, &g);
+  free(g.pp); free(g.ps); free(g.pk);
+  int64_t n = g.n, np = 0;
+  int64_t *kap = calloc(n ? n : 1, sizeof(int64_t));
+  *two_mu = 0;
+  for (int64_t v = 0; v < n; v++) {
+    for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) kap[v] += g.w[e];
+    np += kap[v] > 0;
+    *two_mu += kap[v];
+  }
+  g.pp = calloc(n + 1, sizeof(int64_t)); g.ps = malloc((np ? np : 1) * sizeof(int32_t));
+  g.pk = malloc((np ? np : 1) * sizeof(int64_t));
+  int64_t q = 0;
+  for (int64_t v = 0; v < n; v++) {
+    if (kap[v] > 0) { g.ps[q] = 0; g.pk[q] = kap[v]; q++; }
+    g.pp[v + 1] = q;
+  }
+  free(kap);
+  return g;
+}
+
 int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t max_levels,
-               int32_t max_iterations, int32_t max_sweeps, uint64_t seed, int32_t *membership,
-               int64_t *comps, orc_stats *st) {
+               int32_t max_iterations, int32_t max_sweeps, uint64_t seed, int32_t null_model,
+               int32_t *membership, int64_t *comps, orc_stats *st) {
   if (gamma_num < 0 || gamma_den < 1 || max_levels < 1) return ORC_EINVAL;
+  if (null_model != 0 && null_model != 1) return ORC_EINVAL;
   if (gamma_num >= ((int64_t)1 << 31) || gamma_den >= ((int64_t)1 << 31)) return ORC_EOVERFLOW;
   int64_t gg = gamma_num ? gcd64(gamma_num, gamma_den) : gamma_den;
   ctx_t cx; cx.G = G;
   int64_t S[MAX_SLICES];
   for (int s = 0; s < G->T; s++) S[s] = G->twom[s] > 0 ? G->twom[s] : 1;
   cx.cf.p = gamma_num / gg; cx.cf.q = gamma_den / gg; cx.cf.b = G->b; cx.cf.S = S;
+  level_t gglob; memset(&gglob, 0, sizeof(gglob));
+  const level_t *base = &G->g0;
+  if (null_model == 1) {
+    int64_t two_mu = 0;
+    gglob = global_level(&G->g0, &two_mu);
+    /* head-room of the exact values: 2mu' < 2^31 and max(p, q) * 2mu'^2 < 2^62 */
+    int64_t pq = cx.cf.p > cx.cf.q ? cx.cf.p : cx.cf.q;
+    if (two_mu >= ((int64_t)1 << 31) || (i128)pq * two_mu * two_mu >= ((i128)1 << 62)) {
+      level_free(&gglob);
+      return ORC_EOVERFLOW;
+    }
+    S[0] = two_mu > 0 ? two_mu : 1;
+    cx.cf.b = 1;
+    base = &gglob;
+  }
   if (max_sweeps <= 0) max_sweeps = DEFAULT_SWEEPS;
   int iters = max_iterations > 0 ? max_iterations : MAX_ITER_CAP;
   if (iters > MAX_ITER_CAP) iters = MAX_ITER_CAP;
@@ -884,7 +949,7 @@ int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t
   uint32_t *Pflat = malloc(n0 * sizeof(uint32_t));
   int32_t *Pnew = malloc(n0 * sizeof(int32_t));
   for (int it = 0; it < iters; it++) {
-    level_t g; level_copy(&G->g0, &g);
+    level_t g; level_copy(base, &g);
     for (int64_t v = 0; v < n0; v++) map0[v] = v;
     uint32_t *P = malloc(n0 * sizeof(uint32_t));
     for (int64_t v = 0; v < n0; v++) P[v] = (uint32_t)Pcur[v];
@@ -940,8 +1005,10 @@ int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t
     if (same) break;
   }
   memcpy(membership, Pcur, n0 * sizeof(int32_t));
-  orc_q_components(G, Pcur, comps);
+  if (null_model == 1) orc_q_components_global(G, Pcur, comps);
+  else orc_q_components(G, Pcur, comps);
   free(Pcur); free(map0); free(Pflat); free(Pnew);
+  if (null_model == 1) level_free(&gglob);
   return ORC_OK;
 }
 

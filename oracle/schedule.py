@@ -103,6 +103,41 @@ class SupraGraph:
         self.inter_entries = [(v, x) for v in range(self.n) for x in nbr[v] if x not in intra[v]]
 
 
+class GlobalScore:
+    """The global modularity Q_G of the supra-graph (Eq. 5 over all supra-nodes) as an exact
+    integer multiple: with kappa'_u = b * (intra degree) + a * (coupling count) (omega = a/b),
+    2mu' = sum kappa', W' = b * (intra weight inside communities) + a * (coupling entries
+    inside communities), SS' = sum over communities of (sum kappa')^2:
+        q * 2mu' * W' - p * SS' = q * 2mu'^2 * Q_G            (gamma = p/q)."""
+
+    def __init__(self, G: SupraGraph, gamma):
+        self.G = G
+        gamma = Fraction(gamma)
+        self.p, self.q = gamma.numerator, gamma.denominator
+        a, b = G.omega.numerator, G.omega.denominator
+        self.a, self.b = a, b
+        self.kap = [b * G.k[v] + a * sum(1 for x in G.nbr[v] if x not in G.intra[v])
+                    for v in range(G.n)]
+        self.two_mu = sum(self.kap)
+
+    def __call__(self, lab) -> int:
+        G = self.G
+        W = 0
+        for v, x, ww in G.intra_entries:
+            if lab[v] == lab[x]:
+                W += self.b * ww
+        for v, x in G.inter_entries:
+            if lab[v] == lab[x]:
+                W += self.a
+        sig = {}
+        for v in range(G.n):
+            sig[lab[v]] = sig.get(lab[v], 0) + self.kap[v]
+        return self.q * self.two_mu * W - self.p * sum(x * x for x in sig.values())
+
+    def q(self, lab) -> Fraction:
+        return Fraction(self(lab), self.q * self.two_mu ** 2) if self.two_mu else Fraction(0)
+
+
 class Score:
     """L * 2mu * Q_MS(partition) as an exact integer, for one (graph, gamma):
         2mu Q = sum_s [ W_s - gamma SS_s / 2m_s ] + omega I            (Eq. 6)
@@ -239,10 +274,24 @@ def local_move(G, score, units, adj, colour, labels, max_sweeps, stats):
 
 # --------------------------------------------------------------------------- refinement
 
-def well_connected(G, gamma, X, K):
+def well_connected(G, gamma, X, K, null_model=0):
     """ext(X) >= gamma * sum_s Sigma_{X,s} (Sigma_{K,s} - Sigma_{X,s}) / 2m_s, where ext(X) is
-    the weight of the supra-edges between X and K minus X (X, K sets of level-0 supra-nodes)."""
+    the weight of the supra-edges between X and K minus X (X, K sets of level-0 supra-nodes);
+    for the global null model ext(X) >= gamma * kappa_X (kappa_K - kappa_X) / 2mu."""
+    if null_model == 1:
+        return external_weight(G, X, K) >= null_between_global(G, gamma, X, K)
     return external_weight(G, X, K) >= null_between(G, gamma, X, K)
+
+
+def null_between_global(G, gamma, X, K):
+    kap = [G.k[v] + sum((w for x, w in G.nbr[v].items() if x not in G.intra[v]), Fraction(0))
+           for v in range(G.n)]
+    tm = sum(kap, Fraction(0))
+    if tm == 0:
+        return Fraction(0)
+    kx = sum((kap[v] for v in X), Fraction(0))
+    kk = sum((kap[v] for v in K), Fraction(0))
+    return Fraction(gamma) * kx * (kk - kx) / tm
 
 
 def external_weight(G, X, K):
@@ -262,7 +311,7 @@ def null_between(G, gamma, X, K):
     return Fraction(gamma) * tot
 
 
-def refine(G, score, gamma, units, adj, labels, seed, it, lvl, stats):
+def refine(G, score, gamma, units, adj, labels, seed, it, lvl, stats, null_model=0):
     """Greedy round-synchronous refinement inside the communities `labels`; returns R (the
     founder unit of each unit's sub-community)."""
     n = len(units)
@@ -276,7 +325,7 @@ def refine(G, score, gamma, units, adj, labels, seed, it, lvl, stats):
         return {v for u in range(n) if R[u] == T for v in units[u]}
 
     def wc(T):
-        return well_connected(G, gamma, members(T), comm_members[labels[T]])
+        return well_connected(G, gamma, members(T), comm_members[labels[T]], null_model)
 
     active = [wc(u) for u in range(n)]
     pri = [(hash_priority(seed, it, lvl, 1, u), u) for u in range(n)]
@@ -343,12 +392,14 @@ def split_components(G, flat):
     return out
 
 
-def leiden(g, gamma=1, omega=1, max_levels=32, max_iterations=2, max_sweeps=0, seed=0):
+def leiden(g, gamma=1, omega=1, max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
+           null_model=0):
     """Run the schedule; returns (membership, stats, trace).  trace holds one record per
     level: colour, labels at the level's start (p_in), after local moving (p_lm), R, and the
-    refined sub-communities (founder -> level-0 members) with their well-connectedness."""
+    refined sub-communities (founder -> level-0 members) with their well-connectedness.
+    null_model 0 optimises Q_MS of Eq. 6; 1 the global modularity of the supra-graph."""
     G = SupraGraph(g, omega)
-    score = Score(G, gamma)
+    score = GlobalScore(G, gamma) if null_model == 1 else Score(G, gamma)
     gamma = Fraction(gamma)
     if max_sweeps <= 0:
         max_sweeps = DEFAULT_SWEEPS
@@ -379,7 +430,7 @@ def leiden(g, gamma=1, omega=1, max_levels=32, max_iterations=2, max_sweeps=0, s
             rec["p_lm"] = list(labels)
             if len(set(labels)) == n or lvl == max_levels - 1:
                 break
-            R = refine(G, score, gamma, units, adj, labels, seed, it, lvl, stats)
+            R = refine(G, score, gamma, units, adj, labels, seed, it, lvl, stats, null_model)
             rec["r"] = list(R)
             # refined sub-communities: founder -> (level-0 members, weight to the rest of the
             # community, well connected)
@@ -390,7 +441,7 @@ def leiden(g, gamma=1, omega=1, max_levels=32, max_iterations=2, max_sweeps=0, s
             for u in range(n):
                 subs.setdefault(R[u], set()).update(units[u])
             rec["subs"] = {T: (sorted(mem), external_weight(G, mem, comm0[labels[T]]),
-                               well_connected(G, gamma, mem, comm0[labels[T]]))
+                               well_connected(G, gamma, mem, comm0[labels[T]], null_model))
                            for T, mem in subs.items()}
             if len(set(R)) == n:
                 break
