@@ -43,6 +43,13 @@ typedef struct mslm_server mslm_server; /* continuous-batching request loop     
 
 enum { MSLM_INPUT_ON_DEVICE = 1u, MSLM_OUTPUT_ON_DEVICE = 2u, MSLM_PROFILE = 4u, MSLM_COUNT = 8u };
 
+/* The objective a solve maximises.  MULTISLICE: Q_MS of Eq. 6, a null model per snapshot
+ * (gamma k_i^s k_j^s / 2m_s).  GLOBAL: the modularity of Eq. 5 over the whole supra-graph of
+ * Eq. 3 (null model gamma kappa_u kappa_v / 2mu with kappa the supra-degree, intra weight
+ * plus coupling), the objective the paper's GPU path optimised on the supra-graph in place of
+ * Q_MS (Section 3.2). */
+enum { MSLM_NULL_MULTISLICE = 0, MSLM_NULL_GLOBAL = 1 };
+
 /* One temporal graph.  Slice s holds edges [slice_offsets[s], slice_offsets[s+1]) of
  * src/dst/weight: undirected, each edge listed once in either orientation, ids in [0, N),
  * no self-loops, weight >= 1 (NULL = unit weights).  Repeated pairs inside a slice add
@@ -64,14 +71,17 @@ typedef struct {
  * graph's default coupling.  max_levels >= 1 bounds the aggregation levels of one Leiden
  * iteration; max_iterations <= 0 runs iterations until the partition is stable (at most
  * 32); max_sweeps <= 0 means 32 local-moving sweeps per level.  The seed only changes the
- * hash priorities of the schedule.  Numerators and denominators must be below 2^31. */
+ * hash priorities of the schedule.  Numerators and denominators must be below 2^31.
+ * null_model: MSLM_NULL_MULTISLICE (0) or MSLM_NULL_GLOBAL (1); with GLOBAL the scaled total
+ * weight 2mu' = b * sum_s 2m_s + 2 a N (T-1) (omega = a/b) must stay below 2^31 and
+ * max(p, q) * 2mu'^2 below 2^62 (else EOVERFLOW). */
 typedef struct {
   int64_t gamma_num, gamma_den;
   int64_t omega_num, omega_den;
   int32_t max_levels;
   int32_t max_iterations;
   int32_t max_sweeps;
-  int32_t reserved0;
+  int32_t null_model;
   uint64_t seed;
   uint32_t flags;                 /* MSLM_OUTPUT_ON_DEVICE: membership is a device pointer;
                                      MSLM_PROFILE: time every level-0 local-moving decision
@@ -84,7 +94,10 @@ typedef struct {
 /* Per-solve outcome.  q_components (3T+1 int64) are the exact integer pieces of Q:
  * W_s (weight inside communities in slice s, both directions), SS_s (sum over communities
  * of the squared slice-s degree), 2m_s, and I (ordered coupled copy pairs sharing a
- * community); mslm_q_exact turns them into the reduced fraction Q. */
+ * community); mslm_q_exact turns them into the reduced fraction Q.  For the GLOBAL null model
+ * the T slots of SS hold one value, SS' = sum over communities of (sum of kappa')^2 with
+ * kappa' = b * (intra degree) + a * (coupling count), then zeros; mslm_q_exact_global reduces
+ * them. */
 typedef struct {
   double q;                       /* Q rounded to double                                    */
   int32_t n_communities, levels_run, iterations_run, colours_level0;
@@ -127,6 +140,13 @@ void mslm_destroy(mslm_graph *g);
 mslm_status mslm_q_exact(const int64_t *q_components, int32_t n_slices, int32_t n_nodes,
                          int64_t gamma_num, int64_t gamma_den, int64_t omega_num,
                          int64_t omega_den, char *num, size_t num_cap, char *den, size_t den_cap);
+
+/* The same for the GLOBAL null model: Q_G = (q 2mu' W' - p SS') / (q 2mu'^2) with
+ * W' = b * sum_s W_s + a * I and 2mu' = b * sum_s 2m_s + 2 a N (T-1).  Errors: EINVAL. */
+mslm_status mslm_q_exact_global(const int64_t *q_components, int32_t n_slices, int32_t n_nodes,
+                                int64_t gamma_num, int64_t gamma_den, int64_t omega_num,
+                                int64_t omega_den, char *num, size_t num_cap, char *den,
+                                size_t den_cap);
 
 /* Device bytes a graph and one solve on it need (admission estimate). */
 size_t mslm_footprint_bytes(const mslm_graph_desc *desc);

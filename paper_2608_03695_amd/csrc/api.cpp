@@ -19,7 +19,10 @@ namespace mslm {
 void api_finish(const GraphDev &g, const SolveSpec &sp, SolveOut &o, mslm_result *res) {
   std::string a, b;
   double qd = 0;
-  api_q_exact(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
+  if (sp.null_model == MSLM_NULL_GLOBAL)
+    api_q_exact_global(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
+  else
+    api_q_exact(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
   o.res.q = qd;
   if (res) *res = o.res;
 }
@@ -103,6 +106,25 @@ mslm_status mslm_q_exact(const int64_t *qc, int32_t T, int32_t N, int64_t gamma_
   std::string a, b;
   double qd;
   api_q_exact(qc, T, N, gamma_num / gg, gamma_den / gg, omega_num / go, omega_den / go, a, b, qd);
+  if (a.size() + 1 > num_cap || b.size() + 1 > den_cap) return fail(MSLM_EINVAL, "buffer too small");
+  memcpy(num, a.c_str(), a.size() + 1);
+  memcpy(den, b.c_str(), b.size() + 1);
+  return MSLM_OK;
+}
+
+mslm_status mslm_q_exact_global(const int64_t *qc, int32_t T, int32_t N, int64_t gamma_num,
+                         int64_t gamma_den, int64_t omega_num, int64_t omega_den, char *num,
+                         size_t num_cap, char *den, size_t den_cap) {
+  if (!qc || !num || !den || T < 1 || T > 64 || N < 1) return fail(MSLM_EINVAL, "bad arguments");
+  mslm_status s = api_check_fraction(gamma_num, gamma_den, "gamma");
+  if (s != MSLM_OK) return s;
+  s = api_check_fraction(omega_num, omega_den, "omega");
+  if (s != MSLM_OK) return s;
+  int64_t gg = gamma_num ? api_gcd(gamma_num, gamma_den) : gamma_den;
+  int64_t go = omega_num ? api_gcd(omega_num, omega_den) : omega_den;
+  std::string a, b;
+  double qd;
+  api_q_exact_global(qc, T, N, gamma_num / gg, gamma_den / gg, omega_num / go, omega_den / go, a, b, qd);
   if (a.size() + 1 > num_cap || b.size() + 1 > den_cap) return fail(MSLM_EINVAL, "buffer too small");
   memcpy(num, a.c_str(), a.size() + 1);
   memcpy(den, b.c_str(), b.size() + 1);

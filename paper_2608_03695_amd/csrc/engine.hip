@@ -88,7 +88,7 @@ struct LevelBufs {
 struct Workspace {
   Buf temp;
   // union level 0
-  Buf u_rp, u_col, u_w, u_k, u_uslice, u_usolve, u_sstart;
+  Buf u_rp, u_col, u_w, u_k, u_uslice, u_usolve, u_sstart, u_pmap;
   // per solve / per slice
   Buf s_p, s_q, s_pb, s_a, s_b, s_seed, s_uoff, s_sfirst, s_slast, s_S, s_frozen, s_cnt, s_cnt2;
   Buf fallbacks;
@@ -114,7 +114,7 @@ struct Workspace {
   Buf ref_keep;                           // active flags of solves that skip a round's redo
   // level 0 in colour-batch order (local-moving sweeps)
   Buf p_pos, p_deg, p_rp, p_col, p_w, p_k, p_slice, p_solve, p_iota, p_comm, p_goff, p_glg,
-      p_wide, p_nwide;
+      p_wide, p_nwide, p_sk, p_sk2, p_units;
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };
@@ -154,7 +154,7 @@ __global__ void k_build_validate(const int32_t *src, const int32_t *dst, const i
 
 // every intra edge in both directions, keyed (row, col); the slice comes from the offsets
 __global__ void k_build_intra(const int32_t *src, const int32_t *dst, const int32_t *w,
-                              const int64_t *off, int32_t T, int32_t N, int64_t E,
+                              const int64_t *off, int32_t T, int32_t N, int64_t E, int shift,
                               uint64_t *keys, int64_t *vals) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
@@ -166,34 +166,34 @@ __global__ void k_build_intra(const int32_t *src, const int32_t *dst, const int3
   int64_t base = (int64_t)lo * N;
   uint64_t u = (uint64_t)(base + src[e]), x = (uint64_t)(base + dst[e]);
   int64_t ww = w ? w[e] : 1;
-  keys[2 * e] = (u << 32) | x;
+  keys[2 * e] = (u << shift) | x;
   vals[2 * e] = ww;
-  keys[2 * e + 1] = (x << 32) | u;
+  keys[2 * e + 1] = (x << shift) | u;
   vals[2 * e + 1] = ww;
 }
 
 // coupling entries (i,s)<->(i,s+1) for every node i, raw weight 0 (scaled by a at use)
-__global__ void k_build_inter(int32_t N, int32_t T, uint64_t *keys, int64_t *vals) {
+__global__ void k_build_inter(int32_t N, int32_t T, int shift, uint64_t *keys, int64_t *vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t m = (int64_t)N * (T - 1);
   if (i >= m) return;
   uint64_t v = (uint64_t)i, x = (uint64_t)(i + N);
-  keys[2 * i] = (v << 32) | x;
+  keys[2 * i] = (v << shift) | x;
   vals[2 * i] = 0;
-  keys[2 * i + 1] = (x << 32) | v;
+  keys[2 * i + 1] = (x << shift) | v;
   vals[2 * i + 1] = 0;
 }
 
-__global__ void k_build_csr(const uint64_t *keys, const int64_t *vals, int64_t m, int32_t *col,
-                            int32_t *w, int64_t *rowcnt, int *nonunit) {
+__global__ void k_build_csr(const uint64_t *keys, const int64_t *vals, int64_t m, int shift,
+                            int32_t *col, int32_t *w, int64_t *rowcnt, int *nonunit) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   uint64_t k = keys[i];
-  col[i] = (int32_t)(uint32_t)k;
+  col[i] = (int32_t)(k & ((1ull << shift) - 1));
   int64_t v = vals[i];
   w[i] = (int32_t)v;
   if (v > 1) atomicOr(nonunit, 1);
-  atomicAdd(reinterpret_cast<unsigned long long *>(rowcnt + (k >> 32)), 1ull);
+  atomicAdd(reinterpret_cast<unsigned long long *>(rowcnt + (k >> shift)), 1ull);
 }
 
 // Intra degree of every unit and, per slice, 2m_s and the count of units with nonzero degree.
@@ -273,14 +273,15 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
     MSLM_HIP(hipStreamSynchronize(st));
     if (hbad) throw Error(MSLM_EINVAL, "edge list has an id out of range, a self-loop or a weight < 1");
   }
+  // keys (row << b) | column with b the bits of n: the sort covers the bits in use
+  const int shift = bits_for((uint64_t)n);
   uint64_t *k1 = ws->akeys.get<uint64_t>(mraw);
   int64_t *v1 = ws->avals.get<int64_t>(mraw);
-  if (E > 0) k_build_intra<<<nblk(E), kBS, 0, st>>>(src, dst, w, off, T, N, E, k1, v1);
-  if (ninter > 0) k_build_inter<<<nblk(ninter), kBS, 0, st>>>(N, T, k1 + 2 * E, v1 + 2 * E);
+  if (E > 0) k_build_intra<<<nblk(E), kBS, 0, st>>>(src, dst, w, off, T, N, E, shift, k1, v1);
+  if (ninter > 0) k_build_inter<<<nblk(ninter), kBS, 0, st>>>(N, T, shift, k1 + 2 * E, v1 + 2 * E);
   uint64_t *k2 = ws->akeys2.get<uint64_t>(mraw);
   int64_t *v2 = ws->avals2.get<int64_t>(mraw);
-  int endbit = 32 + bits_for((uint64_t)n);
-  MSLM_PRIM(sort_pairs_u64_i64(k1, k2, v1, v2, mraw, endbit, st, temp_alloc(ws)));
+  MSLM_PRIM(sort_pairs_u64_i64(k1, k2, v1, v2, mraw, 2 * shift, st, temp_alloc(ws)));
   int64_t *dn = ws->nuniq.get<int64_t>(1);
   MSLM_PRIM(reduce_by_key_u64_i64(k2, k1, v2, v1, dn, mraw, st, temp_alloc(ws)));
   int64_t m = 0;
@@ -293,7 +294,7 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   int *flags = ws->flag.get<int>(2);
   MSLM_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (n + 1), st));
   MSLM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 2, st));
-  if (m > 0) k_build_csr<<<nblk(m), kBS, 0, st>>>(k1, v1, m, col, wv, cnt, flags);
+  if (m > 0) k_build_csr<<<nblk(m), kBS, 0, st>>>(k1, v1, m, shift, col, wv, cnt, flags);
   int64_t *rp = g.rp.get<int64_t>(n + 1);
   MSLM_PRIM(exclusive_sum_i64(cnt, rp, n + 1, st, temp_alloc(ws)));
   int32_t *kd = g.k.get<int32_t>(n);

@@ -95,6 +95,9 @@ mslm_status make_spec(const mslm_params *p, int64_t def_on, int64_t def_od, Solv
   sp.max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 32;
   if (sp.max_sweeps > 32) return fail(MSLM_EINVAL, "max_sweeps must be <= 32");
   sp.seed = p->seed;
+  if (p->null_model != MSLM_NULL_MULTISLICE && p->null_model != MSLM_NULL_GLOBAL)
+    return fail(MSLM_EINVAL, "null_model must be MSLM_NULL_MULTISLICE or MSLM_NULL_GLOBAL");
+  sp.null_model = p->null_model;
   return MSLM_OK;
 }
 
@@ -349,6 +352,73 @@ mslm_status api_check_desc(const mslm_graph_desc *d) {
   mslm_status s = check_desc_shape(d);
   return s != MSLM_OK ? s : check_desc_edges(d);
 }
+namespace {
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+u128 gcd128(u128 a, u128 b) {
+  while (b) {
+    u128 t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+std::string dec128(u128 x) {
+  if (x == 0) return "0";
+  std::string s;
+  while (x) {
+    s.push_back(char('0' + (int)(x % 10)));
+    x /= 10;
+  }
+  return std::string(s.rbegin(), s.rend());
+}
+}  // namespace
+
+int64_t global_two_mu(int64_t sum_two_m, int64_t N, int T, const SolveSpec &sp) {
+  const i128 v = (i128)sp.b * sum_two_m + (i128)2 * sp.a * N * (T > 1 ? T - 1 : 0);
+  return v >= ((i128)1 << 62) ? ((int64_t)1 << 62) : (int64_t)v;
+}
+
+bool api_global_headroom(int64_t two_mu, const SolveSpec &sp) {
+  const int64_t pq = sp.p > sp.q ? sp.p : sp.q;
+  if (two_mu >= ((int64_t)1 << 31) || (i128)pq * two_mu * two_mu >= ((i128)1 << 62)) {
+    fail(MSLM_EOVERFLOW, "global null model: 2mu' must stay below 2^31 and max(p,q)*2mu'^2 "
+                         "below 2^62");
+    return false;
+  }
+  return true;
+}
+
+mslm_status api_q_exact_global(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
+                               int64_t ob, std::string &num, std::string &den, double &qd) {
+  // every factor is below 2^31 or (SS') below 2^62, so the numerator and the denominator
+  // stay below 2^94 and int128 holds them exactly
+  int64_t W = 0, tm = 0;
+  for (int s = 0; s < T; s++) {
+    W += c[s];
+    tm += c[2 * T + s];
+  }
+  const i128 two_mu = (i128)ob * tm + (i128)2 * oa * N * (T - 1);
+  const i128 Wp = (i128)ob * W + (i128)oa * c[3 * T];
+  if (two_mu == 0) {
+    num = "0";
+    den = "1";
+    qd = 0.0;
+    return MSLM_OK;
+  }
+  i128 nu = (i128)gq * two_mu * Wp - (i128)gp * c[T];
+  const i128 de = (i128)gq * two_mu * two_mu;
+  const bool neg = nu < 0;
+  u128 a = neg ? (u128)(-nu) : (u128)nu, b = (u128)de;
+  const u128 g = a ? gcd128(a, b) : b;
+  a /= g;
+  b /= g;
+  num = (neg && a ? "-" : "") + dec128(a);
+  den = dec128(b);
+  qd = (neg ? -1.0 : 1.0) * ((double)a / (double)b);
+  return MSLM_OK;
+}
+
 mslm_status api_check_fraction(int64_t num, int64_t den, const char *what) {
   return check_fraction(num, den, what);
 }
@@ -365,18 +435,24 @@ mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, 
 // p*b*S^2 < 2^62 with S = max(2m_s, 1) (level-0 gains); the same checks the device path
 // makes, so a request that passes them cannot fail on them later.
 mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp) {
+  int64_t sum_two_m = 0;
   for (int s = 0; s < d->n_slices; s++) {
     int64_t two_m = 0;
     for (int64_t e = d->slice_offsets[s]; e < d->slice_offsets[s + 1]; e++) {
       two_m += 2 * (int64_t)(d->weight ? d->weight[e] : 1);
       if (two_m >= kLim31) return fail(MSLM_EOVERFLOW, "a slice's total degree 2m_s reaches 2^31");
     }
+    sum_two_m += two_m;
+    if (sp.null_model == MSLM_NULL_GLOBAL) continue;
     const __int128 S = two_m > 0 ? two_m : 1;
     const __int128 a1 = (__int128)sp.q * S * ((__int128)sp.b * S + 2 * sp.a);
     const __int128 a2 = (__int128)sp.p * sp.b * S * S;
     if (a1 >= ((__int128)1 << 62) || a2 >= ((__int128)1 << 62))
       return fail(MSLM_EOVERFLOW, "gain head-room: q*2m_s*w or p*b*k*Sigma reaches 2^62");
   }
+  if (sp.null_model == MSLM_NULL_GLOBAL &&
+      !api_global_headroom(global_two_mu(sum_two_m, d->n_nodes, d->n_slices, sp), sp))
+    return MSLM_EOVERFLOW;
   return MSLM_OK;
 }
 

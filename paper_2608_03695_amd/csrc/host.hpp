@@ -13,6 +13,7 @@ namespace mslm {
 struct SolveSpec {
   int64_t p = 1, q = 1, a = 1, b = 1;
   int32_t max_levels = 32, max_iterations = 2, max_sweeps = 32;
+  int32_t null_model = MSLM_NULL_MULTISLICE;
   uint64_t seed = 0;
 };
 
@@ -30,6 +31,14 @@ mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp);
 // Q of Eq. 6 from its 3T+1 components as a reduced decimal fraction and the nearest double.
 mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
                         int64_t ob, std::string &num, std::string &den, double &qd);
+// Q_G of the global null model from its components (the same layout, SS' in slot T).
+mslm_status api_q_exact_global(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
+                               int64_t ob, std::string &num, std::string &den, double &qd);
+// The head-room preconditions of the global null model for one graph (2mu' as defined in the
+// header); false with the error text set when they fail.
+bool api_global_headroom(int64_t two_mu, const SolveSpec &sp);
+// 2mu' = b * sum_s 2m_s + 2 a N (T-1), saturated at 2^62
+int64_t global_two_mu(int64_t sum_two_m, int64_t N, int T, const SolveSpec &sp);
 // Device bytes of one solve's work buffers on a resident graph (upper estimate), and of a
 // graph plus one solve.
 size_t solve_scratch_estimate(int64_t n, int64_t nnz);

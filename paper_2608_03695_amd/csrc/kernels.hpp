@@ -43,10 +43,15 @@ struct View0 {
   const int64_t *rp;
   const int32_t *col;
   const int32_t *w;        // raw intra weight per entry, or nullptr for unit weights
-  const int32_t *k;        // intra degree per unit
+  // degree in the null model of the unit's solve: the intra degree k_i^s (Eq. 6), or the
+  // scaled supra-degree b*k_i^s + a*(coupling entries of the unit) (the global null model)
+  const int32_t *k;
   const int32_t *uslice;   // global slice of each unit
   const int64_t *sstart;   // [slices + 1] first unit of each global slice
   const int32_t *usolve;   // solve of each unit
+  // Sigma slice of each global slice (nullptr: the slice itself); a solve under the global
+  // null model maps all its slices to one Sigma slice
+  const int32_t *pmap;
   int64_t N1 = 0;          // one solve: nodes per slice (slice and solve follow from the id)
   double invN1 = 0.0;      // 1 / N1
   struct Row {
@@ -82,6 +87,7 @@ struct View0 {
   __device__ int plen(int64_t v) const { return k[v] > 0 ? 1 : 0; }
   __device__ void pent(int64_t v, int, int &gs, int64_t &kk) const {
     gs = slice_of(v);
+    if (pmap) gs = pmap[gs];
     kk = k[v];
   }
   __device__ int64_t degree(int64_t v) const { return rp[v + 1] - rp[v]; }
@@ -98,8 +104,8 @@ struct ViewP {
   const int64_t *rp;       // [n+1] rows by position
   const int32_t *col;      // neighbour position | coupling << 31
   const int32_t *w;        // raw intra weight per entry, or nullptr for unit weights
-  const int32_t *k;        // intra degree by position
-  const int32_t *slice;    // global slice by position
+  const int32_t *k;        // null-model degree by position (View0::k)
+  const int32_t *slice;    // Sigma slice by position
   const int32_t *solve;    // solve by position, or nullptr (one solve)
   const int32_t *uid;      // unit id by position
   struct Row {
@@ -1439,6 +1445,13 @@ __global__ void k_pos_of(const int32_t *units, int64_t n, int32_t *pos) {
   if (i < n) pos[units[i]] = (int32_t)i;
 }
 
+// keys ordering the level's units by (batch key, label), ids ascending among equals
+__global__ void k_pos_label_keys(const uint32_t *keys, const int32_t *units,
+                                 const uint32_t *comm, int64_t n, uint64_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ((uint64_t)keys[i] << 32) | comm[units[i]];
+}
+
 // per position: degree (for the row starts), intra degree, slice, solve, labels
 __global__ void k_pos_meta(View0 g, const int32_t *units, int64_t n, int64_t *deg, int32_t *pk,
                            int32_t *pslice, int32_t *psolve, int32_t *iota,
@@ -1451,8 +1464,11 @@ __global__ void k_pos_meta(View0 g, const int32_t *units, int64_t n, int64_t *de
   }
   const int64_t v = units[i];
   deg[i] = g.degree(v);
-  pk[i] = g.k[v];
-  pslice[i] = g.slice_of(v);
+  int gs;
+  int64_t kk;
+  g.pent(v, 0, gs, kk);
+  pk[i] = (int32_t)kk;
+  pslice[i] = gs;
   if (psolve) psolve[i] = g.solve_of(v);
   iota[i] = (int32_t)i;
   pcomm[i] = comm[v];
@@ -2689,7 +2705,7 @@ __global__ void k_rank_gather(const uint32_t *R, const uint32_t *minm, const int
 constexpr uint64_t kDropKey = ~0ull;
 template <class V>
 __global__ __launch_bounds__(256) void k_agg_keys(V g, SolveDev sd, int64_t n, const uint32_t *r,
-                                                  uint64_t *keys, int64_t *vals) {
+                                                  int shift, uint64_t *keys, int64_t *vals) {
   const int lane = threadIdx.x & 63;
   const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (u >= n) return;
@@ -2700,7 +2716,7 @@ __global__ __launch_bounds__(256) void k_agg_keys(V g, SolveDev sd, int64_t n, c
     int64_t w = g.wt(row, e, x);
     uint32_t rx = ru == kNone ? kNone : r[x];
     bool emit = ru != kNone && w != 0 && rx != ru;
-    keys[e] = emit ? (((uint64_t)ru << 32) | rx) : kDropKey;
+    keys[e] = emit ? (((uint64_t)ru << shift) | rx) : kDropKey;
     vals[e] = emit ? w : 0;
   }
 }
@@ -2709,7 +2725,8 @@ __global__ __launch_bounds__(256) void k_agg_keys(V g, SolveDev sd, int64_t n, c
 __device__ inline int64_t prof_pos(const View0 &, int64_t u, int) { return u; }
 __device__ inline int64_t prof_pos(const ViewK &g, int64_t u, int j) { return g.pp[u] + j; }
 template <class V>
-__global__ void k_agg_prof_keys(V g, int64_t n, const uint32_t *r, uint64_t *keys, int32_t *vals) {
+__global__ void k_agg_prof_keys(V g, int64_t n, const uint32_t *r, int shift, uint64_t *keys,
+                                int32_t *vals) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
   int m = g.plen(u);
@@ -2724,26 +2741,27 @@ __global__ void k_agg_prof_keys(V g, int64_t n, const uint32_t *r, uint64_t *key
     g.pent(u, jj, gs, k);
     int64_t pos = prof_pos(g, u, jj);
     bool keep = r[u] != kNone;
-    keys[pos] = keep ? (((uint64_t)r[u] << 32) | (uint32_t)gs) : kDropKey;
+    keys[pos] = keep ? (((uint64_t)r[u] << shift) | (uint32_t)gs) : kDropKey;
     vals[pos] = keep ? (int32_t)k : 0;
   }
 }
 
 // row bounds of a sorted key array (row = high 32 bits): rs[row] = first, re[row] = last + 1
-__global__ void k_row_bounds(const uint64_t *keys, int64_t m, int64_t *rs, int64_t *re) {
+// keys are (row << shift) | column, sorted
+__global__ void k_row_bounds(const uint64_t *keys, int64_t m, int shift, int64_t *rs, int64_t *re) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  uint64_t row = keys[i] >> 32;
-  if (i == 0 || (keys[i - 1] >> 32) != row) rs[row] = i;
-  if (i == m - 1 || (keys[i + 1] >> 32) != row) re[row] = i + 1;
+  uint64_t row = keys[i] >> shift;
+  if (i == 0 || (keys[i - 1] >> shift) != row) rs[row] = i;
+  if (i == m - 1 || (keys[i + 1] >> shift) != row) re[row] = i + 1;
 }
 __global__ void k_row_cnt(const int64_t *rs, const int64_t *re, int64_t n, int64_t *cnt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) cnt[i] = re[i] - rs[i];
 }
-__global__ void k_low32(const uint64_t *keys, int64_t m, int32_t *out) {
+__global__ void k_low_bits(const uint64_t *keys, int64_t m, int shift, int32_t *out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) out[i] = (int32_t)(uint32_t)keys[i];
+  if (i < m) out[i] = (int32_t)(keys[i] & ((1ull << shift) - 1));
 }
 
 template <class V>
@@ -2940,14 +2958,29 @@ __global__ void k_q_w(View0 g, int64_t n, const int32_t *memb, int64_t *W) {
   wave_add64(W, gs, s);
 }
 
+// Sigma of a membership: per Sigma slice and label, the sum of the null-model degrees
 __global__ void k_sigma_build_memb(View0 g, int64_t n, const int32_t *memb, SliceTable t) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  int k = g.k[v];
-  if (k > 0) tab_add(t, g.uslice[v], (uint32_t)memb[v], k, false);
+  int gs;
+  int64_t k;
+  g.pent(v, 0, gs, k);
+  if (k > 0) tab_add(t, gs, (uint32_t)memb[v], (int32_t)k, false);
 }
 
-// SS_s: sum over the slice's sub-table of value^2
+// Scaled supra-degree of every unit of one solve under the global null model:
+// b*k_i^s + a*c with c the unit's coupling entries (1 in the first and last slice, 2 between,
+// none for one slice).
+__global__ void k_null_degree_global(const int32_t *k, int64_t n, int64_t N, int T, int64_t a,
+                                     int64_t b, int32_t *out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t s = v / N;
+  const int c = T == 1 ? 0 : ((s == 0 || s == T - 1) ? 1 : 2);
+  out[v] = (int32_t)(b * k[v] + a * c);
+}
+
+// SS per Sigma slice: sum over the slice's sub-table of value^2
 __global__ void k_q_ss(const uint64_t *slots, const int64_t *base, int nslices, int64_t total,
                        int64_t *SS) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

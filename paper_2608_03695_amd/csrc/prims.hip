@@ -13,15 +13,17 @@
 //                tile 64 keys at a time, finds the lanes holding the same digit with eight
 //                ballots (one per digit bit), takes its rank among them from the popcount of
 //                the lower lanes and adds the group's size to the wave's running count of that
-//                digit in LDS; per-digit prefixes over the waves then place every key.
+//                digit in LDS; per-digit prefixes over the waves and over the digits place
+//                every key in an LDS copy of the tile sorted by digit, from which consecutive
+//                threads write each digit's run to consecutive output positions.
 // Within a wave the LDS read of a digit's running count and the group leader's write of the
 // new count are issued in program order, so every lane of the group sees the count before it.
 //
-// Reduce-by-key: head flags, a scan of them (segment index of every item), then each thread
-// sums the runs of its eight consecutive items: runs that start inside its range are stored
-// whole (the thread owns their head), the run it continues from the previous thread is kept
-// aside and added to its segment with an atomic in a second launch, after every owner's store.
-// Integer sums, so the result does not depend on the order of the additions.
+// Reduce-by-key: a segmented scan.  Every item is summarised by (is it a segment head, its
+// value); pairs (heads, sum since the last head) combine associatively, so one scan gives
+// every item its segment's index and running sum, and the last item of each segment writes
+// the segment out.  Three launches (tile pairs, one block scanning them, tiles rescanned and
+// written); no atomics, integer sums in the items' order.
 #include "prims.hpp"
 
 #include <hip/hip_runtime.h>
@@ -196,13 +198,18 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K *kin, const V *
                                                          V *vout, int64_t n, int bit,
                                                          const int64_t *offs, int64_t nb) {
   __shared__ uint32_t wcnt[kWaves][kDigits];   // running count per wave and digit
+  __shared__ uint32_t tstart[kDigits];         // first slot of each digit in the sorted tile
   __shared__ int64_t gofs[kDigits];            // first output position of each digit
+  __shared__ K sk[kSortTile];                  // the tile, sorted by digit
+  __shared__ V sv[kSortTile];
+  __shared__ int64_t shc[kWaves];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int i = 0; i < kWaves; i++) wcnt[i][threadIdx.x] = 0;
   gofs[threadIdx.x] = offs[(int64_t)threadIdx.x * nb + blockIdx.x];
   __syncthreads();
   // wave w walks keys [base + w*512, base + (w+1)*512) in rounds of 64
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * 64 * kSortItems;
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = tile + (int64_t)w * 64 * kSortItems;
   const uint64_t below = (1ull << lane) - 1;
   K kk[kSortItems];
   V vv[kSortItems];
@@ -224,24 +231,33 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K *kin, const V *
     if (live && (peers & below) == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  // per digit, the keys of earlier waves come first
+  // per digit: keys of earlier waves first; digits in order inside the tile
   uint32_t pre[kWaves];
-  {
-    uint32_t run = 0;
-    for (int i = 0; i < kWaves; i++) {
-      pre[i] = run;
-      run += wcnt[i][threadIdx.x];
-    }
+  uint32_t cnt = 0;
+  for (int i = 0; i < kWaves; i++) {
+    pre[i] = cnt;
+    cnt += wcnt[i][threadIdx.x];
   }
-  __syncthreads();
-  for (int i = 0; i < kWaves; i++) wcnt[i][threadIdx.x] = pre[i];
+  int64_t tot = 0;
+  const uint32_t start = (uint32_t)block_excl_sum((int64_t)cnt, shc, &tot);
+  tstart[threadIdx.x] = start;
+  for (int i = 0; i < kWaves; i++) wcnt[i][threadIdx.x] = start + pre[i];
   __syncthreads();
   for (int r = 0; r < kSortItems; r++) {
     const int64_t j = base + (int64_t)r * 64 + lane;
     if (j >= n) continue;
-    const int64_t pos = gofs[dg[r]] + wcnt[w][dg[r]] + rk[r];
-    kout[pos] = kk[r];
-    vout[pos] = vv[r];
+    const uint32_t slot = wcnt[w][dg[r]] + rk[r];
+    sk[slot] = kk[r];
+    sv[slot] = vv[r];
+  }
+  __syncthreads();
+  // consecutive threads write consecutive positions inside each digit's run
+  const int live = (int)(n - tile < kSortTile ? n - tile : kSortTile);
+  for (int s = threadIdx.x; s < live; s += kThreads) {
+    const uint32_t d = digit_of(sk[s], bit);
+    const int64_t pos = gofs[d] + (s - (int64_t)tstart[d]);
+    kout[pos] = sk[s];
+    vout[pos] = sv[s];
   }
 }
 
@@ -289,87 +305,185 @@ hipError_t radix_sort(const K *kin, K *kout, const V *vin, V *vout, int64_t n, i
 }
 
 // ------------------------------------------------------------------ reduce by key
-template <class K>
-__global__ __launch_bounds__(kThreads) void k_rbk_heads(const K *keys, int64_t n, uint8_t *head) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i < n) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+// A pair (c, s) summarises a run of items: c heads among them, s the sum of the items after
+// the last head (all of them when c == 0).  Pairs combine associatively:
+//   (c1, s1) then (c2, s2) = (c1 + c2, c2 ? s2 : s1 + s2),
+// so a scan of pairs gives every item the number of segments before it and the running sum
+// of its segment.
+template <class V>
+struct SegPair {
+  int64_t c;
+  V s;
+};
+
+template <class V>
+__device__ inline SegPair<V> seg_combine(const SegPair<V> &a, const SegPair<V> &b) {
+  return SegPair<V>{a.c + b.c, b.c ? b.s : (V)(a.s + b.s)};
+}
+
+// exclusive scan of pairs over the block; the block's total in *tot
+template <class V>
+__device__ inline SegPair<V> block_excl_pairs(SegPair<V> x, int64_t *shc, V *shs,
+                                              SegPair<V> *tot) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  SegPair<V> inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    SegPair<V> y{__shfl_up(inc.c, o, 64), __shfl_up(inc.s, o, 64)};
+    if (lane >= o) inc = seg_combine(y, inc);
+  }
+  if (lane == 63) {
+    shc[w] = inc.c;
+    shs[w] = inc.s;
+  }
+  __syncthreads();
+  SegPair<V> before{0, 0}, all{0, 0};
+  for (int i = 0; i < kWaves; i++) {
+    const SegPair<V> p{shc[i], shs[i]};
+    if (i < w) before = seg_combine(before, p);
+    all = seg_combine(all, p);
+  }
+  __syncthreads();
+  if (tot) *tot = all;
+  // exclusive: everything before this lane
+  SegPair<V> prev{__shfl_up(inc.c, 1, 64), __shfl_up(inc.s, 1, 64)};
+  if (lane == 0) prev = SegPair<V>{0, 0};
+  return seg_combine(before, prev);
+}
+
+// The block's tile of keys and values, loaded with coalesced reads into LDS; item i of the
+// tile is sk[i]; prev/next are the keys just before and after the tile (or a copy of the
+// first/last key when there is none, which never marks a head).
+template <class K, class V>
+struct RbkTile {
+  K sk[kSortTile];
+  V sv[kSortTile];
+  K prev, next;
+};
+
+template <class K, class V>
+__device__ inline int64_t load_tile(const K *keys, const V *vals, int64_t n, RbkTile<K, V> &t) {
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  const int64_t len = n - tile < kSortTile ? n - tile : kSortTile;
+  for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+    t.sk[i] = keys[tile + i];
+    t.sv[i] = vals[tile + i];
+  }
+  if (threadIdx.x == 0) {
+    t.prev = tile > 0 ? keys[tile - 1] : keys[0];
+    t.next = tile + len < n ? keys[tile + len] : keys[tile + len - 1];
+  }
+  __syncthreads();
+  return len;
 }
 
 template <class K, class V>
-__global__ __launch_bounds__(kThreads) void k_rbk_sum(const K *keys, const V *vals,
-                                                      const uint8_t *head, const int64_t *seg,
-                                                      int64_t n, K *kout, V *vout,
-                                                      int64_t *cseg, V *cval) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t lo = t * kSortItems;
-  if (lo >= n) return;
-  const int64_t hi = std::min<int64_t>(lo + kSortItems, n);
-  cseg[t] = -1;
-  int64_t i = lo;
-  if (!head[lo]) {   // the run continued from the previous thread: added after the stores
-    V s = 0;
-    while (i < hi && !head[i]) s += vals[i++];
-    cseg[t] = seg[lo] - 1;   // seg counts the heads before lo, its run's head included
-    cval[t] = s;
-  }
-  while (i < hi) {   // runs whose head this thread holds
-    const int64_t sg = seg[i];
-    const K k = keys[i];
-    V s = vals[i++];
-    while (i < hi && !head[i]) s += vals[i++];
-    kout[sg] = k;
-    vout[sg] = s;
+__device__ inline bool tile_head(const RbkTile<K, V> &t, int64_t i, int64_t tile) {
+  const K before = i > 0 ? t.sk[i - 1] : t.prev;
+  return (tile + i == 0) || t.sk[i] != before;
+}
+
+template <class K, class V>
+__device__ inline SegPair<V> thread_pair(const RbkTile<K, V> &t, int64_t lo, int64_t hi,
+                                         int64_t tile) {
+  SegPair<V> p{0, 0};
+  for (int64_t i = lo; i < hi; i++)
+    p = seg_combine(p, SegPair<V>{tile_head(t, i, tile) ? 1 : 0, t.sv[i]});
+  return p;
+}
+
+template <class K, class V>
+__global__ __launch_bounds__(kThreads) void k_rbk_tiles(const K *keys, const V *vals, int64_t n,
+                                                        int64_t *tc, V *ts) {
+  __shared__ RbkTile<K, V> t;
+  __shared__ int64_t shc[kWaves];
+  __shared__ V shs[kWaves];
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  const int64_t len = load_tile(keys, vals, n, t);
+  const int64_t lo = (int64_t)threadIdx.x * kSortItems;
+  const int64_t hi = lo + kSortItems < len ? lo + kSortItems : len;
+  SegPair<V> tot;
+  block_excl_pairs<V>(thread_pair(t, lo, hi, tile), shc, shs, &tot);
+  if (threadIdx.x == 0) {
+    tc[blockIdx.x] = tot.c;
+    ts[blockIdx.x] = tot.s;
   }
 }
 
+// one block: exclusive scan of the tile pairs in place (nb <= kMaxBlockSums); the total
+// count of segments into *nout
 template <class V>
-__global__ __launch_bounds__(kThreads) void k_rbk_carry(const int64_t *cseg, const V *cval,
-                                                        int64_t nt, V *vout);
-
-template <>
-__global__ __launch_bounds__(kThreads) void k_rbk_carry<int64_t>(const int64_t *cseg,
-                                                                 const int64_t *cval, int64_t nt,
-                                                                 int64_t *vout) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t < nt && cseg[t] >= 0)
-    atomicAdd(reinterpret_cast<unsigned long long *>(vout + cseg[t]),
-              (unsigned long long)cval[t]);
+__global__ __launch_bounds__(1024) void k_rbk_scan_tiles(int64_t *tc, V *ts, int64_t nb,
+                                                         int64_t *nout) {
+  __shared__ int64_t shc[16];
+  __shared__ V shs[16];
+  const int per = (int)((nb + 1023) / 1024);
+  const int64_t lo = (int64_t)threadIdx.x * per;
+  SegPair<V> x{0, 0};
+  for (int64_t i = lo; i < lo + per && i < nb; i++) x = seg_combine(x, SegPair<V>{tc[i], ts[i]});
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  SegPair<V> inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    SegPair<V> y{__shfl_up(inc.c, o, 64), __shfl_up(inc.s, o, 64)};
+    if (lane >= o) inc = seg_combine(y, inc);
+  }
+  if (lane == 63) {
+    shc[w] = inc.c;
+    shs[w] = inc.s;
+  }
+  __syncthreads();
+  SegPair<V> run{0, 0};
+  for (int i = 0; i < w; i++) run = seg_combine(run, SegPair<V>{shc[i], shs[i]});
+  SegPair<V> prev{__shfl_up(inc.c, 1, 64), __shfl_up(inc.s, 1, 64)};
+  if (lane == 0) prev = SegPair<V>{0, 0};
+  run = seg_combine(run, prev);
+  for (int64_t i = lo; i < lo + per && i < nb; i++) {
+    const SegPair<V> t{tc[i], ts[i]};
+    tc[i] = run.c;
+    ts[i] = run.s;
+    run = seg_combine(run, t);
+  }
+  if (threadIdx.x == 1023) *nout = run.c;
 }
 
-template <>
-__global__ __launch_bounds__(kThreads) void k_rbk_carry<int32_t>(const int64_t *cseg,
-                                                                 const int32_t *cval, int64_t nt,
-                                                                 int32_t *vout) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t < nt && cseg[t] >= 0) atomicAdd(vout + cseg[t], cval[t]);
-}
-
-__global__ void k_rbk_count(const uint8_t *head, const int64_t *seg, int64_t n, int64_t *nout) {
-  *nout = seg[n - 1] + head[n - 1];
+// every item knows the segments before it and its segment's running sum; the last item of a
+// segment writes the segment's key and sum
+template <class K, class V>
+__global__ __launch_bounds__(kThreads) void k_rbk_emit(const K *keys, const V *vals, int64_t n,
+                                                       const int64_t *tc, const V *ts, K *kout,
+                                                       V *vout) {
+  __shared__ RbkTile<K, V> t;
+  __shared__ int64_t shc[kWaves];
+  __shared__ V shs[kWaves];
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  const int64_t len = load_tile(keys, vals, n, t);
+  const int64_t lo = (int64_t)threadIdx.x * kSortItems;
+  const int64_t hi = lo + kSortItems < len ? lo + kSortItems : len;
+  SegPair<V> run = block_excl_pairs<V>(thread_pair(t, lo, hi, tile), shc, shs, nullptr);
+  run = seg_combine(SegPair<V>{tc[blockIdx.x], ts[blockIdx.x]}, run);
+  for (int64_t i = lo; i < hi; i++) {
+    run = seg_combine(run, SegPair<V>{tile_head(t, i, tile) ? 1 : 0, t.sv[i]});
+    const bool last = tile + i + 1 == n || (i + 1 < len ? t.sk[i + 1] : t.next) != t.sk[i];
+    if (last) {
+      kout[run.c - 1] = t.sk[i];
+      vout[run.c - 1] = run.s;
+    }
+  }
 }
 
 template <class K, class V>
 hipError_t reduce_by_key(const K *kin, K *kout, const V *vin, V *vout, int64_t *nout, int64_t n,
                          hipStream_t st, TempAlloc ta) {
   if (n <= 0) return hipMemsetAsync(nout, 0, sizeof(int64_t), st);
-  const int64_t nt = (n + kSortItems - 1) / kSortItems;
-  const size_t bytes = Carve::need({(size_t)n, sizeof(int64_t) * (size_t)n,
-                                    sizeof(int64_t) * (size_t)nt, sizeof(V) * (size_t)nt}) +
-                       scan_temp<uint8_t>(n);
-  void *p = ta.get(ta.ctx, bytes);
+  const int64_t nb = grid_for(n, kSortTile);
+  if (nb > kMaxBlockSums) return hipErrorInvalidValue;
+  void *p = ta.get(ta.ctx, Carve::need({sizeof(int64_t) * (size_t)nb, sizeof(V) * (size_t)nb}));
   if (!p) return hipErrorOutOfMemory;
   Carve c{static_cast<char *>(p)};
-  uint8_t *head = c.take<uint8_t>(n);
-  int64_t *seg = c.take<int64_t>(n);
-  int64_t *cseg = c.take<int64_t>(nt);
-  V *cval = c.take<V>(nt);
-  k_rbk_heads<K><<<grid_for(n, kThreads), kThreads, 0, st>>>(kin, n, head);
-  hipError_t e = scan_run<uint8_t>(head, seg, n, st, c);
-  if (e != hipSuccess) return e;
-  k_rbk_sum<K, V><<<grid_for(nt, kThreads), kThreads, 0, st>>>(kin, vin, head, seg, n, kout, vout,
-                                                              cseg, cval);
-  k_rbk_carry<V><<<grid_for(nt, kThreads), kThreads, 0, st>>>(cseg, cval, nt, vout);
-  k_rbk_count<<<1, 1, 0, st>>>(head, seg, n, nout);
+  int64_t *tc = c.take<int64_t>(nb);
+  V *ts = c.take<V>(nb);
+  k_rbk_tiles<K, V><<<(unsigned)nb, kThreads, 0, st>>>(kin, vin, n, tc, ts);
+  k_rbk_scan_tiles<V><<<1, 1024, 0, st>>>(tc, ts, nb, nout);
+  k_rbk_emit<K, V><<<(unsigned)nb, kThreads, 0, st>>>(kin, vin, n, tc, ts, kout, vout);
   return hipGetLastError();
 }
 

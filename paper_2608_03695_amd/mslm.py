@@ -19,8 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libmslm.so")
 MSLM_OK, MSLM_EINVAL, MSLM_ENOMEM, MSLM_EOVERFLOW, MSLM_EUNSUPPORTED, MSLM_EHIP, MSLM_EBUSY = \
     0, -1, -2, -3, -4, -5, -6
 MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE, MSLM_COUNT = 1, 2, 4, 8
+MSLM_NULL_MULTISLICE, MSLM_NULL_GLOBAL = 0, 1
 
-EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_footprint_bytes",
+EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_q_exact_global",
+            "mslm_footprint_bytes",
             "mslm_graph_info", "mslm_last_error", "mslm_set_allocator", "mslm_leiden_static",
             "mslm_batch_leiden",
             "mslm_server_create", "mslm_server_submit", "mslm_server_wait",
@@ -49,7 +51,7 @@ class Params(C.Structure):
     _fields_ = [("gamma_num", C.c_int64), ("gamma_den", C.c_int64),
                 ("omega_num", C.c_int64), ("omega_den", C.c_int64),
                 ("max_levels", C.c_int32), ("max_iterations", C.c_int32),
-                ("max_sweeps", C.c_int32), ("reserved0", C.c_int32),
+                ("max_sweeps", C.c_int32), ("null_model", C.c_int32),
                 ("seed", C.c_uint64), ("flags", C.c_uint32), ("reserved1", C.c_uint32)]
 
 
@@ -111,6 +113,8 @@ def load():
     lib.mslm_q_exact.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
                                  C.c_int64, C.c_char_p, C.c_size_t, C.c_char_p, C.c_size_t]
     lib.mslm_q_exact.restype = C.c_int
+    lib.mslm_q_exact_global.argtypes = lib.mslm_q_exact.argtypes
+    lib.mslm_q_exact_global.restype = C.c_int
     lib.mslm_footprint_bytes.argtypes = [C.POINTER(GraphDesc)]
     lib.mslm_footprint_bytes.restype = C.c_size_t
     lib.mslm_graph_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -161,7 +165,7 @@ def _desc(tg, omega):
 
 
 def params(gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
-           flags=0) -> Params:
+           flags=0, null_model=MSLM_NULL_MULTISLICE) -> Params:
     gamma = Fraction(gamma)
     if omega is None:
         on, od = 0, 0
@@ -169,7 +173,7 @@ def params(gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_s
         omega = Fraction(omega)
         on, od = omega.numerator, omega.denominator
     return Params(gamma.numerator, gamma.denominator, on, od, max_levels, max_iterations,
-                  max_sweeps, 0, seed, flags, 0)
+                  max_sweeps, null_model, seed, flags, 0)
 
 
 def stream_handle(stream=None):
@@ -208,10 +212,12 @@ class Graph:
         return dict(n_supra=n.value, nnz=m.value, two_m=t.value)
 
     def leiden(self, gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0,
-               seed=0, profile=False, count=False, out=None, no_alloc=False):
+               seed=0, profile=False, count=False, out=None, no_alloc=False,
+               null_model=MSLM_NULL_MULTISLICE):
         """Returns (membership int32[T*N], result dict).  `out` may be a device tensor
         (torch, int32, T*N elements) to receive the membership on the device.  no_alloc
-        calls the allocation-free entry point (mslm_leiden_static)."""
+        calls the allocation-free entry point (mslm_leiden_static).  null_model selects
+        Q_MS (Eq. 6, the default) or the global modularity of the supra-graph (Eq. 5)."""
         lib = load()
         flags = (MSLM_PROFILE if profile else 0) | (MSLM_COUNT if count else 0)
         if out is not None:
@@ -221,7 +227,7 @@ class Graph:
         else:
             memb = np.empty(self.n_nodes * self.n_slices, dtype=np.int32)
             dest = _ptr(memb)
-        p = params(gamma, omega, max_levels, max_iterations, max_sweeps, seed, flags)
+        p = params(gamma, omega, max_levels, max_iterations, max_sweeps, seed, flags, null_model)
         res = Result()
         entry = lib.mslm_leiden_static if no_alloc else lib.mslm_leiden
         _check(entry(self._h, C.byref(p), dest, C.byref(res)))
@@ -237,6 +243,20 @@ def q_exact(components, n_slices, n_nodes, gamma, omega) -> Fraction:
     den = C.create_string_buffer(4096)
     _check(lib.mslm_q_exact(_ptr(comps), n_slices, n_nodes, gamma.numerator, gamma.denominator,
                             omega.numerator, omega.denominator, num, 4096, den, 4096))
+    return Fraction(int(num.value.decode()), int(den.value.decode()))
+
+
+def q_exact_global(components, n_slices, n_nodes, gamma, omega) -> Fraction:
+    """Exact global modularity of the supra-graph (Eq. 5) from a global-null-model solve's
+    components, via the library's reduction."""
+    lib = load()
+    gamma, omega = Fraction(gamma), Fraction(omega)
+    comps = np.ascontiguousarray(components, dtype=np.int64)
+    num = C.create_string_buffer(4096)
+    den = C.create_string_buffer(4096)
+    _check(lib.mslm_q_exact_global(_ptr(comps), n_slices, n_nodes, gamma.numerator,
+                                   gamma.denominator, omega.numerator, omega.denominator, num,
+                                   4096, den, 4096))
     return Fraction(int(num.value.decode()), int(den.value.decode()))
 
 
@@ -283,9 +303,9 @@ class Server:
         self._shape = {}
 
     def submit(self, tg, gamma=Fraction(1), omega=Fraction(1), max_levels=32, max_iterations=2,
-               seed=0) -> int:
+               seed=0, null_model=MSLM_NULL_MULTISLICE) -> int:
         d, keep = _desc(tg, omega)
-        p = params(gamma, None, max_levels, max_iterations, 0, seed, 0)
+        p = params(gamma, None, max_levels, max_iterations, 0, seed, 0, null_model)
         t = C.c_uint64()
         _check(load().mslm_server_submit(self._h, C.byref(d), C.byref(p), C.byref(t)))
         self._shape[t.value] = (tg.n_nodes, tg.n_slices)
@@ -320,19 +340,22 @@ class Server:
 
 
 def batch_leiden(graphs: Sequence[Graph], solves, stream=None):
-    """solves: list of (graph index, gamma, omega, max_levels, max_iterations, seed).
-    Returns a list of (membership, result dict), bit-identical to plain calls."""
+    """solves: list of (graph index, gamma, omega, max_levels, max_iterations, seed) with an
+    optional seventh item, the null model.  Returns a list of (membership, result dict),
+    bit-identical to plain calls."""
     lib = load()
     arr = (C.c_void_p * len(graphs))(*[g._h for g in graphs])
     cs = (Solve * len(solves))()
     outs = []
-    for i, (gi, gamma, omega, levels, iters, seed) in enumerate(solves):
+    for i, sv in enumerate(solves):
+        gi, gamma, omega, levels, iters, seed = sv[:6]
+        null_model = sv[6] if len(sv) > 6 else MSLM_NULL_MULTISLICE
         g = graphs[gi]
         memb = np.empty(g.n_nodes * g.n_slices, dtype=np.int32)
         res = Result()
         outs.append((memb, res, g.n_slices))
         cs[i].graph = gi
-        cs[i].params = params(gamma, omega, levels, iters, 0, seed, 0)
+        cs[i].params = params(gamma, omega, levels, iters, 0, seed, 0, null_model)
         cs[i].membership = memb.ctypes.data
         cs[i].result = C.addressof(res)
     _check(lib.mslm_batch_leiden(arr, len(graphs), cs, len(solves), stream_handle(stream)))

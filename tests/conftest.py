@@ -20,3 +20,10 @@ def pytest_sessionstart(session):
     import oracle
     if not oracle._is_current():
         oracle.build(force=True)
+    # a session that selects GPU tests draws the full-size inputs first, before any test
+    # brings up the GPU in this process
+    markexpr = session.config.option.markexpr or ""
+    if "gpu" in markexpr and "not gpu" not in markexpr:
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+        import full_size_inputs
+        full_size_inputs.prepare(workers=min(16, os.cpu_count() or 1))

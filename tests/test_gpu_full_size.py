@@ -1,0 +1,80 @@
+"""GPU parity at full size against results the oracle wrote (tests/golden/make_expected.py
+calls only the oracle):
+
+* config 3 (T=64 x N=1M DC-SBM, exponent 2.1, mu 0.4, omega 1/2): membership sha256, the 193 Q
+  components, Q as a reduced fraction and every schedule statistic;
+* the batched workload: every (gamma, omega) of the 3x3 grid on every 8th of its 512 graphs
+  (576 solves) run as batched calls, each solve's membership and Q components against the
+  oracle's digest and statistics.
+
+The inputs are drawn at the start of the GPU session (tests/full_size_inputs.py).
+"""
+import hashlib
+import json
+import os
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import full_size_inputs as fsi
+from paper_2608_03695_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+STAT_KEYS = ["sweeps", "moves", "sweep_cap_hits", "refine_rounds", "merges", "splits",
+             "levels_run", "iterations_run", "n_communities"]
+
+
+def _golden(name):
+    path = os.path.join(fsi.GOLDEN, f"{name}_expected.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no oracle record {name}_expected.json")
+    return json.load(open(path))
+
+
+def _digest(memb, comps):
+    h = hashlib.sha256(np.ascontiguousarray(memb, dtype=np.int32).tobytes())
+    h.update(np.ascontiguousarray(comps, dtype=np.int64).tobytes())
+    return h.hexdigest()
+
+
+def test_config3_full_size_matches_oracle_record():
+    from paper_2608_03695_amd import mslm
+    exp = _golden("cfg3")
+    tg = fsi.load(fsi.cfg3_path())
+    assert tg.name == exp["workload"] and tg.n_edges == exp["n_edges"]
+    spec = gen.CONFIG_SOLVE[3]
+    g = mslm.Graph(tg, spec.omega)
+    memb, r = g.leiden(spec.gamma, max_levels=spec.max_levels,
+                       max_iterations=spec.max_iterations, seed=spec.seed)
+    g.close()
+    assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == exp["membership_sha256"]
+    assert [int(x) for x in r["q_components"]] == exp["q_components"]
+    q = mslm.q_exact(r["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
+    assert f"{q.numerator}/{q.denominator}" == exp["q"]
+    for k in STAT_KEYS:
+        assert r[k] == exp["stats"][k], k
+
+
+def test_batched_workload_sample_matches_oracle_digests():
+    from paper_2608_03695_amd import mslm
+    exp = _golden("cfg4")
+    want = {(s["graph"], s["gamma"], s["omega"]): s for s in exp["solves"]}
+    graphs = exp["graphs"]
+    handles = [mslm.Graph(fsi.load(fsi.cfg4_path(g)), 1) for g in graphs]
+    solves = [(i, gam, om, 32, 2, 0) for i in range(len(graphs))
+              for gam in gen.GAMMA_GRID for om in gen.OMEGA_GRID]
+    checked = 0
+    for c0 in range(0, len(solves), 96):
+        chunk = solves[c0:c0 + 96]
+        for (i, gam, om, *_), (m, r) in zip(chunk, mslm.batch_leiden(handles, chunk)):
+            s = want[(graphs[i], str(gam), str(om))]
+            case = f"graph {graphs[i]} gamma={gam} omega={om}"
+            assert _digest(m, r["q_components"][:3 * handles[i].n_slices + 1]) == s["digest"], case
+            for k in STAT_KEYS:
+                assert r[k] == s["stats"][k], f"{case}: {k}"
+            checked += 1
+    for h in handles:
+        h.close()
+    assert checked == len(exp["solves"]) == 576

@@ -89,3 +89,42 @@ def test_footprint_grows_with_the_graph():
     small = mslm.footprint_bytes(gen.erdos_renyi(100, 2, 0.05, seed=1))
     large = mslm.footprint_bytes(gen.erdos_renyi(400, 4, 0.05, seed=1))
     assert 0 < small < large
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_exact_global_q_reduction_matches_rationals(seed):
+    """The library's reduction of the global null model's components (SS' in the first SS
+    slot) against the oracle's rational formula, inside the documented head-room:
+    2mu' < 2^31 and max(p, q) * 2mu'^2 < 2^62."""
+    rng = random.Random(500 + seed)
+    T = rng.randint(1, 64)
+    N = rng.randint(1, 10 ** 4)
+    omega = F(rng.randint(0, 50), rng.randint(1, 50))
+    a, b = omega.numerator, omega.denominator
+    budget = (2 ** 31 - 1 - 2 * a * N * (T - 1)) // b
+    if budget < T:
+        omega, a, b = F(0), 0, 1
+        budget = 2 ** 31 - 1
+    comps = np.zeros(3 * T + 1, np.int64)
+    for s in range(T):
+        tm = rng.choice([0, rng.randint(1, max(1, budget // T))])
+        comps[2 * T + s] = tm
+        comps[s] = rng.randint(0, tm) if tm else 0
+    comps[3 * T] = 2 * rng.randint(0, N * (T - 1))
+    two_mu = b * int(comps[2 * T:3 * T].sum()) + 2 * a * N * (T - 1)
+    assert two_mu < 2 ** 31
+    comps[T] = rng.randint(0, two_mu * two_mu)
+    lim = (2 ** 62 - 1) // max(1, two_mu * two_mu)
+    gamma = F(rng.randint(0, min(lim, 2 ** 31 - 1)), rng.randint(1, min(lim, 2 ** 31 - 1)))
+    want = oracle.q_global_from_components(comps, N, T, gamma, omega)
+    assert mslm.q_exact_global(comps, T, N, gamma, omega) == want
+
+
+def test_exact_global_q_of_the_hand_example():
+    """N=2, T=2, edge 0-1 in both slices, omega = gamma = 1.  One community: W' = 4 + I = 8
+    (I = 4 ordered coupled pairs), 2mu' = 8, SS' = 8^2, Q_G = 0.  By node ({0,2},{1,3}): no
+    intra weight inside, I = 4, SS' = 2 * 4^2, Q_G = (8*4 - 32)/64 = 0.  Singletons:
+    SS' = 4 * 2^2, Q_G = -16/64."""
+    assert mslm.q_exact_global(np.array([2, 2, 64, 0, 2, 2, 4]), 2, 2, 1, 1) == 0
+    assert mslm.q_exact_global(np.array([0, 0, 32, 0, 2, 2, 4]), 2, 2, 1, 1) == 0
+    assert mslm.q_exact_global(np.array([0, 0, 16, 0, 2, 2, 0]), 2, 2, 1, 1) == F(-1, 4)
