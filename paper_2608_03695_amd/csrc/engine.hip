@@ -88,7 +88,7 @@ struct LevelBufs {
 struct Workspace {
   Buf temp;
   // union level 0
-  Buf u_rp, u_col, u_w, u_k, u_uslice, u_usolve, u_sstart, u_pmap;
+  Buf u_rp, u_col, u_w, u_k, u_uslice, u_usolve, u_sstart, u_pmap, u_rev;
   // per solve / per slice
   Buf s_p, s_q, s_pb, s_a, s_b, s_seed, s_uoff, s_sfirst, s_slast, s_S, s_frozen, s_cnt, s_cnt2;
   Buf fallbacks;
@@ -112,9 +112,10 @@ struct Workspace {
   Buf ref_wide, ref_wcnt;                 // refinement units with long rows, and their count
   Buf ref_snap_a, ref_snap_p;             // active flags and proposal stamps before a round
   Buf ref_keep;                           // active flags of solves that skip a round's redo
+  Buf lat_part, lat_done;                 // latency mode: candidates split among blocks
   // level 0 in colour-batch order (local-moving sweeps)
   Buf p_pos, p_deg, p_rp, p_col, p_w, p_k, p_slice, p_solve, p_iota, p_comm, p_goff, p_glg,
-      p_wide, p_nwide, p_sk, p_sk2, p_units;
+      p_wide, p_nwide, p_sk, p_sk2, p_units, p_elab, p_prev;
   LevelBufs lvA, lvB;
   std::vector<hipEvent_t> evpool;
 };
@@ -194,6 +195,26 @@ __global__ void k_build_csr(const uint64_t *keys, const int64_t *vals, int64_t m
   w[i] = (int32_t)v;
   if (v > 1) atomicOr(nonunit, 1);
   atomicAdd(reinterpret_cast<unsigned long long *>(rowcnt + (k >> shift)), 1ull);
+}
+
+// Reverse entries: entry e = (u, x) (its sorted unique key) finds (x, u) in x's row, whose
+// columns ascend, by binary search; the offset within x's row is stored.  The supra-graph is
+// symmetric, so the search always succeeds.
+__global__ void k_build_rev(const uint64_t *keys, int64_t m, int shift, const int64_t *rp,
+                            const int32_t *col, int32_t *rev) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const uint64_t k = keys[e];
+  const int32_t u = (int32_t)(k >> shift);
+  const int64_t x = (int64_t)(k & ((1ull << shift) - 1));
+  const int64_t r0 = rp[x];
+  int64_t lo = r0, hi = rp[x + 1];   // col[lo] <= u < col[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  rev[e] = (int32_t)(lo - r0);
 }
 
 // Intra degree of every unit and, per slice, 2m_s and the count of units with nonzero degree.
@@ -297,6 +318,8 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   if (m > 0) k_build_csr<<<nblk(m), kBS, 0, st>>>(k1, v1, m, shift, col, wv, cnt, flags);
   int64_t *rp = g.rp.get<int64_t>(n + 1);
   MSLM_PRIM(exclusive_sum_i64(cnt, rp, n + 1, st, temp_alloc(ws)));
+  int32_t *rev = g.rev.get<int32_t>(m);
+  if (m > 0) k_build_rev<<<nblk(m), kBS, 0, st>>>(k1, m, shift, rp, col, rev);
   int32_t *kd = g.k.get<int32_t>(n);
   int64_t *twom = ws->b_twom.get<int64_t>(2 * T);
   MSLM_HIP(hipMemsetAsync(twom, 0, sizeof(int64_t) * 2 * T, st));

@@ -132,6 +132,7 @@ struct GraphDev {
   std::vector<int64_t> twom;     // per slice, host copy
   std::vector<int64_t> nzslice;  // per slice: units of nonzero degree
   Buf rp, col, w, k;
+  Buf rev;   // per entry (u, x): offset of the entry (x, u) within x's row
 };
 
 struct SolveOut {

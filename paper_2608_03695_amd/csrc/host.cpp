@@ -336,8 +336,9 @@ void api_clear_error() { g_err.clear(); }
 const char *api_error_text() { return g_err.c_str(); }
 size_t solve_scratch_estimate(int64_t n, int64_t nnz) {
   // aggregation keys and values double-buffered, sort scratch, two aggregated levels,
-  // per-unit state, the Sigma tables and level 0 laid out in colour-batch order
-  return (size_t)(96 * nnz + 384 * n) + ((size_t)1 << 20);
+  // per-unit state, the Sigma tables and level 0 laid out in colour-batch order (with the
+  // neighbour-label copy and reverse entries)
+  return (size_t)(104 * nnz + 384 * n) + ((size_t)1 << 20);
 }
 size_t footprint_estimate(const mslm_graph_desc *d) {
   if (check_desc_shape(d) != MSLM_OK) return 0;
@@ -345,7 +346,7 @@ size_t footprint_estimate(const mslm_graph_desc *d) {
   const int64_t E = d->slice_offsets[d->n_slices];
   const int64_t nnz = 2 * E + 2 * (int64_t)d->n_nodes * (d->n_slices - 1);
   // resident graph + peak of one solve
-  return (size_t)(8 * (n + 1) + 8 * nnz + 4 * n) + solve_scratch_estimate(n, nnz) + (64u << 20);
+  return (size_t)(8 * (n + 1) + 12 * nnz + 4 * n) + solve_scratch_estimate(n, nnz) + (64u << 20);
 }
 mslm_status api_check_shape(const mslm_graph_desc *d) { return check_desc_shape(d); }
 mslm_status api_check_desc(const mslm_graph_desc *d) {

@@ -52,6 +52,7 @@ struct View0 {
   // Sigma slice of each global slice (nullptr: the slice itself); a solve under the global
   // null model maps all its slices to one Sigma slice
   const int32_t *pmap;
+  const int32_t *rev;      // per entry (u, x): offset of (x, u) within x's row
   int64_t N1 = 0;          // one solve: nodes per slice (slice and solve follow from the id)
   double invN1 = 0.0;      // 1 / N1
   struct Row {
@@ -84,6 +85,7 @@ struct View0 {
     return x;
   }
   __device__ int64_t orig(int64_t v) const { return v; }
+  __device__ uint32_t lab_at(const uint32_t *comm, int64_t, int64_t x) const { return comm[x]; }
   __device__ int plen(int64_t v) const { return k[v] > 0 ? 1 : 0; }
   __device__ void pent(int64_t v, int, int &gs, int64_t &kk) const {
     gs = slice_of(v);
@@ -108,6 +110,11 @@ struct ViewP {
   const int32_t *slice;    // Sigma slice by position
   const int32_t *solve;    // solve by position, or nullptr (one solve)
   const int32_t *uid;      // unit id by position
+  // per entry, the neighbour's current label (kept up to date by the moves: a moved unit
+  // writes its new label into the entries that point at it, found through prev), so the
+  // decisions read labels in entry order instead of gathering them; nullptr: gather
+  uint32_t *elab;
+  const int32_t *prev;     // per entry (i, x): index of the entry (x, i)
   struct Row {
     int64_t lo, hi, a, b;
   };
@@ -126,6 +133,9 @@ struct ViewP {
     return raw;
   }
   __device__ int64_t orig(int64_t i) const { return uid[i]; }
+  __device__ uint32_t lab_at(const uint32_t *comm, int64_t e, int64_t x) const {
+    return elab ? elab[e] : comm[x];
+  }
   __device__ int plen(int64_t i) const { return k[i] > 0 ? 1 : 0; }
   __device__ void pent(int64_t i, int, int &gs, int64_t &kk) const {
     gs = slice[i];
@@ -154,6 +164,7 @@ struct ViewK {
     return col[e];
   }
   __device__ int64_t orig(int64_t v) const { return v; }
+  __device__ uint32_t lab_at(const uint32_t *comm, int64_t, int64_t x) const { return comm[x]; }
   __device__ int solve_of(int64_t v) const { return usolve[v]; }
   __device__ int plen(int64_t v) const { return (int)(pp[v + 1] - pp[v]); }
   __device__ void pent(int64_t v, int j, int &gs, int64_t &kk) const {
@@ -714,30 +725,100 @@ struct LmCounters {
   unsigned long long *c;
 };
 
+// Candidates of one unit shared by B blocks (latency mode, units spanning several slices with
+// many candidates): each block builds the unit's whole table, evaluates the heaviest candidate
+// (it seeds pruning) and the candidates whose label hashes to its part, and publishes its
+// best; the block that finishes last reduces the B bests in the same total order (value, then
+// label) and decides.  The result is the one a single block reaches.
+struct CandSplit {
+  int part = 0, B = 1;
+  uint16_t *L2 = nullptr;   // LDS list of this block's candidate slots
+  int *n2 = nullptr;
+  ScoreK *parts = nullptr;  // [B] published bests of this unit
+  uint32_t *done = nullptr; // blocks of this unit finished (the last one resets it to 0)
+  int *last = nullptr;      // LDS: this block reduces
+  __device__ bool mine(uint32_t lab) const {
+    return (int)(((uint64_t)(lab * 2654435769u) * (uint32_t)B) >> 32) == part;
+  }
+};
+
+// This block's list of its own candidates (B > 1), else the table itself.
+template <class Grp, class Tab>
+__device__ inline Tab split_view(Grp grp, const Tab &tab, const CandSplit &cs) {
+  Tab ctab = tab;
+  if constexpr (std::is_same<Tab, LdsTab>::value) {
+    if (cs.B > 1) {
+      const int r = grp.rank(), gsz = grp.size();
+      if (r == 0) *cs.n2 = 0;
+      grp.sync();
+      const int nc = tab.count();
+      for (int i = r; i < nc; i += gsz) {
+        const int h = tab.slot(i);
+        const uint32_t key = tab.K[h];
+        if (key != 0 && cs.mine(key - 1)) cs.L2[atomicAdd(cs.n2, 1)] = (uint16_t)h;
+      }
+      grp.sync();
+      ctab.L = cs.L2;
+      ctab.n = cs.n2;
+    }
+  }
+  return ctab;
+}
+
+// Publish this block's best; true in the block that finishes last, whose `best` is then the
+// best over all B blocks.
+template <class P, class V, class Grp>
+__device__ inline bool split_reduce(Grp grp, const V &g, const UnitCtx &u, const SolveDev &sd,
+                                    const SliceTable &sig, const CandSplit &cs,
+                                    typename P::Score &best) {
+  if constexpr (std::is_same<typename P::Score, ScoreK>::value) {
+    if (grp.rank() == 0) {
+      cs.parts[cs.part] = best;
+      __threadfence();
+      const uint32_t old = atomicAdd(cs.done, 1u);
+      *cs.last = old == (uint32_t)(cs.B - 1);
+    }
+    grp.sync();
+    const bool last = *cs.last != 0;
+    grp.sync();
+    if (!last) return false;
+    __threadfence();
+    for (int i = 0; i < cs.B; i++) {
+      const ScoreK o = cs.parts[i];
+      if (better<P>(g, u, sd, sig, o, best)) best = o;
+    }
+    if (grp.rank() == 0) *cs.done = 0;
+    return true;
+  } else {
+    return true;
+  }
+}
+
 template <class P, class Grp, class Tab, class V>
 __device__ inline uint32_t lm_unit_coop(Grp grp, Tab tab, const V &g, const SolveDev &sd,
                                         const UnitCtx &u, const SliceTable &sig,
                                         uint32_t fresh_base, typename P::Score *red,
                                         LmCounters pc, typename P::Score best, int64_t hW,
-                                        uint32_t hL) {
+                                        uint32_t hL, const CandSplit &cs) {
   const int r = grp.rank(), gsz = grp.size();
   const CoopLane c = coop_lane(g, u, sd, sig, r);
+  const Tab ctab = split_view(grp, tab, cs);
   const int sub = r / c.mp, nsub = gsz / c.mp;
   int ncand = 0;
   if (hL != kNone) {
     ScoreK s = coop_make(u, c, hL, hW, kTarget);
     if (better<P>(g, u, sd, sig, s, best)) best = s;
-    ncand = r == 0;
+    ncand = r == 0 && cs.part == 0;
   }
   // subgroups take table slots kCoopBatch at a time; every lane runs the same turns
-  const int nc = tab.count();
+  const int nc = ctab.count();
   for (int i0 = 0; i0 < nc; i0 += nsub * kCoopBatch) {
     uint32_t lab[kCoopBatch];
     int64_t W[kCoopBatch], y[kCoopBatch];
     bool ok[kCoopBatch];
     for (int k = 0; k < kCoopBatch; k++) {
       const int i = i0 + k * nsub + sub;
-      const int h = i < nc ? tab.slot(i) : 0;
+      const int h = i < nc ? ctab.slot(i) : 0;
       const uint32_t key = i < nc ? tab.K[h] : 0u;
       lab[k] = key - 1;
       ok[k] = key != 0 && key - 1 != u.D && key - 1 != hL;
@@ -754,12 +835,13 @@ __device__ inline uint32_t lm_unit_coop(Grp grp, Tab tab, const V &g, const Solv
   }
   if (pc.c) {
     if (ncand) atomicAdd(pc.c + 2, (unsigned long long)ncand);
-    if (r == 0) {
+    if (r == 0 && cs.part == 0) {
       atomicAdd(pc.c + 0, 1ull);
       atomicAdd(pc.c + 1, (unsigned long long)g.degree(u.v));
     }
   }
   best = group_best<P>(grp, g, u, sd, sig, best, red);
+  if (cs.B > 1 && !split_reduce<P>(grp, g, u, sd, sig, cs, best)) return kNone;
   const int64_t wD = tab.get(u.D);
   const ScoreK stay = coop_make(u, c, u.D, wD, kStay);
   uint32_t out = kNone;
@@ -773,7 +855,7 @@ template <class P, class V, class Grp, class Tab>
 __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev &sd, int64_t v,
                                    const uint32_t *comm, const SliceTable &sig, uint32_t fresh_base,
                                    typename P::Score *red, LmCounters pc, int64_t *sredW = nullptr,
-                                   uint32_t *sredL = nullptr) {
+                                   uint32_t *sredL = nullptr, const CandSplit &cs = CandSplit()) {
   const int r = grp.rank(), gsz = grp.size();
   for (int i = r; i < tab.size(); i += gsz) {
     tab.K[i] = 0;
@@ -783,11 +865,22 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   grp.sync();
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
-  for (int64_t e = row.lo + r; e < row.hi; e += gsz) {
-    int64_t w;
-    const int64_t x = g.nbr(row, e, w);
-    if (w == 0) continue;
-    tab.add(comm[x], w);
+  // kGather entries per lane at a time: their column and label loads go out together
+  constexpr int kGather = 4;
+  for (int64_t e0 = row.lo + r; e0 < row.hi; e0 += (int64_t)kGather * gsz) {
+    int64_t w[kGather];
+    uint32_t lab[kGather];
+#pragma unroll
+    for (int t = 0; t < kGather; t++) {
+      const int64_t e = e0 + (int64_t)t * gsz;
+      w[t] = 0;
+      int64_t x = 0;
+      if (e < row.hi) x = g.nbr(row, e, w[t]);
+      lab[t] = w[t] != 0 ? g.lab_at(comm, e, x) : kNone;
+    }
+#pragma unroll
+    for (int t = 0; t < kGather; t++)
+      if (lab[t] != kNone) tab.add(lab[t], w[t]);
   }
   grp.sync();
   UnitCtx u = unit_ctx(g, sd, v, D);
@@ -798,17 +891,18 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   group_heaviest(grp, tab, D, (const uint8_t *)nullptr, hW, hL, sredW, sredL);
   if constexpr (!V::kLevel0 && IsMulti<P>::value) {
     if (u.m >= kCoopMinM)
-      return lm_unit_coop<P>(grp, tab, g, sd, u, sig, fresh_base, red, pc, best, hW, hL);
+      return lm_unit_coop<P>(grp, tab, g, sd, u, sig, fresh_base, red, pc, best, hW, hL, cs);
   }
   int ncand = 0;
   if (hL != kNone) {
     typename P::Score s = P::make(g, u, sd, sig, hL, hW, kTarget);
     if (better<P>(g, u, sd, sig, s, best)) best = s;
-    ncand = r == 0;
+    ncand = r == 0 && cs.part == 0;
   }
-  const int nc = tab.count();
+  const Tab ctab = split_view(grp, tab, cs);
+  const int nc = ctab.count();
   for (int i = r; i < nc; i += gsz) {
-    const int h = tab.slot(i);
+    const int h = ctab.slot(i);
     uint32_t key = tab.K[h];
     if (key == 0 || key - 1 == D || key - 1 == hL) continue;
     if (P::prunable(u, tab.V[h], best)) continue;
@@ -818,12 +912,16 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   }
   if (pc.c) {
     if (ncand) atomicAdd(pc.c + 2, (unsigned long long)ncand);
-    if (r == 0) {
+    if (r == 0 && cs.part == 0) {
       atomicAdd(pc.c + 0, 1ull);
       atomicAdd(pc.c + 1, (unsigned long long)(row.hi - row.lo));
     }
   }
   best = group_best<P>(grp, g, u, sd, sig, best, red);
+  if (cs.B > 1 && !split_reduce<P>(grp, g, u, sd, sig, cs, best)) {
+    grp.sync();
+    return kNone;
+  }
   int64_t wD = tab.get(D);
   typename P::Score stay = P::make(g, u, sd, sig, D, wD, kStay);
   uint32_t out = kNone;
@@ -906,7 +1004,7 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
   int64_t w = 0;
   if (e < row.hi) {
     const int64_t x = g.nbr(row, e, w);
-    if (w != 0) c = comm[x];
+    if (w != 0) c = g.lab_at(comm, e, x);
   }
   int64_t wsum = 0, wD = 0;
   bool leader = c != kNone;
@@ -945,6 +1043,194 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
     if (P::cmp(g, u, sd, sig, best, stay) > 0)
       out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(v) : best.lab;
     target[idx] = out;
+  }
+}
+
+// One slice's Sigma sub-table, resolved once per unit (the probes of the unit's own community
+// and of its candidates all go to it).
+struct SubTab {
+  const uint64_t *sub;
+  int sh;
+  __device__ void open(const SliceTable &t, int s) {
+    sh = t.shift[s];
+    sub = t.slots + t.base[s];
+  }
+  // first probe: its slot and entry (issued for several units before any is resolved)
+  __device__ uint64_t first(uint32_t label, uint32_t &h) const {
+    h = fib_hash(label, sh);
+    return sub[h];
+  }
+  // the value of `label` from its first probe, continuing the linear probe when needed
+  __device__ int64_t resolve(uint32_t label, uint32_t h, uint64_t e) const {
+    const uint32_t key = label + 1, mask = 0xffffffffu >> sh;
+    for (;;) {
+      const uint32_t k = (uint32_t)e;
+      if (k == key) return (int32_t)(e >> 32);
+      if (k == 0) return 0;
+      h = (h + 1) & mask;
+      e = sub[h];
+    }
+  }
+};
+
+// Level 0 in colour-batch order, units of degree <= G, Policy0.  Each group of G lanes decides
+// U units in lockstep, so the dependent loads of U units (row bounds, entries, neighbour
+// labels, Sigma probes) are in flight together; a batch segment is a range of positions, so a
+// unit's position is computed, not loaded.  Entry weights travel as 32-bit raw values
+// (coupling entries flagged in bit 31) and are scaled once per candidate:
+// W = b * (raw intra weight) + a * (coupling entries).  Every decision equals
+// lm_group_block's with Policy0: the same candidates, values and order.
+template <int G, int U, bool kOne>
+__device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t first,
+                                    int64_t count, const uint32_t *comm, const SliceTable &sig,
+                                    uint32_t *target, uint32_t fresh_base, LmCounters pc,
+                                    int64_t blk) {
+  constexpr int kGroups = 256 / G;
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G - 1);
+  const int gbase = lane & ~(G - 1);
+  const int64_t base = blk * (int64_t)(kGroups * U) + threadIdx.x / G;
+  if (base >= count) return;   // whole groups leave together
+  int64_t pos[U];
+  bool live[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int64_t i = base + (int64_t)u * kGroups;
+    live[u] = i < count;
+    pos[u] = first + (live[u] ? i : 0);
+  }
+  // unit headers
+  uint32_t D[U];
+  int64_t lo[U], hi[U];
+  int32_t kv[U], gs[U], js[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int64_t v = pos[u];
+    D[u] = comm[v];
+    lo[u] = g.rp[v];
+    hi[u] = live[u] ? g.rp[v + 1] : lo[u];
+    kv[u] = g.k[v];
+    gs[u] = g.slice[v];
+    js[u] = kOne ? 0 : g.solve_of(v);   // one solve: its constants are uniform
+  }
+  // entries and each unit's Sigma sub-table
+  // entries: column (coupling flag), weight and the neighbour's label from the label copy
+  // (always built when this kernel runs), all read in entry order
+  int32_t cr[U], deg[U];
+  uint32_t val[U], c[U];
+  SubTab tb[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int64_t e = lo[u] + gl;
+    const bool has = e < hi[u];
+    deg[u] = (int32_t)(hi[u] - lo[u]);
+    cr[u] = has ? g.col[e] : 0x7fffffff;
+    c[u] = has ? g.elab[e] : kNone;
+    const uint32_t w = (has && g.w) ? (uint32_t)g.w[e] : 1u;
+    tb[u].open(sig, gs[u]);
+    val[u] = !has ? 0u : (cr[u] < 0 ? 0x80000000u : w);
+  }
+  // a coupling entry of zero weight is no entry; the own community's first probe
+  uint32_t hD[U];
+  uint64_t eD[U];
+  int64_t a[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    a[u] = sd.a[js[u]];
+    const bool ent = val[u] != 0u && (cr[u] >= 0 || a[u] != 0);
+    if (!ent) c[u] = kNone;
+    if (gl == 0 && kv[u] > 0) eD[u] = tb[u].first(D[u], hD[u]);
+  }
+  // equal labels merged inside the group: raw intra weight and coupling entries per label
+  uint32_t wr[U], wrD[U];
+  int nc[U], ncD[U];
+  bool lead[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    wr[u] = 0;
+    wrD[u] = 0;
+    nc[u] = 0;
+    ncD[u] = 0;
+    lead[u] = c[u] != kNone;
+  }
+  // not unrolled: the shuffles of an unrolled loop would hold registers the lockstep units
+  // need (two units per group stay within 64 registers, eight waves per SIMD)
+#pragma unroll 1
+  for (int jj = 0; jj < G; jj++) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t cj = (uint32_t)__shfl((int)c[u], gbase + jj, 64);
+      const uint32_t vj = (uint32_t)__shfl((int)val[u], gbase + jj, 64);
+      const uint32_t rw = vj & 0x7fffffffu;
+      const int cp = (int)(vj >> 31);
+      if (cj == c[u]) {
+        wr[u] += rw;
+        nc[u] += cp;
+        if (jj < gl) lead[u] = false;
+      }
+      if (cj == D[u]) {
+        wrD[u] += rw;
+        ncD[u] += cp;
+      }
+    }
+  }
+  // candidates' first probes, all units together
+  bool cand[U];
+  uint32_t hc[U];
+  uint64_t ec[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    cand[u] = lead[u] && c[u] != D[u];
+    if (cand[u] && kv[u] > 0) ec[u] = tb[u].first(c[u], hc[u]);
+  }
+  // values, the group's best, the decision
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int j = js[u];
+    const int64_t p = sd.p[j], q = sd.q[j], pb = sd.pb[j], b = sd.b[j];
+    const int64_t k0 = kv[u];
+    const int64_t S0 = k0 > 0 ? sd.S[gs[u]] : 1;
+    Score0 best;
+    best.g = 0;
+    best.lab = kNone;
+    if (cand[u]) {
+      const int64_t W = b * (int64_t)wr[u] + a[u] * nc[u];
+      Score0 s;
+      s.lab = c[u];
+      s.g = k0 > 0 ? q * S0 * W - pb * (k0 * tb[u].resolve(c[u], hc[u], ec[u])) : q * W;
+      if (s.g > best.g || (s.g == best.g && s.lab < best.lab)) best = s;
+    }
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) {
+      Score0 o;
+      o.g = shfl_xor64(best.g, m);
+      o.lab = (uint32_t)__shfl_xor((int)best.lab, m, 64);
+      if (o.g > best.g || (o.g == best.g && o.lab < best.lab)) best = o;
+    }
+    if (pc.c) {
+      const unsigned long long nk =
+          __popcll(__ballot(cand[u] && live[u]) &
+                   (((G == 64) ? ~0ull : ((1ull << G) - 1)) << gbase));
+      if (gl == 0 && live[u]) {
+        atomicAdd(pc.c + 0, 1ull);
+        atomicAdd(pc.c + 1, (unsigned long long)deg[u]);
+        if (nk) atomicAdd(pc.c + 2, nk);
+      }
+    }
+    if (gl == 0 && live[u]) {
+      const int64_t wD = b * (int64_t)wrD[u] + a[u] * ncD[u];
+      int64_t stay;
+      if (k0 > 0) {
+        const int64_t yD = tb[u].resolve(D[u], hD[u], eD[u]);
+        stay = q * S0 * wD - pb * (k0 * (yD - k0));
+      } else {
+        stay = q * wD;
+      }
+      uint32_t out = kNone;
+      if (best.g > stay) out = best.lab == kNone ? fresh_base + (uint32_t)g.uid[pos[u]] : best.lab;
+      target[pos[u] - first] = out;
+    }
+    (void)p;
   }
 }
 
@@ -1002,6 +1288,9 @@ struct BinSeg {
   int64_t count;
   int64_t blk0;     // first block of the segment
   int64_t nbk;      // blocks with work (k_lm_multi: the segment spans nbk rounded up to kXcds)
+  int64_t first;    // level 0 in position order: position of the segment's first unit
+  int32_t parts;    // latency mode: blocks per unit (candidates split, CandSplit)
+  int64_t poff;     // latency mode: the segment's first split-unit slot
 };
 struct MultiSeg {
   BinSeg s[6];
@@ -1067,12 +1356,75 @@ __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
   }
 }
 
+// Bins 0..3 alone (lane groups, one adjacency entry per lane): no LDS, so a large batch runs at
+// the occupancy the group code's registers allow, where the fused kernel's LDS tables would
+// hold it lower.  Same XCD-aware block order as k_lm_multi.
+template <class P, class V>
+__global__ __launch_bounds__(256) void k_lm_groups(V g, SolveDev sd, MultiSeg ms,
+                                                   const uint32_t *comm, SliceTable sig,
+                                                   uint32_t fresh_base, LmCounters pc) {
+  const int64_t b = blockIdx.x;
+  int k = 0;
+  while (k < 3 && b >= ms.s[k + 1].blk0) k++;
+  const BinSeg sg = ms.s[k];
+  const int64_t p = b - sg.blk0;
+  const int64_t per = (sg.nbk + kXcds - 1) / kXcds;
+  const int64_t lb = (p % kXcds) * per + p / kXcds;
+  if (lb >= sg.nbk) return;
+  switch (k) {
+    case 0:
+      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 1:
+      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 2:
+      lm_group_block<P, V, 16>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
+                               lb);
+      break;
+    default:
+      lm_group_block<P, V, 32>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
+                               lb);
+  }
+}
+
+// Bins 0..3 of a level-0 colour batch in position order (lm0_lockstep), XCD-aware block order
+// as in k_lm_multi; segment k starts at position ms.s[k].first.  kOne: a single solve.
+template <int U, bool kOne>
+__global__ __launch_bounds__(256) void k_lm0_groups(ViewP g, SolveDev sd, MultiSeg ms,
+                                                    const uint32_t *comm, SliceTable sig,
+                                                    uint32_t fresh_base, LmCounters pc) {
+  const int64_t b = blockIdx.x;
+  int k = 0;
+  while (k < 3 && b >= ms.s[k + 1].blk0) k++;
+  const BinSeg sg = ms.s[k];
+  const int64_t p = b - sg.blk0;
+  const int64_t per = (sg.nbk + kXcds - 1) / kXcds;
+  const int64_t lb = (p % kXcds) * per + p / kXcds;
+  if (lb >= sg.nbk) return;
+  switch (k) {
+    case 0:
+      lm0_lockstep<4, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 1:
+      lm0_lockstep<8, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    case 2:
+      lm0_lockstep<16, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      break;
+    default:
+      lm0_lockstep<32, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+  }
+}
+
 // Latency mode (aggregated levels, colour batches of few units): every bin below the hub bin
 // of both unit classes in one launch.  Occupancy does not matter here, so one kernel carries
 // both policies and an LDS table large enough for degree 4096; its blocks have 512 threads,
 // which leaves the multi-slice policy the registers it needs without spilling.
 struct LatSegs {
   BinSeg s[2 * kBinGtab];   // class (single-slice, multi-slice) x bins 0..kBinGtab-1
+  ScoreK *part;             // [split-unit slots x parts] published bests
+  uint32_t *done;           // [split-unit slots] finished blocks, 0 between launches
 };
 
 template <class P, class V>
@@ -1080,7 +1432,7 @@ __device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg,
                                int64_t lb, const uint32_t *comm, const SliceTable &sig,
                                uint32_t fresh_base, LmCounters pc, uint32_t *sk, int64_t *sv,
                                uint16_t *sl, int *sn, typename P::Score *red, int64_t *hw,
-                               uint32_t *hl) {
+                               uint32_t *hl, CandSplit cs, ScoreK *ls_part, uint32_t *ls_done) {
   switch (bin) {
     case 0:
       lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
@@ -1096,12 +1448,19 @@ __device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg,
       lm_group_block<P, V, 32>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
                                lb);
       break;
-    default: {   // one unit per block; table sized by the bin's degree bound
+    default: {   // one unit per block, or sg.parts blocks per unit; table sized by the bin
       const int lg = bin <= 5 ? kSmallBlockLg : kBlockLg;
       LdsTab tab{sk, sv, lg, sl, sn};
-      uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, sg.units[lb], comm, sig, fresh_base, red,
-                              pc, hw, hl);
-      if (threadIdx.x == 0) sg.target[lb] = t;
+      const int64_t unit = lb / sg.parts;
+      if (sg.parts > 1) {
+        cs.part = (int)(lb % sg.parts);
+        cs.B = sg.parts;
+        cs.parts = ls_part + (sg.poff + unit) * sg.parts;
+        cs.done = ls_done + sg.poff + unit;
+      }
+      uint32_t t = lm_unit<P>(BlockGrp(), tab, g, sd, sg.units[unit], comm, sig, fresh_base, red,
+                              pc, hw, hl, cs);
+      if (threadIdx.x == 0 && (sg.parts == 1 || *cs.last)) sg.target[unit] = t;
     }
   }
 }
@@ -1124,18 +1483,24 @@ __global__ __launch_bounds__(kLatThreads) void k_lm_lat(V g, SolveDev sd, LatSeg
   __shared__ Score1 red1[kLatThreads / 64];
   __shared__ int64_t hw[kLatThreads / 64];
   __shared__ uint32_t hl[kLatThreads / 64];
+  __shared__ uint16_t sl2[kBlockMaxDeg];
+  __shared__ int sn2, slast;
   const int64_t b = blockIdx.x;
   int k = 0;
   while (k < 2 * kBinGtab - 1 && b >= ls.s[k + 1].blk0) k++;
   const BinSeg sg = ls.s[k];
   const int64_t lb = b - sg.blk0;
   const int bin = k % kBinGtab;
+  CandSplit cs;
+  cs.L2 = sl2;
+  cs.n2 = &sn2;
+  cs.last = &slast;
   if (k < kBinGtab)
     lat_bin<PolicyK1>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, red1, hw,
-                      hl);
+                      hl, cs, ls.part, ls.done);
   else
-    lat_bin<PK>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, redK, hw,
-                     hl);
+    lat_bin<PK>(g, sd, sg, bin, lb, comm, sig, fresh_base, pc, sk, sv, sl, &sn, redK, hw, hl, cs,
+                ls.part, ls.done);
 }
 
 // Units of very high degree: a global-memory table per unit, slot offsets from a scan.
@@ -1205,7 +1570,7 @@ __global__ __launch_bounds__(256) void k_hub_accum(V g, SolveDev sd, const int32
     int64_t w;
     const int64_t x = g.nbr(row, e, w);
     if (w == 0) continue;
-    const uint32_t lab = comm[x], key = lab + 1;
+    const uint32_t lab = g.lab_at(comm, e, x), key = lab + 1;
     uint32_t h = fib_hash(lab, 32 - kHubLdsLg);
     bool done = false;
     // at most kHubLdsKeys slots are ever claimed, so an empty slot is always reached
@@ -1366,6 +1731,10 @@ __global__ __launch_bounds__(256) void k_lm_apply(V g, const int32_t *units, int
         tab_add(sig, gs, C, (int32_t)k);
       }
       comm[v] = C;
+      if constexpr (std::is_same<V, ViewP>::value) {
+        if (g.elab)   // the entries pointing at v see its new label
+          for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) g.elab[g.prev[e]] = C;
+      }
       mv = true;
     }
     if (j != s_j) s_mixed = 1;
@@ -1402,6 +1771,10 @@ __global__ __launch_bounds__(256) void k_lm_apply_wave(V g, const int32_t *units
     g.pent(v, jj, gs, k);
     tab_add(sig, gs, D, -(int32_t)k);
     tab_add(sig, gs, C, (int32_t)k);
+  }
+  if constexpr (std::is_same<V, ViewP>::value) {
+    if (g.elab)
+      for (int64_t e = g.rp[v] + lane; e < g.rp[v + 1]; e += 64) g.elab[g.prev[e]] = C;
   }
   if (lane == 0) {
     comm[v] = C;
@@ -1475,22 +1848,35 @@ __global__ void k_pos_meta(View0 g, const int32_t *units, int64_t n, int64_t *de
 }
 
 // entries of one position: neighbour positions with the coupling flag, raw weights
+// PosRows: the optional neighbour-label copy (labels of the level's start) and reverse entries
+struct PosLabels {
+  const uint32_t *comm;   // labels by unit id
+  const int64_t *prp;     // row starts by position
+  uint32_t *elab;         // nullptr: not built
+  int32_t *prev;
+};
+
 __device__ inline void pos_row(const View0 &g, const SolveDev &sd, int64_t v, int64_t out,
                                const int32_t *pos, int32_t *pcol, int32_t *pw, int first,
-                               int step) {
+                               int step, const PosLabels &pl) {
   const typename View0::Row r = g.row(v, sd);
   for (int64_t e = r.lo + first; e < r.hi; e += step) {
     const int32_t x = g.col[e];
     const bool coupling = !(x >= r.slo && x < r.shi);
-    pcol[out + (e - r.lo)] = pos[x] | (coupling ? (int32_t)0x80000000 : 0);
+    const int32_t px = pos[x];
+    pcol[out + (e - r.lo)] = px | (coupling ? (int32_t)0x80000000 : 0);
     if (pw) pw[out + (e - r.lo)] = g.w[e];
+    if (pl.elab) {
+      pl.elab[out + (e - r.lo)] = pl.comm[x];
+      pl.prev[out + (e - r.lo)] = (int32_t)(pl.prp[px] + g.rev[e]);
+    }
   }
 }
 
 // rows of at most 32 entries one thread each; longer rows are listed for a wave each
 __global__ void k_pos_rows(View0 g, SolveDev sd, const int32_t *units, int64_t n,
                            const int64_t *prp, const int32_t *pos, int32_t *pcol, int32_t *pw,
-                           int32_t *wide, uint32_t *nwide) {
+                           int32_t *wide, uint32_t *nwide, PosLabels pl) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t v = units[i];
@@ -1498,18 +1884,18 @@ __global__ void k_pos_rows(View0 g, SolveDev sd, const int32_t *units, int64_t n
     wide[atomicAdd(nwide, 1u)] = (int32_t)i;
     return;
   }
-  pos_row(g, sd, v, prp[i], pos, pcol, pw, 0, 1);
+  pos_row(g, sd, v, prp[i], pos, pcol, pw, 0, 1, pl);
 }
 
 __global__ void k_pos_rows_wide(View0 g, SolveDev sd, const int32_t *units, const int64_t *prp,
                                 const int32_t *pos, int32_t *pcol, int32_t *pw,
-                                const int32_t *wide, const uint32_t *nwide) {
+                                const int32_t *wide, const uint32_t *nwide, PosLabels pl) {
   const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < *nwide;
        k += nw) {
     const int64_t i = wide[k];
-    pos_row(g, sd, units[i], prp[i], pos, pcol, pw, lane, 64);
+    pos_row(g, sd, units[i], prp[i], pos, pcol, pw, lane, 64, pl);
   }
 }
 
