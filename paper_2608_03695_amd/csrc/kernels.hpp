@@ -115,6 +115,7 @@ struct ViewP {
   // decisions read labels in entry order instead of gathering them; nullptr: gather
   uint32_t *elab;
   const int32_t *prev;     // per entry (i, x): index of the entry (x, i)
+  int64_t nnz;             // entries (host use)
   struct Row {
     int64_t lo, hi, a, b;
   };
@@ -1080,7 +1081,7 @@ struct SubTab {
 // (coupling entries flagged in bit 31) and are scaled once per candidate:
 // W = b * (raw intra weight) + a * (coupling entries).  Every decision equals
 // lm_group_block's with Policy0: the same candidates, values and order.
-template <int G, int U, bool kOne>
+template <int G, int U, bool kOne, bool kCopy>
 __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t first,
                                     int64_t count, const uint32_t *comm, const SliceTable &sig,
                                     uint32_t *target, uint32_t fresh_base, LmCounters pc,
@@ -1114,8 +1115,8 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
     js[u] = kOne ? 0 : g.solve_of(v);   // one solve: its constants are uniform
   }
   // entries and each unit's Sigma sub-table
-  // entries: column (coupling flag), weight and the neighbour's label from the label copy
-  // (always built when this kernel runs), all read in entry order
+  // entries: column (coupling flag), weight and, with kCopy, the neighbour's label from the
+  // label copy, all read in entry order
   int32_t cr[U], deg[U];
   uint32_t val[U], c[U];
   SubTab tb[U];
@@ -1125,7 +1126,7 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
     const bool has = e < hi[u];
     deg[u] = (int32_t)(hi[u] - lo[u]);
     cr[u] = has ? g.col[e] : 0x7fffffff;
-    c[u] = has ? g.elab[e] : kNone;
+    c[u] = (kCopy && has) ? g.elab[e] : kNone;
     const uint32_t w = (has && g.w) ? (uint32_t)g.w[e] : 1u;
     tb[u].open(sig, gs[u]);
     val[u] = !has ? 0u : (cr[u] < 0 ? 0x80000000u : w);
@@ -1139,6 +1140,7 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
     a[u] = sd.a[js[u]];
     const bool ent = val[u] != 0u && (cr[u] >= 0 || a[u] != 0);
     if (!ent) c[u] = kNone;
+    else if (!kCopy) c[u] = comm[cr[u] & 0x7fffffff];   // gathered
     if (gl == 0 && kv[u] > 0) eD[u] = tb[u].first(D[u], hD[u]);
   }
   // equal labels merged inside the group: raw intra weight and coupling entries per label
@@ -1389,8 +1391,9 @@ __global__ __launch_bounds__(256) void k_lm_groups(V g, SolveDev sd, MultiSeg ms
 }
 
 // Bins 0..3 of a level-0 colour batch in position order (lm0_lockstep), XCD-aware block order
-// as in k_lm_multi; segment k starts at position ms.s[k].first.  kOne: a single solve.
-template <int U, bool kOne>
+// as in k_lm_multi; segment k starts at position ms.s[k].first.  kOne: a single solve; kCopy:
+// neighbour labels from the label copy.
+template <int U, bool kOne, bool kCopy>
 __global__ __launch_bounds__(256) void k_lm0_groups(ViewP g, SolveDev sd, MultiSeg ms,
                                                     const uint32_t *comm, SliceTable sig,
                                                     uint32_t fresh_base, LmCounters pc) {
@@ -1404,16 +1407,16 @@ __global__ __launch_bounds__(256) void k_lm0_groups(ViewP g, SolveDev sd, MultiS
   if (lb >= sg.nbk) return;
   switch (k) {
     case 0:
-      lm0_lockstep<4, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<4, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
       break;
     case 1:
-      lm0_lockstep<8, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<8, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
       break;
     case 2:
-      lm0_lockstep<16, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<16, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
       break;
     default:
-      lm0_lockstep<32, U, kOne>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<32, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
   }
 }
 
@@ -1603,6 +1606,8 @@ __global__ __launch_bounds__(256) void k_hub_accum(V g, SolveDev sd, const int32
   }
 }
 
+constexpr int kHubWin = 2048;   // table slots compacted at a time by a hub evaluation block
+
 template <class P, class V>
 __global__ __launch_bounds__(256) void k_hub_eval(V g, SolveDev sd, const int32_t *units,
                                                   const uint32_t *comm, SliceTable sig,
@@ -1624,27 +1629,44 @@ __global__ __launch_bounds__(256) void k_hub_eval(V g, SolveDev sd, const int32_
   if constexpr (!V::kLevel0 && IsMulti<P>::value) coop = u.m >= kCoopMinM;
   if (coop) {
     if constexpr (!V::kLevel0 && IsMulti<P>::value) {
+      // the block's span of the table is mostly empty slots: each window of kHubWin slots is
+      // first compacted into an LDS list of its candidates, and only those take coop turns
+      __shared__ int32_t wl[kHubWin];
+      __shared__ int wn;
       const CoopLane c = coop_lane(g, u, sd, sig, threadIdx.x);
       const int sub = threadIdx.x / c.mp, nsub = blockDim.x / c.mp;
-      for (int64_t i0 = s0; i0 < s1; i0 += (int64_t)nsub * kCoopBatch) {
-        uint32_t lab[kCoopBatch];
-        int64_t W[kCoopBatch], y[kCoopBatch];
-        bool ok[kCoopBatch];
-        for (int k = 0; k < kCoopBatch; k++) {
-          const int64_t i = i0 + (int64_t)k * nsub + sub;
-          const uint32_t key = i < s1 ? K[i] : 0u;
-          lab[k] = key - 1;
-          ok[k] = key != 0 && key - 1 != D;
-          W[k] = ok[k] ? Wt[i] : 0;
-          ok[k] = ok[k] && !P::prunable(u, W[k], best);
+      for (int64_t w0 = s0; w0 < s1; w0 += kHubWin) {
+        const int64_t w1 = w0 + kHubWin < s1 ? w0 + kHubWin : s1;
+        if (threadIdx.x == 0) wn = 0;
+        __syncthreads();
+        for (int64_t i = w0 + threadIdx.x; i < w1; i += blockDim.x) {
+          const uint32_t key = K[i];
+          if (key != 0 && key - 1 != D) wl[atomicAdd(&wn, 1)] = (int32_t)(i - w0);
         }
-        coop_lookup<kCoopBatch>(c, lab, ok, y);
-        for (int k = 0; k < kCoopBatch; k++) {
-          if (!ok[k]) continue;
-          ncand += c.j == 0;
-          ScoreK sc = coop_score(u, c, lab[k], W[k], y[k], kTarget);
-          if (better<P>(g, u, sd, sig, sc, best)) best = sc;
+        __syncthreads();
+        const int nw = wn;
+        for (int i0 = 0; i0 < nw; i0 += nsub * kCoopBatch) {
+          uint32_t lab[kCoopBatch];
+          int64_t W[kCoopBatch], y[kCoopBatch];
+          bool ok[kCoopBatch];
+          for (int k = 0; k < kCoopBatch; k++) {
+            const int ii = i0 + k * nsub + sub;
+            const int64_t i = ii < nw ? w0 + wl[ii] : -1;
+            const uint32_t key = i >= 0 ? K[i] : 0u;
+            lab[k] = key - 1;
+            ok[k] = key != 0;
+            W[k] = ok[k] ? Wt[i] : 0;
+            ok[k] = ok[k] && !P::prunable(u, W[k], best);
+          }
+          coop_lookup<kCoopBatch>(c, lab, ok, y);
+          for (int k = 0; k < kCoopBatch; k++) {
+            if (!ok[k]) continue;
+            ncand += c.j == 0;
+            ScoreK sc = coop_score(u, c, lab[k], W[k], y[k], kTarget);
+            if (better<P>(g, u, sd, sig, sc, best)) best = sc;
+          }
         }
+        __syncthreads();   // the list is rewritten by the next window
       }
     }
   } else {
@@ -1914,6 +1936,13 @@ __global__ void k_pos_labels_back(const int32_t *units, int64_t n, const uint32_
                                   uint32_t *comm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) comm[units[i]] = pcomm[i];
+}
+
+// the label copy made current again after sweeps that did not keep it (entry order)
+__global__ void k_pos_elab_refresh(const int32_t *pcol, int64_t nnz, const uint32_t *pcomm,
+                                   uint32_t *elab) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) elab[e] = pcomm[pcol[e] & 0x7fffffff];
 }
 
 // A refinement round taken again exactly for the solves that raised their redo flag only:
