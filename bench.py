@@ -474,8 +474,10 @@ def main():
                    "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
         # the HBM-bound loop: level-0 local-moving decisions (every sweep of every iteration)
         "roofline": roofline(nbytes("lm0"), rp["lm0_kernel_ms"], rp["lm0_launches"],
-                             "level-0 decision launches: k_lm_multi<Policy0, ViewP> (bins up "
-                             "to 1024 entries), k_lm_block<Policy0, ViewP, 1024> (to 4096) and the hub kernels"),
+                             "level-0 decision launches: k_lm0_groups (units of at most 32 "
+                             "entries, large colour batches), k_lm_multi<Policy0, ViewP> (to 1024 "
+                             "entries; all bins of small batches), k_lm_block<Policy0, ViewP, 1024> "
+                             "(to 4096) and the hub kernels"),
         # the work of the aggregated levels' decisions (not timed: their launches are short)
         "bytes_all_levels": nbytes("lm"),
         "ms_per_step_median": statistics.median(step_ms),
