@@ -33,6 +33,9 @@ struct SolveDev {
   const int64_t *S;                    // per global slice: 2m_s, or 1 for an empty slice
   int64_t *fallbacks;                  // exact-comparison counter per solve
   uint32_t *redo;                      // per solve: a sweep met a near-tie it could not settle
+  // during local-moving sweeps: solves that take no part in the sweep (stopped, or not being
+  // taken again); their units are not decided (their moves would not be applied); else nullptr
+  const uint8_t *frozen;
 };
 
 // ------------------------------------------------------------------ level views
@@ -858,6 +861,10 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
                                    typename P::Score *red, LmCounters pc, int64_t *sredW = nullptr,
                                    uint32_t *sredL = nullptr, const CandSplit &cs = CandSplit()) {
   const int r = grp.rank(), gsz = grp.size();
+  if (sd.frozen && sd.frozen[g.solve_of(v)]) {   // its solve is out of this sweep
+    if (cs.B > 1 && r == 0) *cs.last = 0;
+    return kNone;
+  }
   for (int i = r; i < tab.size(); i += gsz) {
     tab.K[i] = 0;
     tab.V[i] = 0;
@@ -993,6 +1000,7 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
   const int64_t idx = (blk * blockDim.x + threadIdx.x) / G;
   if (idx >= count) return;   // whole groups leave together; shuffles stay inside a group
   const int64_t v = units[idx];
+  if (sd.frozen && sd.frozen[g.solve_of(v)]) return;   // its solve is out of this sweep
   const uint32_t D = comm[v];
   typename V::Row row = g.row(v, sd);
   UnitCtx u = unit_ctx(g, sd, v, D);
@@ -1113,6 +1121,10 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
     kv[u] = g.k[v];
     gs[u] = g.slice[v];
     js[u] = kOne ? 0 : g.solve_of(v);   // one solve: its constants are uniform
+    if (sd.frozen && sd.frozen[js[u]]) {   // a solve out of this sweep: nothing to decide
+      live[u] = false;
+      hi[u] = lo[u];
+    }
   }
   // entries and each unit's Sigma sub-table
   // entries: column (coupling flag), weight and, with kCopy, the neighbour's label from the
