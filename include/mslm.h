@@ -148,6 +148,44 @@ mslm_status mslm_q_exact_global(const int64_t *q_components, int32_t n_slices, i
                                 int64_t omega_den, char *num, size_t num_cap, char *den,
                                 size_t den_cap);
 
+/* Execution choices that change the speed of a solve and never its result (the same
+ * memberships, Q components and statistics for every value).  Each graph handle holds one;
+ * mslm_batch_leiden uses the one of the graph its first solve names, the server the defaults.
+ *   graphs             1: the sweeps of an aggregated level are replayed from a captured HIP graph
+ *                      after the second sweep (default 0: plain launches)
+ *   latency_units      aggregated levels: colour batches of at most this many units take the
+ *                      one-launch latency path (64..65536, default 1024)
+ *   split_group_units  level 0: a colour batch with at least this many lane-group units gives
+ *                      them a launch of their own (0..2^30, default 16384)
+ *   copy_moves         level 0: the per-entry neighbour-label copy is kept through sweeps that
+ *                      moved at most (units / copy_moves) units (1..2^30, default 1024)
+ *   lat_parts_max      latency path: most blocks sharing one unit's candidates (1..16, default 16)
+ *   batch_units        mslm_batch_leiden: most supra-nodes per union, in units of 2^20 (1..100,
+ *                      default 24)
+ * Errors: EINVAL for a value out of range or a NULL pointer. */
+typedef struct {
+  int32_t graphs;
+  int32_t latency_units;
+  int32_t split_group_units;
+  int32_t copy_moves;
+  int32_t lat_parts_max;
+  int32_t batch_units;
+  int32_t reserved[2];
+} mslm_tuning;
+
+mslm_status mslm_get_tuning(const mslm_graph *g, mslm_tuning *out);
+mslm_status mslm_set_tuning(mslm_graph *g, const mslm_tuning *t);
+
+/* Autotuner: times full solves of (g, params) under candidate tunings, one setting changed at a
+ * time from the best so far (graphs, latency_units, split_group_units, copy_moves,
+ * lat_parts_max; `rounds` passes over them, 1..4), keeps a change only when it is at least 2%
+ * faster, checks that every candidate's membership and Q components equal those of the
+ * starting tuning (MSLM_EHIP with the error text if one ever differs, which would be a library
+ * bug), installs the best tuning on the handle and writes it to `out`.  ms_start / ms_best
+ * (may be NULL) receive the solve times of the starting and the chosen tuning. */
+mslm_status mslm_autotune(mslm_graph *g, const mslm_params *params, int32_t rounds,
+                          mslm_tuning *out, double *ms_start, double *ms_best);
+
 /* Device bytes a graph and one solve on it need (admission estimate). */
 size_t mslm_footprint_bytes(const mslm_graph_desc *desc);
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -131,6 +132,101 @@ mslm_status mslm_q_exact_global(const int64_t *qc, int32_t T, int32_t N, int64_t
   return MSLM_OK;
 }
 
+mslm_status mslm_get_tuning(const mslm_graph *g, mslm_tuning *out) {
+  if (!g || !out) return fail(MSLM_EINVAL, "graph or tuning is NULL");
+  api_tuning_to(g->tune, out);
+  api_clear_error();
+  return MSLM_OK;
+}
+
+mslm_status mslm_set_tuning(mslm_graph *g, const mslm_tuning *t) {
+  if (!g) return fail(MSLM_EINVAL, "graph is NULL");
+  Tuning tu;
+  mslm_status s = api_tuning_from(t, tu);
+  if (s != MSLM_OK) return s;
+  g->tune = tu;
+  api_clear_error();
+  return MSLM_OK;
+}
+
+// One timed solve of the autotuner under tuning `tu`: its wall time (ms; the call returns once
+// its outputs are on the host) and outputs.
+static mslm_status tune_trial(mslm_graph *g, const SolveSpec &sp, const Tuning &tu, double &ms,
+                              SolveOut &out) {
+  std::vector<SolveOut> outs(1);
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    run_solves({&g->g}, {sp}, outs, g->st, g->ws, false, false, false, tu);
+    ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  } catch (const Error &e) {
+    return fail(e.status, e.what());
+  } catch (const std::exception &e) {
+    return fail(MSLM_ENOMEM, e.what());
+  }
+  out = std::move(outs[0]);
+  return MSLM_OK;
+}
+
+mslm_status mslm_autotune(mslm_graph *g, const mslm_params *params, int32_t rounds,
+                          mslm_tuning *out, double *ms_start, double *ms_best) {
+  if (!g || !out) return fail(MSLM_EINVAL, "graph or tuning is NULL");
+  if (rounds < 1 || rounds > 4) return fail(MSLM_EINVAL, "rounds must be in 1..4");
+  SolveSpec sp;
+  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, sp);
+  if (s != MSLM_OK) return s;
+  Tuning best = g->tune;
+  SolveOut ref;
+  double t_ref = 0, t_best = 0;
+  if ((s = tune_trial(g, sp, best, t_ref, ref)) != MSLM_OK) return s;   // warm-up, reference
+  if ((s = tune_trial(g, sp, best, t_best, ref)) != MSLM_OK) return s;
+  const double t_start = t_best;
+  auto same = [&](const SolveOut &o) {
+    return o.membership == ref.membership &&
+           std::memcmp(o.res.q_components, ref.res.q_components,
+                       sizeof(int64_t) * (3 * g->g.T + 1)) == 0;
+  };
+  for (int r = 0; r < rounds; r++) {
+    for (int knob = 0; knob < 5; knob++) {
+      static const int64_t kCand[5][3] = {{0, 1, -1},
+                                          {256, 1024, 4096},
+                                          {4096, 16384, 65536},
+                                          {64, 1024, 16384},
+                                          {1, 4, 16}};
+      for (int ci = 0; ci < 3 && kCand[knob][ci] >= 0; ci++) {
+        Tuning tr = best;
+        const int64_t v = kCand[knob][ci];
+        int64_t *field[5] = {nullptr, &tr.latency_units, &tr.split_group_units, &tr.copy_moves,
+                             nullptr};
+        if (knob == 0) {
+          if (tr.graphs == v) continue;
+          tr.graphs = (int)v;
+        } else if (knob == 4) {
+          if (tr.lat_parts_max == v) continue;
+          tr.lat_parts_max = (int)v;
+        } else {
+          if (*field[knob] == v) continue;
+          *field[knob] = v;
+        }
+        double ms = 0;
+        SolveOut o;
+        if ((s = tune_trial(g, sp, tr, ms, o)) != MSLM_OK) return s;
+        if (!same(o))
+          return fail(MSLM_EHIP, "autotune: a tuning changed a solve's result (library bug)");
+        if (ms < 0.98 * t_best) {
+          best = tr;
+          t_best = ms;
+        }
+      }
+    }
+  }
+  g->tune = best;
+  api_tuning_to(best, out);
+  if (ms_start) *ms_start = t_start;
+  if (ms_best) *ms_best = t_best;
+  api_clear_error();
+  return MSLM_OK;
+}
+
 size_t mslm_footprint_bytes(const mslm_graph_desc *d) { return footprint_estimate(d); }
 
 static mslm_status finish_result(const GraphDev &g, const SolveSpec &sp, SolveOut &o,
@@ -150,7 +246,7 @@ mslm_status mslm_leiden(mslm_graph *g, const mslm_params *params, int32_t *membe
   if (params->flags & MSLM_OUTPUT_ON_DEVICE) outs[0].dev_membership = membership;
   try {
     run_solves({&g->g}, {sp}, outs, g->st, g->ws, (params->flags & MSLM_PROFILE) != 0,
-               (params->flags & MSLM_COUNT) != 0);
+               (params->flags & MSLM_COUNT) != 0, false, g->tune);
   } catch (const Error &e) {
     return fail(e.status, e.what());
   } catch (const std::exception &e) {
@@ -178,10 +274,12 @@ mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs, const
     gs[i] = &graphs[gi]->g;
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // the tuning of the graph the first solve names
+  const Tuning tune = n_solves > 0 ? graphs[solves[0].graph]->tune : Tuning();
   Workspace *ws = workspace_new();
   try {
     // chunks bounded in units and entries (32-bit labels, device memory)
-    const int64_t kUnits = 24ll << 20, kEntries = 400ll << 20;
+    const int64_t kUnits = tune.batch_units, kEntries = 400ll << 20;
     int i = 0;
     while (i < n_solves) {
       int j = i;
@@ -194,7 +292,7 @@ mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs, const
       std::vector<const GraphDev *> cg(gs.begin() + i, gs.begin() + j);
       std::vector<SolveSpec> cs(specs.begin() + i, specs.begin() + j);
       std::vector<SolveOut> outs(j - i);
-      run_solves(cg, cs, outs, st, ws, false);
+      run_solves(cg, cs, outs, st, ws, false, false, false, tune);
       for (int k = i; k < j; k++) {
         SolveOut &o = outs[k - i];
         memcpy(solves[k].membership, o.membership.data(), sizeof(int32_t) * gs[k]->n);

@@ -113,6 +113,13 @@ struct Workspace {
   Buf ref_snap_a, ref_snap_p;             // active flags and proposal stamps before a round
   Buf ref_keep;                           // active flags of solves that skip a round's redo
   Buf lat_part, lat_done;                 // latency mode: candidates split among blocks
+  // sweeps replayed from HIP graphs: a private stream (default priority) joined to the solve
+  // stream by events, the fresh-label base on the device, and a switch that turns graphs off
+  // after a failed capture
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev0 = nullptr, gev1 = nullptr;
+  bool graphs_off = false;
+  Buf fresh;
   // level 0 in colour-batch order (local-moving sweeps)
   Buf p_pos, p_deg, p_rp, p_col, p_w, p_k, p_slice, p_solve, p_iota, p_comm, p_goff, p_glg,
       p_wide, p_nwide, p_sk, p_sk2, p_units, p_elab, p_prev;
@@ -124,6 +131,9 @@ Workspace *workspace_new() { return new Workspace(); }
 void workspace_free(Workspace *ws) {
   if (!ws) return;
   for (auto e : ws->evpool) (void)hipEventDestroy(e);
+  if (ws->gev0) (void)hipEventDestroy(ws->gev0);
+  if (ws->gev1) (void)hipEventDestroy(ws->gev1);
+  if (ws->gstream) (void)hipStreamDestroy(ws->gstream);
   delete ws;
 }
 

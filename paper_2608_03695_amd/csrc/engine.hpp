@@ -156,6 +156,6 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
 // no_events: record no HIP events (the allocation-free entry point; phase times stay 0).
 void run_solves(const std::vector<const GraphDev *> &graphs, const std::vector<SolveSpec> &specs,
                 std::vector<SolveOut> &outs, hipStream_t st, Workspace *ws, bool profile,
-                bool count = false, bool no_events = false);
+                bool count = false, bool no_events = false, const Tuning &tune = Tuning());
 
 }  // namespace mslm

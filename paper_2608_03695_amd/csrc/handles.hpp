@@ -11,6 +11,7 @@ struct mslm_graph {
   hipStream_t st = nullptr;
   int device = 0;                     // the device current when the graph was created
   mslm::Workspace *ws = nullptr;
+  mslm::Tuning tune;                  // result-invariant execution choices (mslm_set_tuning)
   ~mslm_graph() { mslm::workspace_free(ws); }
 };
 

@@ -420,6 +420,38 @@ mslm_status api_q_exact_global(const int64_t *c, int T, int N, int64_t gp, int64
   return MSLM_OK;
 }
 
+mslm_status api_tuning_from(const mslm_tuning *t, Tuning &out) {
+  if (!t) return fail(MSLM_EINVAL, "tuning is NULL");
+  if (t->graphs != 0 && t->graphs != 1) return fail(MSLM_EINVAL, "tuning.graphs must be 0 or 1");
+  if (t->latency_units < 64 || t->latency_units > 65536)
+    return fail(MSLM_EINVAL, "tuning.latency_units must be in 64..65536");
+  if (t->split_group_units < 0 || t->split_group_units > (1 << 30))
+    return fail(MSLM_EINVAL, "tuning.split_group_units must be in 0..2^30");
+  if (t->copy_moves < 1 || t->copy_moves > (1 << 30))
+    return fail(MSLM_EINVAL, "tuning.copy_moves must be in 1..2^30");
+  if (t->lat_parts_max < 1 || t->lat_parts_max > 16)
+    return fail(MSLM_EINVAL, "tuning.lat_parts_max must be in 1..16");
+  if (t->batch_units < 1 || t->batch_units > 100)
+    return fail(MSLM_EINVAL, "tuning.batch_units must be in 1..100");
+  out.graphs = t->graphs;
+  out.latency_units = t->latency_units;
+  out.split_group_units = t->split_group_units;
+  out.copy_moves = t->copy_moves;
+  out.lat_parts_max = t->lat_parts_max;
+  out.batch_units = (int64_t)t->batch_units << 20;
+  return MSLM_OK;
+}
+
+void api_tuning_to(const Tuning &t, mslm_tuning *out) {
+  std::memset(out, 0, sizeof(*out));
+  out->graphs = t.graphs;
+  out->latency_units = (int32_t)t.latency_units;
+  out->split_group_units = (int32_t)t.split_group_units;
+  out->copy_moves = (int32_t)t.copy_moves;
+  out->lat_parts_max = t.lat_parts_max;
+  out->batch_units = (int32_t)(t.batch_units >> 20);
+}
+
 mslm_status api_check_fraction(int64_t num, int64_t den, const char *what) {
   return check_fraction(num, den, what);
 }

@@ -31,6 +31,16 @@ mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp);
 // Q of Eq. 6 from its 3T+1 components as a reduced decimal fraction and the nearest double.
 mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
                         int64_t ob, std::string &num, std::string &den, double &qd);
+// Result-invariant execution choices (mslm_tuning)
+struct Tuning {
+  int graphs = 0;
+  int64_t latency_units = 1024, split_group_units = 16384, copy_moves = 1024;
+  int lat_parts_max = 16;
+  int64_t batch_units = 24ll << 20;
+};
+mslm_status api_tuning_from(const mslm_tuning *t, Tuning &out);
+void api_tuning_to(const Tuning &t, mslm_tuning *out);
+
 // Q_G of the global null model from its components (the same layout, SS' in slot T).
 mslm_status api_q_exact_global(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
                                int64_t ob, std::string &num, std::string &den, double &qd);

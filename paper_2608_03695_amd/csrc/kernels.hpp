@@ -36,7 +36,14 @@ struct SolveDev {
   // during local-moving sweeps: solves that take no part in the sweep (stopped, or not being
   // taken again); their units are not decided (their moves would not be applied); else nullptr
   const uint8_t *frozen;
+  // a sweep replayed from a HIP graph reads the base of its fresh labels here (its launches
+  // were captured once); nullptr: the base passed to the kernel
+  const uint32_t *fresh;
 };
+
+__device__ inline uint32_t fresh_of(const SolveDev &sd, uint32_t fresh_base) {
+  return sd.fresh ? *sd.fresh : fresh_base;
+}
 
 // ------------------------------------------------------------------ level views
 // Level 0: the supra-CSR of Eq. 3 with raw intra weights; an entry whose column lies
@@ -850,7 +857,7 @@ __device__ inline uint32_t lm_unit_coop(Grp grp, Tab tab, const V &g, const Solv
   const ScoreK stay = coop_make(u, c, u.D, wD, kStay);
   uint32_t out = kNone;
   if (P::cmp(g, u, sd, sig, best, stay) > 0)
-    out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(u.v) : best.lab;
+    out = best.lab == kNone ? fresh_of(sd, fresh_base) + (uint32_t)g.orig(u.v) : best.lab;
   grp.sync();
   return out;
 }
@@ -934,7 +941,7 @@ __device__ inline uint32_t lm_unit(Grp grp, Tab tab, const V &g, const SolveDev 
   typename P::Score stay = P::make(g, u, sd, sig, D, wD, kStay);
   uint32_t out = kNone;
   if (P::cmp(g, u, sd, sig, best, stay) > 0)
-    out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(v) : best.lab;
+    out = best.lab == kNone ? fresh_of(sd, fresh_base) + (uint32_t)g.orig(v) : best.lab;
   grp.sync();
   return out;
 }
@@ -1050,7 +1057,7 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
     else stay = P::make(g, u, sd, sig, D, wD, kStay);
     uint32_t out = kNone;
     if (P::cmp(g, u, sd, sig, best, stay) > 0)
-      out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(v) : best.lab;
+      out = best.lab == kNone ? fresh_of(sd, fresh_base) + (uint32_t)g.orig(v) : best.lab;
     target[idx] = out;
   }
 }
@@ -1241,7 +1248,8 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
         stay = q * wD;
       }
       uint32_t out = kNone;
-      if (best.g > stay) out = best.lab == kNone ? fresh_base + (uint32_t)g.uid[pos[u]] : best.lab;
+      if (best.g > stay)
+        out = best.lab == kNone ? fresh_of(sd, fresh_base) + (uint32_t)g.uid[pos[u]] : best.lab;
       target[pos[u] - first] = out;
     }
     (void)p;
@@ -1728,7 +1736,7 @@ __global__ __launch_bounds__(64) void k_hub_final(V g, SolveDev sd, const int32_
   if (lane == 0) {
     uint32_t out = kNone;
     if (P::cmp(g, u, sd, sig, best, stay) > 0)
-      out = best.lab == kNone ? fresh_base + (uint32_t)g.orig(v) : best.lab;
+      out = best.lab == kNone ? fresh_of(sd, fresh_base) + (uint32_t)g.orig(v) : best.lab;
     target[idx] = out;
   }
 }

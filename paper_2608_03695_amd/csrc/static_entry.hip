@@ -80,7 +80,7 @@ extern "C" mslm_status mslm_leiden_static(mslm_graph *g, const mslm_params *para
   std::string msg;
   try {
     run_solves({&g->g}, {sp}, outs, g->st, ws, false, (params->flags & MSLM_COUNT) != 0,
-               /*no_events=*/true);
+               /*no_events=*/true, g->tune);
   } catch (const Error &e) {
     rc = e.status;
     msg = e.what();

@@ -24,7 +24,7 @@ MSLM_NULL_MULTISLICE, MSLM_NULL_GLOBAL = 0, 1
 EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_q_exact_global",
             "mslm_footprint_bytes",
             "mslm_graph_info", "mslm_last_error", "mslm_set_allocator", "mslm_leiden_static",
-            "mslm_batch_leiden",
+            "mslm_batch_leiden", "mslm_get_tuning", "mslm_set_tuning", "mslm_autotune",
             "mslm_server_create", "mslm_server_submit", "mslm_server_wait",
             "mslm_server_memory", "mslm_server_destroy"]
 
@@ -53,6 +53,19 @@ class Params(C.Structure):
                 ("max_levels", C.c_int32), ("max_iterations", C.c_int32),
                 ("max_sweeps", C.c_int32), ("null_model", C.c_int32),
                 ("seed", C.c_uint64), ("flags", C.c_uint32), ("reserved1", C.c_uint32)]
+
+
+class Tuning(C.Structure):
+    """mslm_tuning: execution choices that never change a result."""
+    _fields_ = [("graphs", C.c_int32), ("latency_units", C.c_int32),
+                ("split_group_units", C.c_int32), ("copy_moves", C.c_int32),
+                ("lat_parts_max", C.c_int32), ("batch_units", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+    KEYS = ["graphs", "latency_units", "split_group_units", "copy_moves", "lat_parts_max",
+            "batch_units"]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k in self.KEYS}
 
 
 class Result(C.Structure):
@@ -115,6 +128,13 @@ def load():
     lib.mslm_q_exact.restype = C.c_int
     lib.mslm_q_exact_global.argtypes = lib.mslm_q_exact.argtypes
     lib.mslm_q_exact_global.restype = C.c_int
+    lib.mslm_get_tuning.argtypes = [P, C.POINTER(Tuning)]
+    lib.mslm_get_tuning.restype = C.c_int
+    lib.mslm_set_tuning.argtypes = [P, C.POINTER(Tuning)]
+    lib.mslm_set_tuning.restype = C.c_int
+    lib.mslm_autotune.argtypes = [P, C.POINTER(Params), C.c_int32, C.POINTER(Tuning),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.mslm_autotune.restype = C.c_int
     lib.mslm_footprint_bytes.argtypes = [C.POINTER(GraphDesc)]
     lib.mslm_footprint_bytes.restype = C.c_size_t
     lib.mslm_graph_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -205,6 +225,31 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+    def tuning(self):
+        t = Tuning()
+        _check(load().mslm_get_tuning(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Change execution choices (mslm_tuning fields by name); results never change."""
+        t = Tuning()
+        _check(load().mslm_get_tuning(self._h, C.byref(t)))
+        for k, v in kw.items():
+            if k not in Tuning.KEYS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(load().mslm_set_tuning(self._h, C.byref(t)))
+
+    def autotune(self, gamma=Fraction(1), omega=None, rounds=1, max_levels=32,
+                 max_iterations=2, seed=0, null_model=MSLM_NULL_MULTISLICE):
+        """mslm_autotune: returns (chosen tuning dict, ms with the starting tuning, ms tuned)."""
+        p = params(gamma, omega, max_levels, max_iterations, 0, seed, 0, null_model)
+        t = Tuning()
+        a, b = C.c_double(), C.c_double()
+        _check(load().mslm_autotune(self._h, C.byref(p), int(rounds), C.byref(t), C.byref(a),
+                                    C.byref(b)))
+        return t.as_dict(), a.value, b.value
 
     def info(self):
         n, m, t = C.c_int64(), C.c_int64(), C.c_int64()
