@@ -205,6 +205,15 @@ def bench_batched(args):
         raise SystemExit("no GPU visible")
     handles = [mslm.Graph(tg, 1) for tg in tgs]
     m_supra = sum(h.info()["nnz"] // 2 for h in handles)
+    tuning = None
+    if args.autotune:
+        # tune on the batch's largest graph; a batch runs with the tuning of its first solve's graph
+        big = max(range(ng), key=lambda i: handles[i].info()["nnz"])
+        tu, ms0, ms1 = handles[big].autotune(1, 1, rounds=1)
+        for h in handles:   # batched and plain calls alike
+            h.set_tuning(**tu)
+        tuning = {"chosen": tu, "tuned_on_graph": big, "ms_default": ms0, "ms_tuned": ms1}
+        log(f"autotune on graph {big}: {tu} ({ms0:.1f} -> {ms1:.1f} ms)")
     solves = [(g, sp.gamma, sp.omega, sp.max_levels, sp.max_iterations, sp.seed)
               for g, sp in gen.batch_solves(ng)]
     log(f"{len(solves)} solves over {ng} graphs ({m_supra} supra-edges); warm-up")
@@ -246,6 +255,7 @@ def bench_batched(args):
         "plain_s": t_plain, "plain_solves_per_s": len(picked) / t_plain,
         "speedup_vs_plain": (len(solves) / t_batch) / (len(picked) / t_plain),
         "identical_results": f"{same}/{len(picked)} sampled solves",
+        "tuning": tuning,
     }
 
 
@@ -380,6 +390,9 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="cfg5: server worker slots")
     ap.add_argument("--plain-sample", type=int, default=8,
                     help="cfg4: time plain calls on every k-th solve of the grid")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner (one round) before the warm-up; the "
+                         "timed steps use the tuning it picks (results are the same)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (counter calibration)")
     ap.add_argument("--graph-cache", default=None,
@@ -421,6 +434,12 @@ def main():
     m_supra = info["nnz"] // 2
     kw = dict(gamma=spec.gamma, max_levels=spec.max_levels, max_iterations=spec.max_iterations,
               seed=spec.seed)
+    tuning = None
+    if args.autotune:
+        # result-invariant execution choices picked by timing solves (not part of a step)
+        tu, ms0, ms1 = g.autotune(rounds=1, **kw)
+        tuning = {"chosen": tu, "ms_default": ms0, "ms_tuned": ms1}
+        log(f"autotune: {tu} ({ms0:.1f} -> {ms1:.1f} ms)")
     for i in range(args.warmup):
         g.leiden(**kw)
         log(f"warmup {i} done")
@@ -461,6 +480,7 @@ def main():
                 + rc[pre + "_candidates"] * BYTES_CAND)
     q = mslm.q_exact(results[-1]["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
     out = {
+        "tuning": tuning,
         "metric": METRIC,
         "value": m_supra / (ms_step * 1e-3),
         "unit": "supra-edges/s",
