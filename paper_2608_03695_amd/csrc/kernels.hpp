@@ -1090,17 +1090,20 @@ struct SubTab {
 };
 
 // Level 0 in colour-batch order, units of degree <= G, Policy0.  Each group of G lanes decides
-// U units in lockstep, so the dependent loads of U units (row bounds, entries, neighbour
-// labels, Sigma probes) are in flight together; a batch segment is a range of positions, so a
-// unit's position is computed, not loaded.  Entry weights travel as 32-bit raw values
+// U units in lockstep (their dependent loads in flight together; one unit measured fastest, at
+// 8 waves per SIMD); a batch segment is a range of positions, so a unit's position is computed,
+// not loaded.  Equal neighbour labels are merged in a small LDS table per group (a claim, an
+// add, a read) rather than by G rounds of shuffles.  Entry weights travel as 32-bit raw values
 // (coupling entries flagged in bit 31) and are scaled once per candidate:
 // W = b * (raw intra weight) + a * (coupling entries).  Every decision equals
-// lm_group_block's with Policy0: the same candidates, values and order.
+// lm_group_block's with Policy0: the same candidates and values (the best under the same total
+// order).
 template <int G, int U, bool kOne, bool kCopy>
 __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t first,
                                     int64_t count, const uint32_t *comm, const SliceTable &sig,
                                     uint32_t *target, uint32_t fresh_base, LmCounters pc,
-                                    int64_t blk) {
+                                    int64_t blk, uint32_t *lm0_keys,
+                                    unsigned long long *lm0_vals) {
   constexpr int kGroups = 256 / G;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
@@ -1162,36 +1165,72 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
     else if (!kCopy) c[u] = comm[cr[u] & 0x7fffffff];   // gathered
     if (gl == 0 && kv[u] > 0) eD[u] = tb[u].first(D[u], hD[u]);
   }
-  // equal labels merged inside the group: raw intra weight and coupling entries per label
+  // equal labels merged inside the group in a small LDS table per (group, unit): each entry
+  // adds its raw weight (low half) and coupling count (high half) to its label's slot; the
+  // lane that claims a slot leads that label.  Three LDS steps instead of G shuffle rounds.
+  constexpr int kSlots = 2 * G;   // load at most one half
+  uint32_t *sk = lm0_keys + (threadIdx.x >> 6) * (U * 128) + (gbase / G) * kSlots;
+  unsigned long long *sv = lm0_vals + (threadIdx.x >> 6) * (U * 128) + (gbase / G) * kSlots;
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    sk[u * 128 + gl] = 0u;
+    sk[u * 128 + gl + G] = 0u;
+    sv[u * 128 + gl] = 0ull;
+    sv[u * 128 + gl + G] = 0ull;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the clears land before the claims
+  bool lead[U];
+  int slot[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    lead[u] = false;
+    slot[u] = -1;
+    if (c[u] != kNone) {
+      const uint32_t key = c[u] + 1;
+      uint32_t h = (c[u] * 2654435769u) >> (32 - __builtin_ctz(kSlots));
+      for (;;) {
+        const uint32_t prev = atomicCAS(sk + u * 128 + h, 0u, key);
+        if (prev == 0u || prev == key) {
+          lead[u] = prev == 0u;
+          break;
+        }
+        h = (h + 1) & (kSlots - 1);
+      }
+      slot[u] = (int)h;
+      const unsigned long long add =
+          (val[u] >> 31) ? (1ull << 32) : (unsigned long long)(val[u] & 0x7fffffffu);
+      atomicAdd(sv + u * 128 + h, add);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);
   uint32_t wr[U], wrD[U];
   int nc[U], ncD[U];
-  bool lead[U];
 #pragma unroll
   for (int u = 0; u < U; u++) {
     wr[u] = 0;
-    wrD[u] = 0;
     nc[u] = 0;
+    wrD[u] = 0;
     ncD[u] = 0;
-    lead[u] = c[u] != kNone;
-  }
-  // not unrolled: the shuffles of an unrolled loop would hold registers the lockstep units
-  // need (two units per group stay within 64 registers, eight waves per SIMD)
-#pragma unroll 1
-  for (int jj = 0; jj < G; jj++) {
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const uint32_t cj = (uint32_t)__shfl((int)c[u], gbase + jj, 64);
-      const uint32_t vj = (uint32_t)__shfl((int)val[u], gbase + jj, 64);
-      const uint32_t rw = vj & 0x7fffffffu;
-      const int cp = (int)(vj >> 31);
-      if (cj == c[u]) {
-        wr[u] += rw;
-        nc[u] += cp;
-        if (jj < gl) lead[u] = false;
-      }
-      if (cj == D[u]) {
-        wrD[u] += rw;
-        ncD[u] += cp;
+    if (lead[u]) {
+      const unsigned long long t = sv[u * 128 + slot[u]];
+      wr[u] = (uint32_t)t;
+      nc[u] = (int)(t >> 32);
+    }
+    if (gl == 0) {   // the own community's weight
+      const uint32_t key = D[u] + 1;
+      uint32_t h = (D[u] * 2654435769u) >> (32 - __builtin_ctz(kSlots));
+      for (int probes = 0; probes < kSlots; probes++) {
+        const uint32_t k = sk[u * 128 + h];
+        if (k == key) {
+          const unsigned long long t = sv[u * 128 + h];
+          wrD[u] = (uint32_t)t;
+          ncD[u] = (int)(t >> 32);
+          break;
+        }
+        if (k == 0u) break;
+        h = (h + 1) & (kSlots - 1);
       }
     }
   }
@@ -1417,6 +1456,8 @@ template <int U, bool kOne, bool kCopy>
 __global__ __launch_bounds__(256) void k_lm0_groups(ViewP g, SolveDev sd, MultiSeg ms,
                                                     const uint32_t *comm, SliceTable sig,
                                                     uint32_t fresh_base, LmCounters pc) {
+  __shared__ uint32_t keys[4 * U * 128];
+  __shared__ unsigned long long vals[4 * U * 128];
   const int64_t b = blockIdx.x;
   int k = 0;
   while (k < 3 && b >= ms.s[k + 1].blk0) k++;
@@ -1427,16 +1468,20 @@ __global__ __launch_bounds__(256) void k_lm0_groups(ViewP g, SolveDev sd, MultiS
   if (lb >= sg.nbk) return;
   switch (k) {
     case 0:
-      lm0_lockstep<4, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<4, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target,
+                                        fresh_base, pc, lb, keys, vals);
       break;
     case 1:
-      lm0_lockstep<8, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<8, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target,
+                                        fresh_base, pc, lb, keys, vals);
       break;
     case 2:
-      lm0_lockstep<16, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<16, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target,
+                                        fresh_base, pc, lb, keys, vals);
       break;
     default:
-      lm0_lockstep<32, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm0_lockstep<32, U, kOne, kCopy>(g, sd, sg.first, sg.count, comm, sig, sg.target,
+                                        fresh_base, pc, lb, keys, vals);
   }
 }
 
