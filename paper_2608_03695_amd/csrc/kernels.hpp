@@ -994,13 +994,14 @@ __device__ inline uint32_t batch_slot(const ViewK &g, int64_t v) {
 }
 
 // Units of degree <= G: G lanes per unit, one adjacency entry per lane; the group merges
-// equal community labels with shuffles (the first lane holding a label leads it), every
-// leader evaluates its community, and the group reduces to the best.
+// equal community labels in a 2G-slot LDS table per group (the lane that claims a label's slot
+// leads it), every leader evaluates its community, and the group reduces to the best.  lk/lv:
+// the block's LDS, 128 slots per wave.
 template <class P, class V, int G>
 __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int32_t *units,
                                       int64_t count, const uint32_t *comm, const SliceTable &sig,
                                       uint32_t *target, uint32_t fresh_base, LmCounters pc,
-                                      int64_t blk) {
+                                      int64_t blk, uint32_t *lk, int64_t *lv) {
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);
@@ -1023,15 +1024,49 @@ __device__ inline void lm_group_block(const V &g, const SolveDev &sd, const int3
     if (w != 0) c = g.lab_at(comm, e, x);
   }
   int64_t wsum = 0, wD = 0;
-  bool leader = c != kNone;
-  for (int j = 0; j < G; j++) {
-    uint32_t cj = (uint32_t)__shfl((int)c, gbase + j, 64);
-    int64_t wj = __shfl(w, gbase + j, 64);
-    if (cj == c) {
-      wsum += wj;
-      if (j < gl) leader = false;
+  bool leader = false;
+  {
+    constexpr int kSlots = 2 * G;
+    uint32_t *sk = lk + (threadIdx.x >> 6) * 128 + (gbase / G) * kSlots;
+    unsigned long long *sv =
+        reinterpret_cast<unsigned long long *>(lv) + (threadIdx.x >> 6) * 128 + (gbase / G) * kSlots;
+    sk[gl] = 0u;
+    sk[gl + G] = 0u;
+    sv[gl] = 0ull;
+    sv[gl + G] = 0ull;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the clears land before the claims
+    int h = -1;
+    if (c != kNone) {
+      const uint32_t key = c + 1;
+      uint32_t hh = (c * 2654435769u) >> (32 - __builtin_ctz(kSlots));
+      for (;;) {
+        const uint32_t prev = atomicCAS(sk + hh, 0u, key);
+        if (prev == 0u || prev == key) {
+          leader = prev == 0u;
+          break;
+        }
+        hh = (hh + 1) & (kSlots - 1);
+      }
+      h = (int)hh;
+      atomicAdd(sv + hh, (unsigned long long)w);
     }
-    if (cj == D) wD += wj;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    if (leader) wsum = (int64_t)sv[h];
+    if (gl == 0) {   // the own community's weight
+      const uint32_t key = D + 1;
+      uint32_t hh = (D * 2654435769u) >> (32 - __builtin_ctz(kSlots));
+      for (int probes = 0; probes < kSlots; probes++) {
+        const uint32_t k = sk[hh];
+        if (k == key) {
+          wD = (int64_t)sv[hh];
+          break;
+        }
+        if (k == 0u) break;
+        hh = (hh + 1) & (kSlots - 1);
+      }
+    }
   }
   typename P::Score best = P::make(g, u, sd, sig, kNone, 0, kEmpty);
   const bool cand = leader && c != D;
@@ -1300,7 +1335,10 @@ __global__ __launch_bounds__(256) void k_lm_group(V g, SolveDev sd, const int32_
                                                   int64_t count, const uint32_t *comm,
                                                   SliceTable sig, uint32_t *target,
                                                   uint32_t fresh_base, LmCounters pc) {
-  lm_group_block<P, V, G>(g, sd, units, count, comm, sig, target, fresh_base, pc, blockIdx.x);
+  __shared__ uint32_t lk[4 * 128];
+  __shared__ int64_t lv[4 * 128];
+  lm_group_block<P, V, G>(g, sd, units, count, comm, sig, target, fresh_base, pc, blockIdx.x, lk,
+                          lv);
 }
 
 template <class P, class V>
@@ -1384,18 +1422,20 @@ __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
   if (lb >= sg.nbk) return;
   switch (k) {
     case 0:
-      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb,
+                               sk, sv);
       break;
     case 1:
-      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb,
+                               sk, sv);
       break;
     case 2:
       lm_group_block<P, V, 16>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
-                               lb);
+                               lb, sk, sv);
       break;
     case 3:
       lm_group_block<P, V, 32>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
-                               lb);
+                               lb, sk, sv);
       break;
     case 4: {
       const int wv = threadIdx.x >> 6;
@@ -1424,6 +1464,8 @@ template <class P, class V>
 __global__ __launch_bounds__(256) void k_lm_groups(V g, SolveDev sd, MultiSeg ms,
                                                    const uint32_t *comm, SliceTable sig,
                                                    uint32_t fresh_base, LmCounters pc) {
+  __shared__ uint32_t lk[4 * 128];
+  __shared__ int64_t lv[4 * 128];
   const int64_t b = blockIdx.x;
   int k = 0;
   while (k < 3 && b >= ms.s[k + 1].blk0) k++;
@@ -1434,18 +1476,20 @@ __global__ __launch_bounds__(256) void k_lm_groups(V g, SolveDev sd, MultiSeg ms
   if (lb >= sg.nbk) return;
   switch (k) {
     case 0:
-      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb,
+                               lk, lv);
       break;
     case 1:
-      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb,
+                               lk, lv);
       break;
     case 2:
       lm_group_block<P, V, 16>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
-                               lb);
+                               lb, lk, lv);
       break;
     default:
       lm_group_block<P, V, 32>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
-                               lb);
+                               lb, lk, lv);
   }
 }
 
@@ -1503,18 +1547,20 @@ __device__ inline void lat_bin(const V &g, const SolveDev &sd, const BinSeg &sg,
                                uint32_t *hl, CandSplit cs, ScoreK *ls_part, uint32_t *ls_done) {
   switch (bin) {
     case 0:
-      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm_group_block<P, V, 4>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb,
+                               sk, sv);
       break;
     case 1:
-      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb);
+      lm_group_block<P, V, 8>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc, lb,
+                               sk, sv);
       break;
     case 2:
       lm_group_block<P, V, 16>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
-                               lb);
+                               lb, sk, sv);
       break;
     case 3:
       lm_group_block<P, V, 32>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
-                               lb);
+                               lb, sk, sv);
       break;
     default: {   // one unit per block, or sg.parts blocks per unit; table sized by the bin
       const int lg = bin <= 5 ? kSmallBlockLg : kBlockLg;
