@@ -954,7 +954,7 @@ constexpr int kSmallBlockMaxDeg = 1024;
 constexpr int kBlockMaxDeg = 4096;
 
 // Degree bins of the decision kernels: 0..3 lane groups of 4/8/16/32 lanes per unit (one
-// adjacency entry per lane, equal labels merged with shuffles), 4 a wave with an LDS
+// adjacency entry per lane, equal labels merged in an LDS table), 4 a wave with an LDS
 // table, 5 a block with an LDS table, 6 a block with a global-memory table.
 constexpr int kNumBins = 8;
 constexpr int kBinWaveLast = 4;          // bins 0..4 fit a wave's table
@@ -1441,6 +1441,17 @@ __global__ __launch_bounds__(256) void k_lm_multi(V g, SolveDev sd, MultiSeg ms,
       const int wv = threadIdx.x >> 6;
       const int64_t idx = lb * 4 + wv;
       if (idx >= sg.count) return;
+      // a unit of at most 64 entries in fewer than kCoopMinM slices: the wave as one lane group
+      // (entries one per lane, labels merged in this wave's LDS region)
+      const int64_t v0 = sg.units[idx];
+      if (g.degree(v0) <= 64 && g.plen(v0) < kCoopMinM) {
+        // lm_group_block addresses 128 slots per wave from the pointer it gets: shift it so
+        // that this wave lands on its own 512-slot wave table, which no other wave touches
+        lm_group_block<P, V, 64>(g, sd, sg.units, sg.count, comm, sig, sg.target, fresh_base, pc,
+                                 lb, sk + (wv << kWaveLg) - wv * 128,
+                                 sv + (wv << kWaveLg) - wv * 128);
+        break;
+      }
       LdsTab tab{sk + (wv << kWaveLg), sv + (wv << kWaveLg), kWaveLg, sl + wv * kWaveMaxDeg,
                  sn + wv};
       uint32_t t = lm_unit<P>(WaveGrp(), tab, g, sd, sg.units[idx], comm, sig, fresh_base,
