@@ -77,11 +77,12 @@ def _load():
     lib.orc_nnz.argtypes = [P]
     lib.orc_nnz.restype = C.c_int64
     lib.orc_csr.argtypes = [P, P, P, P, P, P]
-    lib.orc_leiden.argtypes = [P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+    lib.orc_leiden.argtypes = [P, C.c_int64, C.c_int64, P, P, C.c_int32, C.c_int32, C.c_int32,
                                C.c_uint64, C.c_int32, P, P, C.POINTER(Stats)]
     lib.orc_leiden.restype = C.c_int
     lib.orc_q_components.argtypes = [P, P, P]
     lib.orc_q_components_global.argtypes = [P, P, P]
+    lib.orc_q_components_cpm.argtypes = [P, P, P]
     lib.orc_mix64.argtypes = [C.c_uint64]
     lib.orc_mix64.restype = C.c_uint64
     lib.orc_priority.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_uint32]
@@ -160,16 +161,23 @@ class OracleGraph:
         return rp, col, w, raw, twom
 
     def leiden(self, gamma=Fraction(1), max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
-               null_model=0):
+               null_model=0, gamma_slices=None, initial=None):
         """null_model 0: the multislice modularity of Eq. 6 (per-slice null model);
-        1: the global modularity of the supra-graph (Eq. 5 over all supra-nodes)."""
+        1: the global modularity of the supra-graph (Eq. 5 over all supra-nodes); 2: the
+        multislice CPM.  gamma_slices: T per-slice resolutions gamma^(s) (> 0) in place of
+        gamma; initial: the first iteration's start partition (N*T labels in [0, N*T))."""
         lib = _load()
         gamma = Fraction(gamma)
         memb = np.zeros(self.g.n_supra, np.int32)
         comps = np.zeros(3 * self.g.n_slices + 1, np.int64)
         st = Stats()
-        rc = lib.orc_leiden(self._h, gamma.numerator, gamma.denominator, max_levels,
-                            max_iterations, max_sweeps, seed, null_model, _ptr(memb),
+        gs = None
+        if gamma_slices is not None:
+            gs = np.array([[Fraction(x).numerator, Fraction(x).denominator]
+                           for x in gamma_slices], dtype=np.int64).ravel()
+        ini = None if initial is None else np.ascontiguousarray(initial, dtype=np.int32)
+        rc = lib.orc_leiden(self._h, gamma.numerator, gamma.denominator, _ptr(gs), _ptr(ini),
+                            max_levels, max_iterations, max_sweeps, seed, null_model, _ptr(memb),
                             _ptr(comps), C.byref(st))
         if rc != 0:
             raise ValueError(f"oracle leiden failed: {rc}")
@@ -178,22 +186,44 @@ class OracleGraph:
     def q_components(self, membership, null_model=0):
         memb = np.ascontiguousarray(membership, dtype=np.int32)
         comps = np.zeros(3 * self.g.n_slices + 1, np.int64)
-        fn = _load().orc_q_components_global if null_model == 1 else _load().orc_q_components
+        lib = _load()
+        fn = {0: lib.orc_q_components, 1: lib.orc_q_components_global,
+              2: lib.orc_q_components_cpm}[null_model]
         fn(self._h, _ptr(memb), _ptr(comps))
         return comps
 
 
+def _per_slice(gamma, T):
+    if isinstance(gamma, (list, tuple, np.ndarray)):
+        assert len(gamma) == T
+        return [Fraction(x) for x in gamma]
+    return [Fraction(gamma)] * T
+
+
 def q_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
-    """Q = (sum_s [W_s - gamma SS_s / 2m_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1))."""
+    """Q = (sum_s [W_s - gamma^(s) SS_s / 2m_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1));
+    gamma: one resolution or T per-slice resolutions."""
     T = n_slices
-    gamma, omega = Fraction(gamma), Fraction(omega)
+    gam, omega = _per_slice(gamma, T), Fraction(omega)
     W, SS, tm, I = comps[:T], comps[T:2 * T], comps[2 * T:3 * T], comps[3 * T]
     num = Fraction(0)
     for s in range(T):
         num += int(W[s])
         if int(tm[s]):
-            num -= gamma * int(SS[s]) / Fraction(int(tm[s]))
+            num -= gam[s] * int(SS[s]) / Fraction(int(tm[s]))
     num += omega * int(I)
+    den = sum(int(x) for x in tm) + 2 * omega * n_nodes * (T - 1)
+    return num / den if den else Fraction(0)
+
+
+def q_cpm_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
+    """The multislice CPM from its components (SS_s = sum over communities of the squared
+    number of their slice-s supra-nodes): (sum_s [W_s - gamma^(s) SS_s] + omega I) / 2mu, the
+    normalisation 2mu = sum_s 2m_s + 2 omega N (T-1) of Eq. 6."""
+    T = n_slices
+    gam, omega = _per_slice(gamma, T), Fraction(omega)
+    W, SS, tm, I = comps[:T], comps[T:2 * T], comps[2 * T:3 * T], comps[3 * T]
+    num = sum(int(W[s]) - gam[s] * int(SS[s]) for s in range(T)) + omega * int(I)
     den = sum(int(x) for x in tm) + 2 * omega * n_nodes * (T - 1)
     return num / den if den else Fraction(0)
 

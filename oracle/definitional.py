@@ -14,6 +14,10 @@ baseline may use it.  Everything is written straight from the paper's definition
 * Static Newman modularity (Eq. 5, undirected, so d_out = d_in = k) for T = 1.
 * Closed forms for the all-singleton and one-community partitions.
 * Brute-force maximum over all set partitions of the supra-nodes (n <= 10).
+* The variants Eq. 6 admits: a resolution gamma^(s) per slice (every function taking gamma
+  accepts one value or a sequence of T), and the multislice CPM (cpm=True): the null term
+  gamma^(s) k_i^s k_j^s / 2m^s replaced by gamma^(s) n_i n_j with node weight n = 1 per
+  supra-node, under the same normalisation 1/2mu.
 
 Readings where the paper is silent (all listed with the design notes):
 * 2mu is the total weight of the supra-graph of Eq. 3: sum_s 2m_s + 2*omega*N*(T-1).
@@ -83,6 +87,24 @@ def two_mu(g, omega):
     return Fraction(tot) + 2 * Fraction(omega) * g.n_nodes * (g.n_slices - 1)
 
 
+def gammas(gamma, t):
+    """gamma^(s), s = 0..t-1, from one resolution or a sequence of t."""
+    if isinstance(gamma, (list, tuple, np.ndarray)):
+        assert len(gamma) == t
+        return [Fraction(x) for x in gamma]
+    return [Fraction(gamma)] * t
+
+
+def null_term(gam, k, twom, s, i, j, cpm):
+    """The null-model term of the pair (i, j) in slice s: gamma^(s) k_i k_j / 2m_s (zero in a
+    slice without edges), or gamma^(s) * 1 * 1 under the multislice CPM."""
+    if cpm:
+        return gam[s]
+    if not twom[s]:
+        return Fraction(0)
+    return gam[s] * k[s][i] * k[s][j] / Fraction(twom[s])
+
+
 def _over_two_mu(num, g, omega):
     """num / 2mu; an empty supra-graph (2mu = 0) has Q = 0 by convention."""
     tm = two_mu(g, omega)
@@ -91,11 +113,11 @@ def _over_two_mu(num, g, omega):
 
 # --------------------------------------------------------------------------- Eq. 6, three ways
 
-def q_quadruple_sum(g, gamma, omega, membership):
-    """Eq. 6 literally: (1/2mu) sum_{ijsr} [(A_ij^s - gamma k_i^s k_j^s / 2m^s) delta_sr
-    + delta_ij omega^sr] delta(c_i^s, c_j^r)."""
+def q_quadruple_sum(g, gamma, omega, membership, cpm=False):
+    """Eq. 6 literally: (1/2mu) sum_{ijsr} [(A_ij^s - gamma^(s) k_i^s k_j^s / 2m^s) delta_sr
+    + delta_ij omega^sr] delta(c_i^s, c_j^r)  (cpm: gamma^(s) n_i n_j, n = 1)."""
     n, t = g.n_nodes, g.n_slices
-    gamma, omega = Fraction(gamma), Fraction(omega)
+    gam, omega = gammas(gamma, t), Fraction(omega)
     mats = slice_matrices(g)
     k = degrees(mats)
     twom = [sum(ks) for ks in k]
@@ -107,30 +129,28 @@ def q_quadruple_sum(g, gamma, omega, membership):
         term = Fraction(0)
         if s == r:
             term += mats[s][i][j]
-            if twom[s]:
-                term -= gamma * k[s][i] * k[s][j] / Fraction(twom[s])
+            term -= null_term(gam, k, twom, s, i, j, cpm)
         if i == j:
             term += coupling(s, r, omega)
         total += term
     return _over_two_mu(total, g, omega) 
 
 
-def modularity_matrix(g, gamma, omega):
-    """Supra-modularity matrix: per-slice A - gamma k k^T / 2m blocks, omega couplings off-block."""
+def modularity_matrix(g, gamma, omega, cpm=False):
+    """Supra-modularity matrix: per-slice A - gamma^(s) k k^T / 2m blocks (cpm: A - gamma^(s)
+    J), omega couplings off-block."""
     n, t = g.n_nodes, g.n_slices
-    gamma, omega = Fraction(gamma), Fraction(omega)
+    gam, omega = gammas(gamma, t), Fraction(omega)
     mats = slice_matrices(g)
     k = degrees(mats)
+    twom = [sum(ks) for ks in k]
     size = n * t
     M = [[Fraction(0)] * size for _ in range(size)]
     for s in range(t):
-        tm = sum(k[s])
         for i in range(n):
             for j in range(n):
-                v = Fraction(mats[s][i][j])
-                if tm:
-                    v -= gamma * k[s][i] * k[s][j] / Fraction(tm)
-                M[s * n + i][s * n + j] = v
+                M[s * n + i][s * n + j] = Fraction(mats[s][i][j]) - null_term(gam, k, twom, s, i,
+                                                                               j, cpm)
     for s in range(t):
         for r in range(t):
             if s != r:
@@ -139,9 +159,9 @@ def modularity_matrix(g, gamma, omega):
     return M
 
 
-def q_trace_form(g, gamma, omega, membership):
+def q_trace_form(g, gamma, omega, membership, cpm=False):
     """Tr(C^T M C) / 2mu with C the one-hot community assignment matrix."""
-    M = modularity_matrix(g, gamma, omega)
+    M = modularity_matrix(g, gamma, omega, cpm)
     labels = sorted(set(int(x) for x in np.asarray(membership).ravel()))
     col = {lab: a for a, lab in enumerate(labels)}
     size = len(M)
@@ -156,13 +176,14 @@ def q_trace_form(g, gamma, omega, membership):
     return _over_two_mu(tr, g, omega) 
 
 
-def q_component_form(g, gamma, omega, membership):
-    """Per-slice form: (sum_s [W_s - gamma SS_s / 2m_s] + omega I) / 2mu, where W_s is the
+def q_component_form(g, gamma, omega, membership, cpm=False):
+    """Per-slice form: (sum_s [W_s - gamma^(s) SS_s / 2m_s] + omega I) / 2mu, where W_s is the
     intra weight inside communities (both directions), SS_s the sum over communities of
-    the squared slice-s community degree, and I the number of ordered consecutive-slice
-    pairs (i, s), (i, s+-1) that share a community.  Works on edge lists (no dense matrix)."""
+    the squared slice-s community degree (cpm: of the squared slice-s community size, and no
+    2m_s), and I the number of ordered consecutive-slice pairs (i, s), (i, s+-1) that share a
+    community.  Works on edge lists (no dense matrix)."""
     n, t = g.n_nodes, g.n_slices
-    gamma, omega = Fraction(gamma), Fraction(omega)
+    gam, omega = gammas(gamma, t), Fraction(omega)
     c = np.asarray(membership).reshape(t, n)
     num = Fraction(0)
     for s in range(t):
@@ -179,11 +200,13 @@ def q_component_form(g, gamma, omega, membership):
         tm = sum(kdeg)
         sig = {}
         for i in range(n):
-            sig[int(c[s][i])] = sig.get(int(c[s][i]), 0) + kdeg[i]
+            sig[int(c[s][i])] = sig.get(int(c[s][i]), 0) + (1 if cpm else kdeg[i])
         SS = sum(v * v for v in sig.values())
         num += W
-        if tm:
-            num -= gamma * SS / Fraction(tm)
+        if cpm:
+            num -= gam[s] * SS
+        elif tm:
+            num -= gam[s] * SS / Fraction(tm)
     I = 0
     for s in range(t - 1):
         I += 2 * int(np.sum(c[s] == c[s + 1]))
@@ -287,34 +310,42 @@ def brute_force_max_global(g, gamma, omega):
 
 # --------------------------------------------------------------------------- closed forms
 
-def q_all_singletons(g, gamma, omega):
-    """Every supra-node alone: only the diagonal null terms survive."""
+def q_all_singletons(g, gamma, omega, cpm=False):
+    """Every supra-node alone: only the diagonal null terms survive (cpm: -gamma^(s) per
+    supra-node)."""
     mats = slice_matrices(g)
     k = degrees(mats)
+    gam = gammas(gamma, g.n_slices)
     num = Fraction(0)
     for s in range(g.n_slices):
         tm = sum(k[s])
-        if tm:
-            num -= Fraction(gamma) * sum(x * x for x in k[s]) / Fraction(tm)
+        if cpm:
+            num -= gam[s] * g.n_nodes
+        elif tm:
+            num -= gam[s] * sum(x * x for x in k[s]) / Fraction(tm)
     return _over_two_mu(num, g, omega)
 
 
-def q_one_community(g, gamma, omega):
-    """All supra-nodes together: [(1 - gamma) sum_s 2m_s + 2 omega N (T-1)] / 2mu."""
+def q_one_community(g, gamma, omega, cpm=False):
+    """All supra-nodes together: [sum_s (1 - gamma^(s)) 2m_s + 2 omega N (T-1)] / 2mu
+    (cpm: sum_s (2m_s - gamma^(s) N^2) in place of the first sum)."""
     mats = slice_matrices(g)
-    tot = sum(sum(sum(row) for row in a) for a in mats)
-    num = (1 - Fraction(gamma)) * tot + 2 * Fraction(omega) * g.n_nodes * (g.n_slices - 1)
+    gam = gammas(gamma, g.n_slices)
+    num = 2 * Fraction(omega) * g.n_nodes * (g.n_slices - 1)
+    for s, a in enumerate(mats):
+        tm = sum(sum(row) for row in a)
+        num += tm - gam[s] * g.n_nodes ** 2 if cpm else (1 - gam[s]) * tm
     return _over_two_mu(num, g, omega)
 
 
 # --------------------------------------------------------------------------- brute force
 
-def brute_force_max(g, gamma, omega):
+def brute_force_max(g, gamma, omega, cpm=False):
     """Maximum Q over every set partition of the N*T supra-nodes (restricted growth strings).
 
     Returns (Q*, list of optimal memberships).  Sizes up to 10 supra-nodes (Bell(10) = 115975).
     """
-    best, mems = _brute_force(modularity_matrix(g, gamma, omega))
+    best, mems = _brute_force(modularity_matrix(g, gamma, omega, cpm))
     return _over_two_mu(best, g, omega), mems
 
 
@@ -401,11 +432,11 @@ def communities_connected(g, omega, membership):
     return all(k == 1 for k in comps_per_label.values())
 
 
-def improving_single_moves(g, gamma, omega, membership):
+def improving_single_moves(g, gamma, omega, membership, cpm=False):
     """All (supra-node, target) pairs whose move raises Q strictly (targets: communities of
     neighbours, and a fresh empty community).  Evaluated by recomputing Q exactly."""
     c = np.asarray(membership).ravel().copy()
-    base = q_component_form(g, gamma, omega, c)
+    base = q_component_form(g, gamma, omega, c, cpm)
     nbr = [set() for _ in range(g.n_supra)]
     for a, b, _ in supra_edges(g, omega):
         nbr[a].add(b)
@@ -418,7 +449,7 @@ def improving_single_moves(g, gamma, omega, membership):
         for tgt in sorted(targets):
             old = c[v]
             c[v] = tgt
-            if q_component_form(g, gamma, omega, c) > base:
+            if q_component_form(g, gamma, omega, c, cpm) > base:
                 found.append((v, tgt))
             c[v] = old
     return found

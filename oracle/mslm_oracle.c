@@ -21,6 +21,10 @@
  *         profiles, the local-moving partition as the next level's start;
  *       * after the levels: communities split into connected components, labels by first
  *         appearance in supra-node order v = s*N + i.
+ *   - Variants of the objective (Eq. 6 in its full generality, Section 3.2): a resolution
+ *     gamma^(s) per slice; the global null model of Eq. 5 over the supra-graph; the multislice
+ *     CPM (null term gamma^(s) n_i n_j with node weight 1 per supra-node); and a start
+ *     partition for the first iteration (warm start / resume).
  *   - Exact arithmetic: integer weights are scaled by the coupling denominator b (omega = a/b)
  *     so all weights are integers; gains are compared as exact rationals (int128 when a unit
  *     lies in one slice, an own arbitrary-precision integer otherwise).  Nothing is rounded.
@@ -51,8 +55,8 @@ typedef __int128 i128;
 
 /* ------------------------------------------------------------------ small exact integers */
 /* Sign-magnitude integers of up to BN_CAP 32-bit limbs, enough for a product of 64 slice
- * denominators below 2^31 times a 2^93 numerator. */
-#define BN_CAP 104
+ * denominators below 2^62 (a resolution denominator times 2m_s) times a 2^125 numerator. */
+#define BN_CAP 136
 typedef struct { int neg; int len; uint32_t d[BN_CAP]; } bn_t;
 
 static void bn_zero(bn_t *x) { x->neg = 0; x->len = 0; }
@@ -292,14 +296,16 @@ void orc_csr(const orc_graph *g, int64_t *rp, int32_t *col, int64_t *w, int32_t 
 
 /* ------------------------------------------------------------------ exact gains */
 typedef struct {
-  int64_t p, q, b;             /* gamma = p/q, coupling denominator b */
-  const int64_t *S;            /* per-slice denominators: 2m_s, or 1 for an empty slice */
+  const int64_t *gp, *gq;      /* per slice: resolution gamma^(s) = gp[s]/gq[s], reduced */
+  int64_t b;                   /* coupling denominator */
+  const int64_t *S;            /* per-slice denominators: 2m_s, or 1 for an empty slice (and
+                                  1 for every slice of the multislice CPM) */
 } coef_t;
 
-/* Exact value of  q*W*Pi - p*b*sum_j k_j*y_j*(Pi/S_j)  with Pi = prod_j S_j over the unit's
- * profile slices.  For one fixed unit Pi is a common positive factor of every target, so the
- * ordering of these values is the ordering of the b-scaled gains
- *     W - (p b / q) * sum_j k_j y_j / S_j.
+/* Exact value of  W*Pi - b*sum_j gp_j*k_j*y_j*(Pi/(gq_j*S_j))  with Pi = prod_j gq_j*S_j over
+ * the unit's profile slices s_j.  For one fixed unit Pi is a common positive factor of every
+ * target, so the ordering of these values is the ordering of the b-scaled gains
+ *     W - b * sum_j gamma^(s_j) k_j y_j / S_j.
  * Single-slice units use int128; others the bignum path. */
 typedef struct { int big; i128 small; bn_t v; } gval_t;
 
@@ -307,27 +313,29 @@ static void gain_value(const coef_t *cf, int64_t W, int m, const int32_t *ps, co
                        const int64_t *y, gval_t *out) {
   if (m <= 1) {
     out->big = 0;
-    if (m == 0) { out->small = (i128)cf->q * W; return; }
-    int64_t S = cf->S[ps[0]];
-    out->small = (i128)cf->q * W * S - (i128)(cf->p * cf->b) * ((i128)pk[0] * y[0]);
+    if (m == 0) { out->small = W; return; }
+    int s = ps[0];
+    out->small = (i128)cf->gq[s] * cf->S[s] * W - (i128)(cf->gp[s] * cf->b) * ((i128)pk[0] * y[0]);
     return;
   }
-  /* sum_j k_j y_j / S_j as num/den, den = prod S_j */
+  /* sum_j gp_j k_j y_j / (gq_j S_j) as num/den, den = prod gq_j S_j */
   bn_t num, den, t1, t2;
   bn_zero(&num); bn_from_u64(&den, 1);
   for (int j = 0; j < m; j++) {
-    uint64_t S = (uint64_t)cf->S[ps[j]];
+    int s = ps[j];
+    uint64_t D = (uint64_t)cf->gq[s] * (uint64_t)cf->S[s];   /* < 2^62 */
     int64_t ky = pk[j] * y[j];          /* < 2^62 by the slice-size precondition */
-    bn_mul_u64(&num, S);
-    t1 = den; bn_mul_u64(&t1, (uint64_t)(ky < 0 ? -ky : ky)); t1.neg = ky < 0 && t1.len;
+    bn_mul_u64(&num, D);
+    t1 = den; bn_mul_u64(&t1, (uint64_t)(ky < 0 ? -ky : ky)); bn_mul_u64(&t1, (uint64_t)cf->gp[s]);
+    t1.neg = ky < 0 && t1.len;
     bn_add(&num, &num, &t1, 0);
-    bn_mul_u64(&den, S);
+    bn_mul_u64(&den, D);
   }
-  /* q*W*den - p*b*num */
-  t1 = den; bn_mul_u64(&t1, (uint64_t)cf->q);
+  /* W*den - b*num */
+  t1 = den;
   uint64_t aw = (uint64_t)(W < 0 ? -W : W);
   bn_mul_u64(&t1, aw); t1.neg = W < 0 && t1.len;
-  t2 = num; bn_mul_u64(&t2, (uint64_t)(cf->p * cf->b));
+  t2 = num; bn_mul_u64(&t2, (uint64_t)cf->b);
   if (t2.len == 0) t2.neg = 0;
   out->big = 1;
   bn_add(&out->v, &t1, &t2, 1);
@@ -617,8 +625,8 @@ static int32_t local_move(const ctx_t *cx, const level_t *g, const int32_t *colo
 
 /* ------------------------------------------------------------------ refinement */
 /* Well-connectedness of a set X inside its community K (Section 3.2, after Traag et al.):
- *   ext(X) >= (p b / q) * sum_s Sigma_{X,s} (Sigma_{K,s} - Sigma_{X,s}) / S_s,
- * evaluated exactly: q*ext*Pi - p*b*sum_s x_s (K_s - x_s) Pi/S_s >= 0. */
+ *   ext(X) >= b * sum_s gamma^(s) Sigma_{X,s} (Sigma_{K,s} - Sigma_{X,s}) / S_s,
+ * evaluated exactly as the sign of the gain form above with W = ext, k = x_s, y = K_s - x_s. */
 static int well_connected(const coef_t *cf, int64_t ext, int m, const int32_t *sl, const int64_t *xs,
                           const int64_t *ks) {
   int64_t *prod = malloc((m ? m : 1) * sizeof(int64_t));
@@ -858,6 +866,23 @@ int orc_q_components(const orc_graph *G, const int32_t *memb, int64_t *comps) {
  * communities of the squared scaled supra-degree sum (sum_C (sum_{v in C} kappa'_v)^2, with
  * kappa' = b * (intra degree) + a * (coupling count)), comps[T+1..2T-1] = 0, comps[2T..3T-1] =
  * 2m_s, comps[3T] = I. */
+/* Components of the multislice CPM (node weight 1 per supra-node): as orc_q_components with
+ * comps[T..2T-1] = sum over communities of the squared number of their supra-nodes in slice s. */
+int orc_q_components_cpm(const orc_graph *G, const int32_t *memb, int64_t *comps) {
+  int32_t N = G->N, T = G->T;
+  const level_t *g = &G->g0;
+  orc_q_components(G, memb, comps);
+  map_t sig; map_init(&sig, g->n);
+  for (int64_t v = 0; v < g->n; v++) map_add(&sig, (uint32_t)memb[v], (int32_t)(v / N), 1);
+  for (int32_t s = T; s < 2 * T; s++) comps[s] = 0;
+  for (uint64_t h = 0; h < sig.cap; h++) if (sig.key[h] != MAP_EMPTY) {
+    int32_t s = (int32_t)(sig.key[h] & 0xff);
+    comps[T + s] += sig.val[h] * sig.val[h];
+  }
+  map_free(&sig);
+  return ORC_OK;
+}
+
 int orc_q_components_global(const orc_graph *G, const int32_t *memb, int64_t *comps) {
   int32_t T = G->T;
   const level_t *g = &G->g0;
@@ -912,24 +937,54 @@ static level_t global_level(const level_t *g0, int64_t *two_mu) {
   return g;
 }
 
-int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t max_levels,
+/* The multislice CPM (the Constant Potts Model of Traag et al. with the slices coupled as in
+ * Eq. 6): the null term gamma^(s) k_i k_j / 2m_s of Eq. 6 becomes gamma^(s) n_i n_j with node
+ * weight n = 1 per supra-node, so every supra-node's profile is the single entry (its slice, 1)
+ * and every slice's denominator is 1. */
+static level_t cpm_level(const level_t *g0, int32_t N) {
+  level_t g; level_copy(g0, &g);
+  free(g.pp); free(g.ps); free(g.pk);
+  int64_t n = g.n;
+  g.pp = calloc(n + 1, sizeof(int64_t)); g.ps = malloc((n ? n : 1) * sizeof(int32_t));
+  g.pk = malloc((n ? n : 1) * sizeof(int64_t));
+  for (int64_t v = 0; v < n; v++) { g.ps[v] = (int32_t)(v / N); g.pk[v] = 1; g.pp[v + 1] = v + 1; }
+  return g;
+}
+
+/* null_model: 0 Q_MS of Eq. 6, 1 the global modularity of the supra-graph, 2 the multislice
+ * CPM.  gamma_slices (NULL: gamma_num/gamma_den in every slice) holds T pairs (num, den) of
+ * positive per-slice resolutions gamma^(s) (not with the global null model).  initial (NULL:
+ * singletons) is the start partition of the first iteration, labels in [0, N*T), taken in its
+ * canonical form (labels by first appearance). */
+int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den,
+               const int64_t *gamma_slices, const int32_t *initial, int32_t max_levels,
                int32_t max_iterations, int32_t max_sweeps, uint64_t seed, int32_t null_model,
                int32_t *membership, int64_t *comps, orc_stats *st) {
-  if (gamma_num < 0 || gamma_den < 1 || max_levels < 1) return ORC_EINVAL;
-  if (null_model != 0 && null_model != 1) return ORC_EINVAL;
-  if (gamma_num >= ((int64_t)1 << 31) || gamma_den >= ((int64_t)1 << 31)) return ORC_EOVERFLOW;
-  int64_t gg = gamma_num ? gcd64(gamma_num, gamma_den) : gamma_den;
+  if (max_levels < 1) return ORC_EINVAL;
+  if (null_model < 0 || null_model > 2) return ORC_EINVAL;
+  if (gamma_slices && null_model == 1) return ORC_EINVAL;
+  const int64_t n0 = G->g0.n;
+  if (initial)
+    for (int64_t v = 0; v < n0; v++) if (initial[v] < 0 || initial[v] >= n0) return ORC_EINVAL;
   ctx_t cx; cx.G = G;
-  int64_t S[MAX_SLICES];
-  for (int s = 0; s < G->T; s++) S[s] = G->twom[s] > 0 ? G->twom[s] : 1;
-  cx.cf.p = gamma_num / gg; cx.cf.q = gamma_den / gg; cx.cf.b = G->b; cx.cf.S = S;
+  int64_t S[MAX_SLICES], gp[MAX_SLICES], gq[MAX_SLICES];
+  for (int s = 0; s < G->T; s++) {
+    int64_t a = gamma_slices ? gamma_slices[2 * s] : gamma_num;
+    int64_t d = gamma_slices ? gamma_slices[2 * s + 1] : gamma_den;
+    if (a < 0 || d < 1 || (gamma_slices && a == 0)) return ORC_EINVAL;
+    if (a >= ((int64_t)1 << 31) || d >= ((int64_t)1 << 31)) return ORC_EOVERFLOW;
+    int64_t gg = a ? gcd64(a, d) : d;
+    gp[s] = a / gg; gq[s] = d / gg;
+    S[s] = null_model == 2 ? 1 : (G->twom[s] > 0 ? G->twom[s] : 1);
+  }
+  cx.cf.gp = gp; cx.cf.gq = gq; cx.cf.b = G->b; cx.cf.S = S;
   level_t gglob; memset(&gglob, 0, sizeof(gglob));
   const level_t *base = &G->g0;
   if (null_model == 1) {
     int64_t two_mu = 0;
     gglob = global_level(&G->g0, &two_mu);
     /* head-room of the exact values: 2mu' < 2^31 and max(p, q) * 2mu'^2 < 2^62 */
-    int64_t pq = cx.cf.p > cx.cf.q ? cx.cf.p : cx.cf.q;
+    int64_t pq = gp[0] > gq[0] ? gp[0] : gq[0];
     if (two_mu >= ((int64_t)1 << 31) || (i128)pq * two_mu * two_mu >= ((i128)1 << 62)) {
       level_free(&gglob);
       return ORC_EOVERFLOW;
@@ -937,14 +992,23 @@ int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t
     S[0] = two_mu > 0 ? two_mu : 1;
     cx.cf.b = 1;
     base = &gglob;
+  } else if (null_model == 2) {
+    gglob = cpm_level(&G->g0, G->N);
+    base = &gglob;
   }
   if (max_sweeps <= 0) max_sweeps = DEFAULT_SWEEPS;
   int iters = max_iterations > 0 ? max_iterations : MAX_ITER_CAP;
   if (iters > MAX_ITER_CAP) iters = MAX_ITER_CAP;
   memset(st, 0, sizeof(*st));
-  const int64_t n0 = G->g0.n;
-  int32_t *Pcur = malloc(n0 * sizeof(int32_t));
-  for (int64_t v = 0; v < n0; v++) Pcur[v] = (int32_t)v;
+  int32_t *Pcur = malloc((n0 ? n0 : 1) * sizeof(int32_t));
+  if (initial) {
+    uint32_t *c0 = malloc((n0 ? n0 : 1) * sizeof(uint32_t));
+    canon(n0, (const uint32_t *)initial, c0);
+    for (int64_t v = 0; v < n0; v++) Pcur[v] = (int32_t)c0[v];
+    free(c0);
+  } else {
+    for (int64_t v = 0; v < n0; v++) Pcur[v] = (int32_t)v;
+  }
   int64_t *map0 = malloc(n0 * sizeof(int64_t));
   uint32_t *Pflat = malloc(n0 * sizeof(uint32_t));
   int32_t *Pnew = malloc(n0 * sizeof(int32_t));
@@ -1006,16 +1070,19 @@ int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t
   }
   memcpy(membership, Pcur, n0 * sizeof(int32_t));
   if (null_model == 1) orc_q_components_global(G, Pcur, comps);
+  else if (null_model == 2) orc_q_components_cpm(G, Pcur, comps);
   else orc_q_components(G, Pcur, comps);
   free(Pcur); free(map0); free(Pflat); free(Pnew);
-  if (null_model == 1) level_free(&gglob);
+  if (null_model != 0) level_free(&gglob);
   return ORC_OK;
 }
 
 /* Exact comparison helper exposed for tests: sign of  q*W*Pi - p*b*sum_j k_j y_j Pi/S_j. */
 int orc_gain_sign(int64_t p, int64_t q, int64_t b, const int64_t *S, int64_t W, int m,
                   const int32_t *ps, const int64_t *pk, const int64_t *y) {
-  coef_t cf = {p, q, b, S};
+  int64_t gp[MAX_SLICES], gq[MAX_SLICES];
+  for (int s = 0; s < MAX_SLICES; s++) { gp[s] = p; gq[s] = q; }
+  coef_t cf = {gp, gq, b, S};
   gval_t g; gain_value(&cf, W, m, ps, pk, y, &g);
   return gval_sign(&g);
 }

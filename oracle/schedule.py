@@ -13,7 +13,11 @@ runs at scale, written for tiny inputs and for being read against the paper:
 The schedule (Leiden with local moving, refinement and aggregation, Section 3.2, made
 deterministic; the readings are the ones listed in the design notes):
 
-* Iterations start from the canonical form of the previous partition (singletons first); an
+* Objectives: Q_MS of Eq. 6 with a resolution gamma^(s) per slice (one gamma for all slices
+  by default); the global modularity of the supra-graph (Eq. 5); the multislice CPM, whose
+  null term is gamma^(s) n_i n_j with node weight n = 1 per supra-node (no 2m_s).
+* Iterations start from the canonical form of the previous partition (singletons, or the
+  given start partition, first); an
   iteration whose output equals its start is stable and ends the solve; max_iterations <= 0
   means until stable, at most 32.
 * Per level: first-fit colouring of the units in decreasing hash priority; colour-batched
@@ -27,7 +31,7 @@ deterministic; the readings are the ones listed in the design notes):
   Sweeps end at the first sweep without a move or after max_sweeps (32 by default).
 * Refinement (greedy Leiden refinement): sub-communities start as single units; a set X is
   well connected in its community K when the edge weight between X and K minus X is at least
-  gamma * sum_s Sigma_{X,s} (Sigma_{K,s} - Sigma_{X,s}) / 2m_s.  In each round every single
+  sum_s gamma^(s) Sigma_{X,s} (Sigma_{K,s} - Sigma_{X,s}) / 2m_s.  In each round every single
   unit that is well connected and still active proposes the well-connected sub-community of
   its own community, adjacent to it, whose joining raises Q of the refined partition the most
   (strictly positive, ties to the lowest label); an active unit without a proposal drops out
@@ -138,21 +142,37 @@ class GlobalScore:
         return Fraction(self(lab), self.q * self.two_mu ** 2) if self.two_mu else Fraction(0)
 
 
+def per_slice(gamma, T):
+    """gamma^(s) for s = 0..T-1 from one resolution or a sequence of T."""
+    if isinstance(gamma, (list, tuple)):
+        assert len(gamma) == T
+        return [Fraction(x) for x in gamma]
+    return [Fraction(gamma)] * T
+
+
+def null_weight(G, v, cpm):
+    """The weight a supra-node carries into its slice's null term: its intra degree k_{i,s}
+    (Eq. 6), or 1 under the multislice CPM."""
+    return 1 if cpm else G.k[v]
+
+
 class Score:
-    """L * 2mu * Q_MS(partition) as an exact integer, for one (graph, gamma):
-        2mu Q = sum_s [ W_s - gamma SS_s / 2m_s ] + omega I            (Eq. 6)
+    """L * 2mu * Q_MS(partition) as an exact integer, for one (graph, per-slice gamma):
+        2mu Q = sum_s [ W_s - gamma^(s) SS_s / 2m_s ] + omega I        (Eq. 6)
     W_s: intra weight (both directions) inside communities, SS_s: sum over communities of the
-    squared slice-s degree, I: directed coupling entries inside communities.  L clears every
+    squared slice-s degree, I: directed coupling entries inside communities.  Under the
+    multislice CPM SS_s sums squared supra-node counts and there is no 2m_s.  L clears every
     denominator, so comparisons of changes of Q are comparisons of integers."""
 
-    def __init__(self, G: SupraGraph, gamma):
+    def __init__(self, G: SupraGraph, gamma, cpm=False):
         self.G = G
-        self.gamma = Fraction(gamma)
-        q = self.gamma.denominator
-        L = lcm(q, G.omega.denominator, *[q * G.two_m[s] for s in range(G.T) if G.two_m[s] > 0])
+        self.cpm = cpm
+        gam = per_slice(gamma, G.T)
+        coef = [gam[s] if cpm else (gam[s] / G.two_m[s] if G.two_m[s] > 0 else Fraction(0))
+                for s in range(G.T)]
+        L = lcm(G.omega.denominator, *[c.denominator for c in coef])
         self.L = L
-        self.c_null = [(L * self.gamma / G.two_m[s]) if G.two_m[s] > 0 else Fraction(0)
-                       for s in range(G.T)]
+        self.c_null = [L * c for c in coef]
         assert all(c.denominator == 1 for c in self.c_null)
         self.c_null = [int(c) for c in self.c_null]
         c_int = L * G.omega
@@ -170,9 +190,10 @@ class Score:
                 total += self.c_inter
         sig = {}
         for v in range(G.n):
-            if G.k[v]:
+            x = null_weight(G, v, self.cpm)
+            if x:
                 key = (lab[v], G.slice[v])
-                sig[key] = sig.get(key, 0) + G.k[v]
+                sig[key] = sig.get(key, 0) + x
         for (c, s), x in sig.items():
             total -= self.c_null[s] * x * x
         return total
@@ -275,12 +296,13 @@ def local_move(G, score, units, adj, colour, labels, max_sweeps, stats):
 # --------------------------------------------------------------------------- refinement
 
 def well_connected(G, gamma, X, K, null_model=0):
-    """ext(X) >= gamma * sum_s Sigma_{X,s} (Sigma_{K,s} - Sigma_{X,s}) / 2m_s, where ext(X) is
+    """ext(X) >= sum_s gamma^(s) Sigma_{X,s} (Sigma_{K,s} - Sigma_{X,s}) / 2m_s, where ext(X) is
     the weight of the supra-edges between X and K minus X (X, K sets of level-0 supra-nodes);
-    for the global null model ext(X) >= gamma * kappa_X (kappa_K - kappa_X) / 2mu."""
+    for the global null model ext(X) >= gamma * kappa_X (kappa_K - kappa_X) / 2mu; for the
+    multislice CPM the Sigmas count supra-nodes and there is no 2m_s."""
     if null_model == 1:
         return external_weight(G, X, K) >= null_between_global(G, gamma, X, K)
-    return external_weight(G, X, K) >= null_between(G, gamma, X, K)
+    return external_weight(G, X, K) >= null_between(G, gamma, X, K, cpm=null_model == 2)
 
 
 def null_between_global(G, gamma, X, K):
@@ -298,17 +320,20 @@ def external_weight(G, X, K):
     return sum((w for v in X for x, w in G.nbr[v].items() if x in K and x not in X), Fraction(0))
 
 
-def null_between(G, gamma, X, K):
+def null_between(G, gamma, X, K, cpm=False):
+    gam = per_slice(gamma, G.T)
     sx, sk = [0] * G.T, [0] * G.T
     for v in X:
-        sx[G.slice[v]] += G.k[v]
+        sx[G.slice[v]] += null_weight(G, v, cpm)
     for v in K:
-        sk[G.slice[v]] += G.k[v]
+        sk[G.slice[v]] += null_weight(G, v, cpm)
     tot = Fraction(0)
     for s in range(G.T):
-        if G.two_m[s]:
-            tot += Fraction(sx[s] * (sk[s] - sx[s]), G.two_m[s])
-    return Fraction(gamma) * tot
+        if cpm:
+            tot += gam[s] * sx[s] * (sk[s] - sx[s])
+        elif G.two_m[s]:
+            tot += gam[s] * Fraction(sx[s] * (sk[s] - sx[s]), G.two_m[s])
+    return tot
 
 
 def refine(G, score, gamma, units, adj, labels, seed, it, lvl, stats, null_model=0):
@@ -393,14 +418,20 @@ def split_components(G, flat):
 
 
 def leiden(g, gamma=1, omega=1, max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
-           null_model=0):
+           null_model=0, gamma_slices=None, initial=None):
     """Run the schedule; returns (membership, stats, trace).  trace holds one record per
     level: colour, labels at the level's start (p_in), after local moving (p_lm), R, and the
     refined sub-communities (founder -> level-0 members) with their well-connectedness.
-    null_model 0 optimises Q_MS of Eq. 6; 1 the global modularity of the supra-graph."""
+    null_model 0 optimises Q_MS of Eq. 6; 1 the global modularity of the supra-graph; 2 the
+    multislice CPM.  gamma_slices: T per-slice resolutions in place of gamma; initial: the
+    first iteration's start partition."""
     G = SupraGraph(g, omega)
-    score = GlobalScore(G, gamma) if null_model == 1 else Score(G, gamma)
-    gamma = Fraction(gamma)
+    if gamma_slices is not None:
+        assert null_model != 1
+        gamma = [Fraction(x) for x in gamma_slices]
+    else:
+        gamma = Fraction(gamma)
+    score = GlobalScore(G, gamma) if null_model == 1 else Score(G, gamma, cpm=null_model == 2)
     if max_sweeps <= 0:
         max_sweeps = DEFAULT_SWEEPS
     iters = max_iterations if max_iterations > 0 else MAX_ITER_CAP
@@ -408,7 +439,7 @@ def leiden(g, gamma=1, omega=1, max_levels=32, max_iterations=2, max_sweeps=0, s
     stats = dict(sweeps=0, moves=0, sweep_cap_hits=0, refine_rounds=0, merges=0, splits=0,
                  levels_run=0, iterations_run=0, n_communities=0, colours_first=0)
     trace = []
-    prev = list(range(G.n))
+    prev = list(range(G.n)) if initial is None else canonical([int(x) for x in initial])
     for it in range(iters):
         units = [[v] for v in range(G.n)]
         labels = canonical(prev)

@@ -23,11 +23,13 @@ int orc_create(int32_t N, int32_t T, const int64_t *off, const int32_t *src, con
 void orc_destroy(orc_graph *g);
 int64_t orc_nnz(const orc_graph *g);
 void orc_csr(const orc_graph *g, int64_t *rp, int32_t *col, int64_t *w, int32_t *raw, int64_t *twom);
-int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den, int32_t max_levels,
+int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den,
+               const int64_t *gamma_slices, const int32_t *initial, int32_t max_levels,
                int32_t max_iterations, int32_t max_sweeps, uint64_t seed, int32_t null_model,
                int32_t *membership, int64_t *comps, orc_stats *st);
 int orc_q_components(const orc_graph *G, const int32_t *memb, int64_t *comps);
 int orc_q_components_global(const orc_graph *G, const int32_t *memb, int64_t *comps);
+int orc_q_components_cpm(const orc_graph *G, const int32_t *memb, int64_t *comps);
 int orc_gain_sign(int64_t p, int64_t q, int64_t b, const int64_t *S, int64_t W, int m,
                   const int32_t *ps, const int64_t *pk, const int64_t *y);
 void orc_trace_enable(int on);
@@ -185,8 +187,18 @@ void oracle_runs() {
     std::vector<int32_t> memb(n);
     std::vector<int64_t> comps(3 * T + 1);
     orc_stats st{};
-    const int model = rep % 3 == 2 ? 1 : 0;   // every third run with the global null model
-    expect(orc_leiden(og, pick(1, 4), pick(1, 3), (int32_t)pick(1, 32), (int32_t)pick(0, 3),
+    // the three objectives in turn; per-slice resolutions and a start partition now and then
+    const int model = rep % 3;
+    std::vector<int64_t> gs(2 * T);
+    for (int s = 0; s < T; s++) {
+      gs[2 * s] = pick(1, 4);
+      gs[2 * s + 1] = pick(1, 3);
+    }
+    std::vector<int32_t> init(n);
+    for (int64_t v = 0; v < n; v++) init[v] = (int32_t)pick(0, n - 1);
+    const bool per_slice = model != 1 && rep % 5 < 2, warm = rep % 7 < 3;
+    expect(orc_leiden(og, pick(1, 4), pick(1, 3), per_slice ? gs.data() : nullptr,
+                      warm ? init.data() : nullptr, (int32_t)pick(1, 32), (int32_t)pick(0, 3),
                       (int32_t)pick(0, 4), next(), model, memb.data(), comps.data(), &st) == 0,
            "oracle leiden");
     if (trace) {
@@ -210,6 +222,7 @@ void oracle_runs() {
     }
     std::vector<int64_t> comps2(3 * T + 1);
     if (model == 1) orc_q_components_global(og, memb.data(), comps2.data());
+    else if (model == 2) orc_q_components_cpm(og, memb.data(), comps2.data());
     else orc_q_components(og, memb.data(), comps2.data());
     expect(comps == comps2, "Q components of the result");
     orc_destroy(og);
