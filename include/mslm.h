@@ -44,11 +44,13 @@ typedef struct mslm_server mslm_server; /* continuous-batching request loop     
 enum { MSLM_INPUT_ON_DEVICE = 1u, MSLM_OUTPUT_ON_DEVICE = 2u, MSLM_PROFILE = 4u, MSLM_COUNT = 8u };
 
 /* The objective a solve maximises.  MULTISLICE: Q_MS of Eq. 6, a null model per snapshot
- * (gamma k_i^s k_j^s / 2m_s).  GLOBAL: the modularity of Eq. 5 over the whole supra-graph of
- * Eq. 3 (null model gamma kappa_u kappa_v / 2mu with kappa the supra-degree, intra weight
+ * (gamma^(s) k_i^s k_j^s / 2m_s).  GLOBAL: the modularity of Eq. 5 over the whole supra-graph
+ * of Eq. 3 (null model gamma kappa_u kappa_v / 2mu with kappa the supra-degree, intra weight
  * plus coupling), the objective the paper's GPU path optimised on the supra-graph in place of
- * Q_MS (Section 3.2). */
-enum { MSLM_NULL_MULTISLICE = 0, MSLM_NULL_GLOBAL = 1 };
+ * Q_MS (Section 3.2).  CPM: the multislice Constant Potts Model that Section 3.2 names as a
+ * quality function of the same supra-graph strategy, read as Eq. 6 with the null term
+ * gamma^(s) n_i n_j, node weight n = 1 per supra-node (no 2m_s), under the same 1/2mu. */
+enum { MSLM_NULL_MULTISLICE = 0, MSLM_NULL_GLOBAL = 1, MSLM_NULL_CPM = 2 };
 
 /* One temporal graph.  Slice s holds edges [slice_offsets[s], slice_offsets[s+1]) of
  * src/dst/weight: undirected, each edge listed once in either orientation, ids in [0, N),
@@ -72,9 +74,16 @@ typedef struct {
  * iteration; max_iterations <= 0 runs iterations until the partition is stable (at most
  * 32); max_sweeps <= 0 means 32 local-moving sweeps per level.  The seed only changes the
  * hash priorities of the schedule.  Numerators and denominators must be below 2^31.
- * null_model: MSLM_NULL_MULTISLICE (0) or MSLM_NULL_GLOBAL (1); with GLOBAL the scaled total
- * weight 2mu' = b * sum_s 2m_s + 2 a N (T-1) (omega = a/b) must stay below 2^31 and
- * max(p, q) * 2mu'^2 below 2^62 (else EOVERFLOW). */
+ * null_model: MSLM_NULL_MULTISLICE (0), MSLM_NULL_GLOBAL (1) or MSLM_NULL_CPM (2); with GLOBAL
+ * the scaled total weight 2mu' = b * sum_s 2m_s + 2 a N (T-1) (omega = a/b) must stay below
+ * 2^31 and max(p, q) * 2mu'^2 below 2^62 (else EOVERFLOW).
+ * gamma_slices (host, NULL = gamma in every slice): T pairs (num, den), the resolution
+ * gamma^(s) of each slice (Eq. 6), each positive with num, den < 2^31; not with GLOBAL
+ * (EINVAL).  The kernels fold them into the slice denominators (see mslm_leiden's errors).
+ * initial_membership (host, NULL = singletons): the start partition of the first Leiden
+ * iteration (warm start, or resume from an earlier result), T*N labels in [0, T*N) in
+ * supra-node order (equal labels = one community; any labelling of a partition gives the same
+ * solve).  Both arrays are read during the call (copied by mslm_server_submit). */
 typedef struct {
   int64_t gamma_num, gamma_den;
   int64_t omega_num, omega_den;
@@ -89,12 +98,15 @@ typedef struct {
                                      launches of aggregated levels are left untimed);
                                      MSLM_COUNT: count the work of those kernels            */
   uint32_t reserved1;
+  const int64_t *gamma_slices;
+  const int32_t *initial_membership;
 } mslm_params;
 
 /* Per-solve outcome.  q_components (3T+1 int64) are the exact integer pieces of Q:
  * W_s (weight inside communities in slice s, both directions), SS_s (sum over communities
- * of the squared slice-s degree), 2m_s, and I (ordered coupled copy pairs sharing a
- * community); mslm_q_exact turns them into the reduced fraction Q.  For the GLOBAL null model
+ * of the squared slice-s degree; for the CPM of the squared slice-s supra-node count), 2m_s,
+ * and I (ordered coupled copy pairs sharing a community); mslm_q_exact (mslm_q_exact_variant
+ * for per-slice resolutions and the CPM) turns them into the reduced fraction Q.  For the GLOBAL null model
  * the T slots of SS hold one value, SS' = sum over communities of (sum of kappa')^2 with
  * kappa' = b * (intra degree) + a * (coupling count), then zeros; mslm_q_exact_global reduces
  * them. */
@@ -128,7 +140,10 @@ mslm_status mslm_create(const mslm_graph_desc *desc, void *hip_stream, mslm_grap
  * membership[T*N] receives the community of supra-node v = s*N + i, labelled 0..K-1 in
  * order of first appearance; every community is connected.  res may be NULL.
  * Errors: EINVAL (parameters), EOVERFLOW (int64 gain head-room: q*2m_s*w and p*b*k*Sigma
- * must stay below 2^62), ENOMEM, EHIP. */
+ * must stay below 2^62, with k and Sigma bounded by N under the CPM; with per-slice
+ * resolutions, Q = lcm of their denominators and C = lcm over s of gamma^(s)*Q take the places
+ * of q and p, each slice's 2m_s (1 under the CPM) is multiplied by C / (gamma^(s)*Q) and must
+ * stay below 2^31), ENOMEM, EHIP. */
 mslm_status mslm_leiden(mslm_graph *g, const mslm_params *params, int32_t *membership,
                         mslm_result *res);
 
@@ -147,6 +162,18 @@ mslm_status mslm_q_exact_global(const int64_t *q_components, int32_t n_slices, i
                                 int64_t gamma_num, int64_t gamma_den, int64_t omega_num,
                                 int64_t omega_den, char *num, size_t num_cap, char *den,
                                 size_t den_cap);
+
+/* Exact value of any objective from a solve's 3T+1 components: null_model MULTISLICE (Eq. 6,
+ * as mslm_q_exact), GLOBAL (as mslm_q_exact_global) or CPM, whose SS_s slots hold the sum over
+ * communities of the squared number of their slice-s supra-nodes:
+ *   Q = (sum_s [W_s - gamma^(s) SS_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1)).
+ * gamma_slices as in mslm_params (NULL: gamma_num/gamma_den in every slice; not with GLOBAL).
+ * Errors: EINVAL. */
+mslm_status mslm_q_exact_variant(const int64_t *q_components, int32_t n_slices, int32_t n_nodes,
+                                 int32_t null_model, const int64_t *gamma_slices,
+                                 int64_t gamma_num, int64_t gamma_den, int64_t omega_num,
+                                 int64_t omega_den, char *num, size_t num_cap, char *den,
+                                 size_t den_cap);
 
 /* Execution choices that change the speed of a solve and never its result (the same
  * memberships, Q components and statistics for every value).  Each graph handle holds one;

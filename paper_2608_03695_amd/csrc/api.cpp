@@ -20,10 +20,7 @@ namespace mslm {
 void api_finish(const GraphDev &g, const SolveSpec &sp, SolveOut &o, mslm_result *res) {
   std::string a, b;
   double qd = 0;
-  if (sp.null_model == MSLM_NULL_GLOBAL)
-    api_q_exact_global(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
-  else
-    api_q_exact(o.res.q_components, g.T, g.N, sp.p, sp.q, sp.a, sp.b, a, b, qd);
+  api_q_exact_spec(o.res.q_components, g.T, g.N, sp, a, b, qd);
   o.res.q = qd;
   if (res) *res = o.res;
 }
@@ -132,6 +129,40 @@ mslm_status mslm_q_exact_global(const int64_t *qc, int32_t T, int32_t N, int64_t
   return MSLM_OK;
 }
 
+mslm_status mslm_q_exact_variant(const int64_t *qc, int32_t T, int32_t N, int32_t null_model,
+                                 const int64_t *gamma_slices, int64_t gamma_num,
+                                 int64_t gamma_den, int64_t omega_num, int64_t omega_den,
+                                 char *num, size_t num_cap, char *den, size_t den_cap) {
+  if (!qc || !num || !den || T < 1 || T > 64 || N < 1) return fail(MSLM_EINVAL, "bad arguments");
+  if (null_model == MSLM_NULL_GLOBAL && !gamma_slices)
+    return mslm_q_exact_global(qc, T, N, gamma_num, gamma_den, omega_num, omega_den, num,
+                               num_cap, den, den_cap);
+  if (null_model != MSLM_NULL_MULTISLICE && null_model != MSLM_NULL_CPM)
+    return fail(MSLM_EINVAL, "null_model: one resolution for the global null model, else "
+                             "MSLM_NULL_MULTISLICE or MSLM_NULL_CPM");
+  mslm_status s = api_check_fraction(omega_num, omega_den, "omega");
+  if (s != MSLM_OK) return s;
+  std::vector<int64_t> gn(T), gd(T);
+  for (int t = 0; t < T; t++) {
+    const int64_t a = gamma_slices ? gamma_slices[2 * t] : gamma_num;
+    const int64_t d = gamma_slices ? gamma_slices[2 * t + 1] : gamma_den;
+    s = api_check_fraction(a, d, "gamma");
+    if (s != MSLM_OK) return s;
+    const int64_t g = a ? api_gcd(a, d) : d;
+    gn[t] = a / g;
+    gd[t] = d / g;
+  }
+  int64_t go = omega_num ? api_gcd(omega_num, omega_den) : omega_den;
+  std::string a, b;
+  double qd;
+  api_q_exact_slices(qc, T, N, gn.data(), gd.data(), null_model == MSLM_NULL_CPM,
+                     omega_num / go, omega_den / go, a, b, qd);
+  if (a.size() + 1 > num_cap || b.size() + 1 > den_cap) return fail(MSLM_EINVAL, "buffer too small");
+  memcpy(num, a.c_str(), a.size() + 1);
+  memcpy(den, b.c_str(), b.size() + 1);
+  return MSLM_OK;
+}
+
 mslm_status mslm_get_tuning(const mslm_graph *g, mslm_tuning *out) {
   if (!g || !out) return fail(MSLM_EINVAL, "graph or tuning is NULL");
   api_tuning_to(g->tune, out);
@@ -172,7 +203,7 @@ mslm_status mslm_autotune(mslm_graph *g, const mslm_params *params, int32_t roun
   if (!g || !out) return fail(MSLM_EINVAL, "graph or tuning is NULL");
   if (rounds < 1 || rounds > 4) return fail(MSLM_EINVAL, "rounds must be in 1..4");
   SolveSpec sp;
-  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, sp);
+  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, g->g.N, g->g.T, sp);
   if (s != MSLM_OK) return s;
   Tuning best = g->tune;
   SolveOut ref;
@@ -240,7 +271,7 @@ mslm_status mslm_leiden(mslm_graph *g, const mslm_params *params, int32_t *membe
   if (!g) return fail(MSLM_EINVAL, "graph is NULL");
   if (!membership) return fail(MSLM_EINVAL, "membership is NULL");
   SolveSpec sp;
-  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, sp);
+  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, g->g.N, g->g.T, sp);
   if (s != MSLM_OK) return s;
   std::vector<SolveOut> outs(1);
   if (params->flags & MSLM_OUTPUT_ON_DEVICE) outs[0].dev_membership = membership;
@@ -269,7 +300,8 @@ mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs, const
     int gi = solves[i].graph;
     if (gi < 0 || gi >= n_graphs || !graphs[gi]) return fail(MSLM_EINVAL, "solve names an invalid graph");
     if (!solves[i].membership) return fail(MSLM_EINVAL, "solve has no membership buffer");
-    mslm_status s = api_make_spec(&solves[i].params, graphs[gi]->g.omega_num, graphs[gi]->g.omega_den, specs[i]);
+    mslm_status s = api_make_spec(&solves[i].params, graphs[gi]->g.omega_num, graphs[gi]->g.omega_den,
+                                  graphs[gi]->g.N, graphs[gi]->g.T, specs[i]);
     if (s != MSLM_OK) return s;
     gs[i] = &graphs[gi]->g;
   }

@@ -95,9 +95,59 @@ mslm_status make_spec(const mslm_params *p, int64_t def_on, int64_t def_od, Solv
   sp.max_sweeps = p->max_sweeps > 0 ? p->max_sweeps : 32;
   if (sp.max_sweeps > 32) return fail(MSLM_EINVAL, "max_sweeps must be <= 32");
   sp.seed = p->seed;
-  if (p->null_model != MSLM_NULL_MULTISLICE && p->null_model != MSLM_NULL_GLOBAL)
-    return fail(MSLM_EINVAL, "null_model must be MSLM_NULL_MULTISLICE or MSLM_NULL_GLOBAL");
+  if (p->null_model != MSLM_NULL_MULTISLICE && p->null_model != MSLM_NULL_GLOBAL &&
+      p->null_model != MSLM_NULL_CPM)
+    return fail(MSLM_EINVAL, "null_model must be MSLM_NULL_MULTISLICE, MSLM_NULL_GLOBAL or "
+                             "MSLM_NULL_CPM");
   sp.null_model = p->null_model;
+  sp.pe = sp.p;
+  sp.qe = sp.q;
+  sp.gn.clear();
+  sp.gd.clear();
+  sp.smul.clear();
+  sp.init.clear();
+  return MSLM_OK;
+}
+
+typedef __int128 i128h;
+
+// lcm of two positive values, false when it reaches `limit`
+bool lcm_below(int64_t x, int64_t y, int64_t limit, int64_t &out) {
+  const i128h l = (i128h)(x / gcd64(x, y)) * y;
+  if (l >= limit) return false;
+  out = (int64_t)l;
+  return true;
+}
+
+// Per-slice resolutions: reduce them and fold them into (pe, qe, smul) as SolveSpec states.
+mslm_status slice_resolutions(const int64_t *gs, int32_t T, SolveSpec &sp) {
+  if (sp.null_model == MSLM_NULL_GLOBAL)
+    return fail(MSLM_EINVAL, "gamma_slices: the global null model has one resolution");
+  sp.gn.assign(T, 0);
+  sp.gd.assign(T, 1);
+  for (int s = 0; s < T; s++) {
+    mslm_status st = check_fraction(gs[2 * s], gs[2 * s + 1], "gamma_slices");
+    if (st != MSLM_OK) return st;
+    if (gs[2 * s] == 0) return fail(MSLM_EINVAL, "gamma_slices: every resolution must be > 0");
+    const int64_t g = gcd64(gs[2 * s], gs[2 * s + 1]);
+    sp.gn[s] = gs[2 * s] / g;
+    sp.gd[s] = gs[2 * s + 1] / g;
+  }
+  int64_t Q = 1, C = 1;
+  for (int s = 0; s < T; s++)
+    if (!lcm_below(Q, sp.gd[s], kLim31, Q))
+      return fail(MSLM_EOVERFLOW, "gamma_slices: the common denominator reaches 2^31");
+  sp.smul.assign(T, 1);
+  std::vector<int64_t> P(T);
+  for (int s = 0; s < T; s++) {
+    P[s] = sp.gn[s] * (Q / sp.gd[s]);   // < 2^62
+    if (!lcm_below(C, P[s], (int64_t)1 << 62, C))
+      return fail(MSLM_EOVERFLOW, "gamma_slices: the common multiple of the scaled resolutions "
+                                  "reaches 2^62");
+  }
+  for (int s = 0; s < T; s++) sp.smul[s] = C / P[s];
+  sp.pe = C;
+  sp.qe = Q;
   return MSLM_OK;
 }
 
@@ -245,15 +295,21 @@ double to_double(const BigU &a) {
   return x;
 }
 
-// Q = (sum_s [W_s - gamma SS_s / 2m_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1)),
-// multiplied through by b*q*prod(2m_s != 0) and reduced.
-mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa, int64_t ob,
-                    std::string &num, std::string &den, double &qd) {
-  std::vector<int64_t> nzm;
-  for (int s = 0; s < T; s++)
-    if (c[2 * T + s] > 0) nzm.push_back(c[2 * T + s]);
+// Q = (sum_s [W_s - gamma^(s) SS_s / D_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1)) with
+// D_s = 2m_s (Eq. 6; a slice without edges has no null term) or 1 (the multislice CPM),
+// multiplied through by b * L, L = prod over the slices with a null term of gd_s * D_s, and
+// reduced.
+mslm_status q_exact_gen(const int64_t *c, int T, int N, const int64_t *gn, const int64_t *gd,
+                        bool cpm, int64_t oa, int64_t ob, std::string &num, std::string &den,
+                        double &qd) {
+  std::vector<uint64_t> dn(T, 0);   // gd_s * D_s (< 2^62), 0: no null term
+  for (int s = 0; s < T; s++) {
+    const int64_t D = cpm ? 1 : c[2 * T + s];
+    if (D > 0) dn[s] = (uint64_t)gd[s] * (uint64_t)D;
+  }
   BigU L = BigU::from(1);
-  for (int64_t m : nzm) L.mul((uint64_t)m);
+  for (uint64_t m : dn)
+    if (m) L.mul(m);
   BigS sumN;   // numerator
   int64_t sumW = 0, sum2m = 0;
   for (int s = 0; s < T; s++) {
@@ -262,42 +318,34 @@ mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int6
   }
   BigS t = mk(sumW);
   t.m.mul((uint64_t)ob);
-  t.m.mul((uint64_t)gq);
-  t.m = [&] { BigU x = t.m; for (int64_t m : nzm) x.mul((uint64_t)m); return x; }();
+  t.m = [&] { BigU x = t.m; for (uint64_t m : dn) if (m) x.mul(m); return x; }();
   sumN = adds(sumN, t);
   for (int s = 0; s < T; s++) {
-    int64_t m2 = c[2 * T + s];
-    if (m2 <= 0) continue;
+    if (!dn[s]) continue;
     BigS u = mk(c[T + s]);
     u.m.mul((uint64_t)ob);
-    u.m.mul((uint64_t)gp);
-    bool skipped = false;
-    for (int64_t m : nzm) {
-      if (!skipped && m == m2) {
-        skipped = true;
-        continue;
-      }
-      u.m.mul((uint64_t)m);
-    }
+    u.m.mul((uint64_t)gn[s]);
+    for (int r = 0; r < T; r++)
+      if (r != s && dn[r]) u.m.mul(dn[r]);
     u.neg = !u.m.zero();
     sumN = adds(sumN, u);
   }
   BigS iv = mk(c[3 * T]);
   iv.m.mul((uint64_t)oa);
-  iv.m.mul((uint64_t)gq);
-  for (int64_t m : nzm) iv.m.mul((uint64_t)m);
+  for (uint64_t m : dn)
+    if (m) iv.m.mul(m);
   sumN = adds(sumN, iv);
-  // denominator: b*q*L*sum 2m_s + 2*a*q*L*N*(T-1)
+  // denominator: b*L*sum 2m_s + 2*a*L*N*(T-1)
   BigU d1 = BigU::from((uint64_t)sum2m);
   d1.mul((uint64_t)ob);
-  d1.mul((uint64_t)gq);
-  for (int64_t m : nzm) d1.mul((uint64_t)m);
+  for (uint64_t m : dn)
+    if (m) d1.mul(m);
   BigU d2 = BigU::from(2);
   d2.mul((uint64_t)oa);
-  d2.mul((uint64_t)gq);
   d2.mul((uint64_t)N);
   d2.mul((uint64_t)(T - 1));
-  for (int64_t m : nzm) d2.mul((uint64_t)m);
+  for (uint64_t m : dn)
+    if (m) d2.mul(m);
   BigU D = addu(d1, d2);
   if (D.zero()) {   // empty supra-graph: Q = 0 by convention
     num = "0";
@@ -325,6 +373,13 @@ mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int6
   b.d.erase(b.d.begin(), b.d.begin() + std::min(sh, b.d.size()));
   qd = (sumN.neg ? -1.0 : 1.0) * to_double(a) / to_double(b);
   return MSLM_OK;
+}
+
+// Eq. 6 with one resolution gp/gq in every slice.
+mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa, int64_t ob,
+                    std::string &num, std::string &den, double &qd) {
+  std::vector<int64_t> gn(T, gp), gd(T, gq);
+  return q_exact_gen(c, T, N, gn.data(), gd.data(), false, oa, ob, num, den, qd);
 }
 
 }  // namespace
@@ -456,8 +511,61 @@ mslm_status api_check_fraction(int64_t num, int64_t den, const char *what) {
   return check_fraction(num, den, what);
 }
 int64_t api_gcd(int64_t a, int64_t b) { return gcd64(a, b); }
-mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, SolveSpec &sp) {
-  return make_spec(p, on, od, sp);
+mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, int32_t N, int32_t T,
+                          SolveSpec &sp) {
+  mslm_status s = make_spec(p, on, od, sp);
+  if (s != MSLM_OK) return s;
+  if (p->gamma_slices) {
+    s = slice_resolutions(p->gamma_slices, T, sp);
+    if (s != MSLM_OK) return s;
+  }
+  if (p->initial_membership) {
+    const int64_t n = (int64_t)N * T;
+    for (int64_t v = 0; v < n; v++)
+      if (p->initial_membership[v] < 0 || p->initial_membership[v] >= n)
+        return fail(MSLM_EINVAL, "initial_membership: label of supra-node " + std::to_string(v) +
+                                     " outside [0, T*N)");
+    sp.init.assign(p->initial_membership, p->initial_membership + n);
+  }
+  return MSLM_OK;
+}
+
+bool api_slice_denominator(const SolveSpec &sp, int s, int64_t two_m, int64_t N, int64_t &Sdev) {
+  const bool cpm = sp.null_model == MSLM_NULL_CPM;
+  const int64_t S = two_m > 0 ? two_m : 1;
+  const i128h sd = (i128h)(cpm ? 1 : S) * (sp.smul.empty() ? 1 : sp.smul[s]);
+  if (sd >= kLim31) {
+    fail(MSLM_EOVERFLOW, "per-slice resolutions: a scaled slice denominator reaches 2^31");
+    return false;
+  }
+  const i128h K = cpm ? N : S;
+  const i128h a1 = (i128h)sp.qe * sd * ((i128h)sp.b * S + 2 * sp.a);
+  const i128h a2 = (i128h)sp.pe * sp.b * K * K;
+  if (a1 >= ((i128h)1 << 62) || a2 >= ((i128h)1 << 62)) {
+    fail(MSLM_EOVERFLOW, "gain head-room: q*2m_s*w or p*b*k*Sigma reaches 2^62");
+    return false;
+  }
+  Sdev = (int64_t)sd;
+  return true;
+}
+
+mslm_status api_q_exact_spec(const int64_t *c, int T, int N, const SolveSpec &sp,
+                             std::string &num, std::string &den, double &qd) {
+  if (sp.null_model == MSLM_NULL_GLOBAL)
+    return api_q_exact_global(c, T, N, sp.p, sp.q, sp.a, sp.b, num, den, qd);
+  std::vector<int64_t> gn(sp.gn), gd(sp.gd);
+  if (gn.empty()) {
+    gn.assign(T, sp.p);
+    gd.assign(T, sp.q);
+  }
+  return q_exact_gen(c, T, N, gn.data(), gd.data(), sp.null_model == MSLM_NULL_CPM, sp.a, sp.b,
+                     num, den, qd);
+}
+
+mslm_status api_q_exact_slices(const int64_t *c, int T, int N, const int64_t *gn,
+                               const int64_t *gd, bool cpm, int64_t oa, int64_t ob,
+                               std::string &num, std::string &den, double &qd) {
+  return q_exact_gen(c, T, N, gn, gd, cpm, oa, ob, num, den, qd);
 }
 mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
                         int64_t ob, std::string &num, std::string &den, double &qd) {
@@ -477,11 +585,8 @@ mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp) {
     }
     sum_two_m += two_m;
     if (sp.null_model == MSLM_NULL_GLOBAL) continue;
-    const __int128 S = two_m > 0 ? two_m : 1;
-    const __int128 a1 = (__int128)sp.q * S * ((__int128)sp.b * S + 2 * sp.a);
-    const __int128 a2 = (__int128)sp.p * sp.b * S * S;
-    if (a1 >= ((__int128)1 << 62) || a2 >= ((__int128)1 << 62))
-      return fail(MSLM_EOVERFLOW, "gain head-room: q*2m_s*w or p*b*k*Sigma reaches 2^62");
+    int64_t Sdev = 0;
+    if (!api_slice_denominator(sp, s, two_m, d->n_nodes, Sdev)) return MSLM_EOVERFLOW;
   }
   if (sp.null_model == MSLM_NULL_GLOBAL &&
       !api_global_headroom(global_two_mu(sum_two_m, d->n_nodes, d->n_slices, sp), sp))

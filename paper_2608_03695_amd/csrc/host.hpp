@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/mslm.h"
 
@@ -15,6 +16,17 @@ struct SolveSpec {
   int32_t max_levels = 32, max_iterations = 2, max_sweeps = 32;
   int32_t null_model = MSLM_NULL_MULTISLICE;
   uint64_t seed = 0;
+  // per-slice resolutions gamma^(s) = gn[s]/gd[s] (reduced); empty: p/q in every slice
+  std::vector<int64_t> gn, gd;
+  // the start partition of the first iteration [T*N]; empty: singletons
+  std::vector<int32_t> init;
+  // The constants of the exact gains.  With Q = lcm_s gd_s, P_s = gn_s * Q / gd_s and
+  // C = lcm_s P_s, slice s's null term gamma^(s) k y / S_s equals (C/Q) k y / (S_s * smul_s)
+  // with smul_s = C / P_s, so the kernels' values qe*S'*W - pe*b*k*y (pe = C, qe = Q,
+  // S' = S_s * smul_s) order targets as Eq. 6's gains do.  One resolution: pe = p, qe = q and
+  // smul empty (every multiplier 1).
+  int64_t pe = 1, qe = 1;
+  std::vector<int64_t> smul;
 };
 
 mslm_status api_fail(mslm_status s, const std::string &m);   // sets the error text
@@ -24,10 +36,27 @@ mslm_status api_check_shape(const mslm_graph_desc *d);
 mslm_status api_check_desc(const mslm_graph_desc *d);        // shape, then host edge lists
 mslm_status api_check_fraction(int64_t num, int64_t den, const char *what);
 int64_t api_gcd(int64_t a, int64_t b);
-mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, SolveSpec &sp);
-// The int64 head-room preconditions of a solve on host edge lists (2m_s < 2^31 per slice,
-// q*S*(b*S + 2a) < 2^62 and p*b*S^2 < 2^62 with S = max(2m_s, 1)).
+// Validates and reduces a solve's parameters for a graph of N nodes and T slices (on, od: the
+// graph's default coupling), copying the per-slice resolutions and the start partition.
+mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, int32_t N, int32_t T,
+                          SolveSpec &sp);
+// The kernels' denominator of slice s (2m_s, or 1 under the CPM, times the slice's multiplier)
+// and the int64 head-room of that slice's gains: S' < 2^31, qe*S'*(b*max(2m_s,1) + 2a) < 2^62
+// and pe*b*K^2 < 2^62 with K = max(2m_s, 1), or N under the CPM.  False with the error text
+// set when a bound fails.
+bool api_slice_denominator(const SolveSpec &sp, int s, int64_t two_m, int64_t N, int64_t &Sdev);
+// The head-room preconditions of a solve on host edge lists (2m_s < 2^31 per slice, then
+// api_slice_denominator per slice, or the global null model's).
 mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp);
+// Q of any objective of a solve from its 3T+1 components (the spec's null model and
+// resolutions) as a reduced decimal fraction and the nearest double.
+mslm_status api_q_exact_spec(const int64_t *c, int T, int N, const SolveSpec &sp,
+                             std::string &num, std::string &den, double &qd);
+// Q of Eq. 6 (cpm = false) or of the multislice CPM from the components with a resolution
+// gn[s]/gd[s] per slice.
+mslm_status api_q_exact_slices(const int64_t *c, int T, int N, const int64_t *gn,
+                               const int64_t *gd, bool cpm, int64_t oa, int64_t ob,
+                               std::string &num, std::string &den, double &qd);
 // Q of Eq. 6 from its 3T+1 components as a reduced decimal fraction and the nearest double.
 mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
                         int64_t ob, std::string &num, std::string &den, double &qd);

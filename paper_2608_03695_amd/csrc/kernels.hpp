@@ -3369,6 +3369,14 @@ __global__ void k_offset_labels(const int32_t *lab, const int32_t *usolve, const
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) out[v] = (uint32_t)(uoff[usolve[v]] + lab[v]);
 }
+// Each solve's labels by first appearance from the union's canonical labels (communities
+// ranked by their smallest member over the whole union): the solve's first unit is the
+// smallest member of its community, so its rank counts the communities of earlier solves.
+__global__ void k_local_labels(const uint32_t *comm, const int32_t *usolve, const int64_t *uoff,
+                               int64_t n, int32_t *out) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) out[v] = (int32_t)(comm[v] - comm[uoff[usolve[v]]]);
+}
 __global__ void k_count_roots_R(const uint32_t *R, const int32_t *usolve, int64_t n, uint32_t *cnt) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool h = u < n && R[u] == (uint32_t)u;

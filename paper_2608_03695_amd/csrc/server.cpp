@@ -303,7 +303,7 @@ mslm_status mslm_server_submit(mslm_server *s, const mslm_graph_desc *d, const m
   if (d->flags & MSLM_INPUT_ON_DEVICE)
     return api_fail(MSLM_EINVAL, "the server takes host edge lists only");
   auto r = std::make_shared<Request>();
-  rc = api_make_spec(p, d->omega_num, d->omega_den, r->spec);
+  rc = api_make_spec(p, d->omega_num, d->omega_den, d->n_nodes, d->n_slices, r->spec);
   if (rc != MSLM_OK) return rc;
   rc = api_check_headroom(d, r->spec);   // a request that passes cannot fail on head-room later
   if (rc != MSLM_OK) return rc;

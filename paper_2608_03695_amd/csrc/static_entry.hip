@@ -52,7 +52,7 @@ extern "C" mslm_status mslm_leiden_static(mslm_graph *g, const mslm_params *para
   if (params && (params->flags & MSLM_PROFILE))
     return api_fail(MSLM_EINVAL, "MSLM_PROFILE records HIP events, which this entry point does not create");
   SolveSpec sp;
-  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, sp);
+  mslm_status s = api_make_spec(params, g->g.omega_num, g->g.omega_den, g->g.N, g->g.T, sp);
   if (s != MSLM_OK) return s;
   const size_t need = solve_scratch_estimate(g->g.n, g->g.nnz);
   if (need > kScratchBytes)

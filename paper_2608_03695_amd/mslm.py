@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libmslm.so")
 MSLM_OK, MSLM_EINVAL, MSLM_ENOMEM, MSLM_EOVERFLOW, MSLM_EUNSUPPORTED, MSLM_EHIP, MSLM_EBUSY = \
     0, -1, -2, -3, -4, -5, -6
 MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE, MSLM_COUNT = 1, 2, 4, 8
-MSLM_NULL_MULTISLICE, MSLM_NULL_GLOBAL = 0, 1
+MSLM_NULL_MULTISLICE, MSLM_NULL_GLOBAL, MSLM_NULL_CPM = 0, 1, 2
 
 EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_q_exact_global",
-            "mslm_footprint_bytes",
+            "mslm_q_exact_variant", "mslm_footprint_bytes",
             "mslm_graph_info", "mslm_last_error", "mslm_set_allocator", "mslm_leiden_static",
             "mslm_batch_leiden", "mslm_get_tuning", "mslm_set_tuning", "mslm_autotune",
             "mslm_server_create", "mslm_server_submit", "mslm_server_wait",
@@ -52,7 +52,8 @@ class Params(C.Structure):
                 ("omega_num", C.c_int64), ("omega_den", C.c_int64),
                 ("max_levels", C.c_int32), ("max_iterations", C.c_int32),
                 ("max_sweeps", C.c_int32), ("null_model", C.c_int32),
-                ("seed", C.c_uint64), ("flags", C.c_uint32), ("reserved1", C.c_uint32)]
+                ("seed", C.c_uint64), ("flags", C.c_uint32), ("reserved1", C.c_uint32),
+                ("gamma_slices", C.c_void_p), ("initial_membership", C.c_void_p)]
 
 
 class Tuning(C.Structure):
@@ -128,6 +129,10 @@ def load():
     lib.mslm_q_exact.restype = C.c_int
     lib.mslm_q_exact_global.argtypes = lib.mslm_q_exact.argtypes
     lib.mslm_q_exact_global.restype = C.c_int
+    lib.mslm_q_exact_variant.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
+                                         C.c_int64, C.c_int64, C.c_int64, C.c_char_p, C.c_size_t,
+                                         C.c_char_p, C.c_size_t]
+    lib.mslm_q_exact_variant.restype = C.c_int
     lib.mslm_get_tuning.argtypes = [P, C.POINTER(Tuning)]
     lib.mslm_get_tuning.restype = C.c_int
     lib.mslm_set_tuning.argtypes = [P, C.POINTER(Tuning)]
@@ -184,16 +189,29 @@ def _desc(tg, omega):
     return d, keep
 
 
+def _slices_array(gamma_slices):
+    if gamma_slices is None:
+        return None
+    return np.array([[Fraction(x).numerator, Fraction(x).denominator] for x in gamma_slices],
+                    dtype=np.int64).ravel()
+
+
 def params(gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
-           flags=0, null_model=MSLM_NULL_MULTISLICE) -> Params:
+           flags=0, null_model=MSLM_NULL_MULTISLICE, gamma_slices=None, initial=None):
+    """(Params, arrays its pointers refer to): keep the second alive for the call."""
     gamma = Fraction(gamma)
     if omega is None:
         on, od = 0, 0
     else:
         omega = Fraction(omega)
         on, od = omega.numerator, omega.denominator
-    return Params(gamma.numerator, gamma.denominator, on, od, max_levels, max_iterations,
-                  max_sweeps, null_model, seed, flags, 0)
+    keep = [_slices_array(gamma_slices),
+            None if initial is None else np.ascontiguousarray(initial, dtype=np.int32)]
+    p = Params(gamma.numerator, gamma.denominator, on, od, max_levels, max_iterations,
+               max_sweeps, null_model, seed, flags, 0,
+               None if keep[0] is None else keep[0].ctypes.data,
+               None if keep[1] is None else keep[1].ctypes.data)
+    return p, keep
 
 
 def stream_handle(stream=None):
@@ -244,7 +262,7 @@ class Graph:
     def autotune(self, gamma=Fraction(1), omega=None, rounds=1, max_levels=32,
                  max_iterations=2, seed=0, null_model=MSLM_NULL_MULTISLICE):
         """mslm_autotune: returns (chosen tuning dict, ms with the starting tuning, ms tuned)."""
-        p = params(gamma, omega, max_levels, max_iterations, 0, seed, 0, null_model)
+        p, keep = params(gamma, omega, max_levels, max_iterations, 0, seed, 0, null_model)
         t = Tuning()
         a, b = C.c_double(), C.c_double()
         _check(load().mslm_autotune(self._h, C.byref(p), int(rounds), C.byref(t), C.byref(a),
@@ -258,11 +276,13 @@ class Graph:
 
     def leiden(self, gamma=Fraction(1), omega=None, max_levels=32, max_iterations=2, max_sweeps=0,
                seed=0, profile=False, count=False, out=None, no_alloc=False,
-               null_model=MSLM_NULL_MULTISLICE):
+               null_model=MSLM_NULL_MULTISLICE, gamma_slices=None, initial=None):
         """Returns (membership int32[T*N], result dict).  `out` may be a device tensor
         (torch, int32, T*N elements) to receive the membership on the device.  no_alloc
         calls the allocation-free entry point (mslm_leiden_static).  null_model selects
-        Q_MS (Eq. 6, the default) or the global modularity of the supra-graph (Eq. 5)."""
+        Q_MS (Eq. 6, the default), the global modularity of the supra-graph (Eq. 5) or the
+        multislice CPM; gamma_slices gives T per-slice resolutions in place of gamma; initial
+        is a start partition (T*N labels in [0, T*N))."""
         lib = load()
         flags = (MSLM_PROFILE if profile else 0) | (MSLM_COUNT if count else 0)
         if out is not None:
@@ -272,7 +292,8 @@ class Graph:
         else:
             memb = np.empty(self.n_nodes * self.n_slices, dtype=np.int32)
             dest = _ptr(memb)
-        p = params(gamma, omega, max_levels, max_iterations, max_sweeps, seed, flags, null_model)
+        p, keep = params(gamma, omega, max_levels, max_iterations, max_sweeps, seed, flags,
+                         null_model, gamma_slices, initial)
         res = Result()
         entry = lib.mslm_leiden_static if no_alloc else lib.mslm_leiden
         _check(entry(self._h, C.byref(p), dest, C.byref(res)))
@@ -302,6 +323,22 @@ def q_exact_global(components, n_slices, n_nodes, gamma, omega) -> Fraction:
     _check(lib.mslm_q_exact_global(_ptr(comps), n_slices, n_nodes, gamma.numerator,
                                    gamma.denominator, omega.numerator, omega.denominator, num,
                                    4096, den, 4096))
+    return Fraction(int(num.value.decode()), int(den.value.decode()))
+
+
+def q_exact_variant(components, n_slices, n_nodes, gamma, omega, null_model=MSLM_NULL_MULTISLICE,
+                    gamma_slices=None) -> Fraction:
+    """Exact value of any objective (Eq. 6 with per-slice resolutions, the global null model,
+    the multislice CPM) from a solve's components, via the library's reduction."""
+    lib = load()
+    gamma, omega = Fraction(gamma), Fraction(omega)
+    comps = np.ascontiguousarray(components, dtype=np.int64)
+    gs = _slices_array(gamma_slices)
+    num = C.create_string_buffer(1 << 16)
+    den = C.create_string_buffer(1 << 16)
+    _check(lib.mslm_q_exact_variant(_ptr(comps), n_slices, n_nodes, null_model, _ptr(gs),
+                                    gamma.numerator, gamma.denominator, omega.numerator,
+                                    omega.denominator, num, 1 << 16, den, 1 << 16))
     return Fraction(int(num.value.decode()), int(den.value.decode()))
 
 
@@ -348,9 +385,10 @@ class Server:
         self._shape = {}
 
     def submit(self, tg, gamma=Fraction(1), omega=Fraction(1), max_levels=32, max_iterations=2,
-               seed=0, null_model=MSLM_NULL_MULTISLICE) -> int:
+               seed=0, null_model=MSLM_NULL_MULTISLICE, gamma_slices=None, initial=None) -> int:
         d, keep = _desc(tg, omega)
-        p = params(gamma, None, max_levels, max_iterations, 0, seed, 0, null_model)
+        p, pkeep = params(gamma, None, max_levels, max_iterations, 0, seed, 0, null_model,
+                          gamma_slices, initial)
         t = C.c_uint64()
         _check(load().mslm_server_submit(self._h, C.byref(d), C.byref(p), C.byref(t)))
         self._shape[t.value] = (tg.n_nodes, tg.n_slices)
@@ -385,22 +423,28 @@ class Server:
 
 
 def batch_leiden(graphs: Sequence[Graph], solves, stream=None):
-    """solves: list of (graph index, gamma, omega, max_levels, max_iterations, seed) with an
-    optional seventh item, the null model.  Returns a list of (membership, result dict),
-    bit-identical to plain calls."""
+    """solves: list of (graph index, gamma, omega, max_levels, max_iterations, seed) with
+    optional further items: the null model, the per-slice resolutions, a start partition.
+    Returns a list of (membership, result dict), bit-identical to plain calls."""
     lib = load()
     arr = (C.c_void_p * len(graphs))(*[g._h for g in graphs])
     cs = (Solve * len(solves))()
     outs = []
+    keep = []
     for i, sv in enumerate(solves):
         gi, gamma, omega, levels, iters, seed = sv[:6]
         null_model = sv[6] if len(sv) > 6 else MSLM_NULL_MULTISLICE
+        gamma_slices = sv[7] if len(sv) > 7 else None
+        initial = sv[8] if len(sv) > 8 else None
         g = graphs[gi]
         memb = np.empty(g.n_nodes * g.n_slices, dtype=np.int32)
         res = Result()
         outs.append((memb, res, g.n_slices))
         cs[i].graph = gi
-        cs[i].params = params(gamma, omega, levels, iters, 0, seed, 0, null_model)
+        p, pkeep = params(gamma, omega, levels, iters, 0, seed, 0, null_model, gamma_slices,
+                          initial)
+        keep.append(pkeep)
+        cs[i].params = p
         cs[i].membership = memb.ctypes.data
         cs[i].result = C.addressof(res)
     _check(lib.mslm_batch_leiden(arr, len(graphs), cs, len(solves), stream_handle(stream)))

@@ -129,19 +129,49 @@ void host_checks() {
   p.gamma_den = 6;
   p.max_levels = 32;
   SolveSpec sp;
-  expect(api_make_spec(&p, 2, 4, sp) == MSLM_OK && sp.p == 1 && sp.q == 2 && sp.a == 1 && sp.b == 2,
+  expect(api_make_spec(&p, 2, 4, 10, 3, sp) == MSLM_OK && sp.p == 1 && sp.q == 2 && sp.a == 1 &&
+             sp.b == 2 && sp.pe == 1 && sp.qe == 2 && sp.smul.empty(),
          "spec reduction");
+  // per-slice resolutions over 64 slices and a start partition
+  {
+    mslm_params pv = p;
+    std::vector<int64_t> gs(128);
+    for (int s = 0; s < 64; s++) {
+      gs[2 * s] = pick(1, 12);
+      gs[2 * s + 1] = pick(1, 12);
+    }
+    std::vector<int32_t> init(64 * 5);
+    for (auto &x : init) x = (int32_t)pick(0, 64 * 5 - 1);
+    pv.gamma_slices = gs.data();
+    pv.initial_membership = init.data();
+    SolveSpec sv;
+    const mslm_status rc = api_make_spec(&pv, 1, 1, 5, 64, sv);
+    expect(rc == MSLM_OK || rc == MSLM_EOVERFLOW, "per-slice spec");
+    if (rc == MSLM_OK) {
+      bool ok = sv.smul.size() == 64 && sv.init.size() == 320;
+      for (int s = 0; s < 64 && ok; s++)   // gamma^(s) = pe / (qe * smul_s)
+        ok = (__int128)sv.gn[s] * sv.qe * sv.smul[s] == (__int128)sv.pe * sv.gd[s];
+      expect(ok, "per-slice constants");
+      int64_t Sd = 0;
+      (void)api_slice_denominator(sv, 3, pick(0, 1 << 20), 5, Sd);
+    }
+    init[7] = 64 * 5;
+    expect(api_make_spec(&pv, 1, 1, 5, 64, sv) == MSLM_EINVAL, "start label out of range");
+    init[7] = 0;
+    gs[10] = 0;
+    expect(api_make_spec(&pv, 1, 1, 5, 64, sv) == MSLM_EINVAL, "zero per-slice resolution");
+  }
   p.max_levels = 0;
-  expect(api_make_spec(&p, 1, 1, sp) == MSLM_EINVAL, "zero levels");
+  expect(api_make_spec(&p, 1, 1, 10, 3, sp) == MSLM_EINVAL, "zero levels");
   p.max_levels = 4;
   p.max_sweeps = 33;
-  expect(api_make_spec(&p, 1, 1, sp) == MSLM_EINVAL, "33 sweeps");
-  expect(api_make_spec(nullptr, 1, 1, sp) == MSLM_EINVAL, "NULL params");
+  expect(api_make_spec(&p, 1, 1, 10, 3, sp) == MSLM_EINVAL, "33 sweeps");
+  expect(api_make_spec(nullptr, 1, 1, 10, 3, sp) == MSLM_EINVAL, "NULL params");
   // head-room: a dense slice with gamma 2^30
   Graph dense = random_graph(400, 1, 40000);
   mslm_graph_desc dd = dense.desc(false);
   SolveSpec big;
-  big.p = (int64_t)1 << 30;
+  big.p = big.pe = (int64_t)1 << 30;
   expect(api_check_headroom(&dd, big) == MSLM_EOVERFLOW, "head-room overflow");
   SolveSpec one;
   expect(api_check_headroom(&dd, one) == MSLM_OK, "head-room ok");
@@ -162,6 +192,15 @@ void host_checks() {
                        pick(1, 1 << 30), num, den, q) == MSLM_OK && !num.empty() && !den.empty() &&
                den != "0",
            "exact Q");
+    std::vector<int64_t> gn(T), gd(T);
+    for (int s = 0; s < T; s++) {
+      gn[s] = pick(1, ((int64_t)1 << 31) - 1);
+      gd[s] = pick(1, ((int64_t)1 << 31) - 1);
+    }
+    expect(api_q_exact_slices(c.data(), T, N, gn.data(), gd.data(), rep % 2 == 1,
+                              pick(0, 1 << 30), pick(1, 1 << 30), num, den, q) == MSLM_OK &&
+               !num.empty() && den != "0",
+           "exact Q, per-slice resolutions");
   }
 }
 

@@ -56,7 +56,7 @@ def test_null_arguments_rejected():
     lib = mslm.load()
     import ctypes as C
     assert lib.mslm_create(None, None, C.byref(C.c_void_p())) == mslm.MSLM_EINVAL
-    p = mslm.params()
+    p, _ = mslm.params()
     assert lib.mslm_leiden(None, C.byref(p), None, None) == mslm.MSLM_EINVAL
     lib.mslm_destroy(None)   # NULL-safe
     assert b"NULL" in lib.mslm_last_error() or lib.mslm_last_error()
@@ -128,3 +128,37 @@ def test_exact_global_q_of_the_hand_example():
     assert mslm.q_exact_global(np.array([2, 2, 64, 0, 2, 2, 4]), 2, 2, 1, 1) == 0
     assert mslm.q_exact_global(np.array([0, 0, 32, 0, 2, 2, 4]), 2, 2, 1, 1) == 0
     assert mslm.q_exact_global(np.array([0, 0, 16, 0, 2, 2, 0]), 2, 2, 1, 1) == F(-1, 4)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_exact_q_reduction_of_the_variants_matches_rationals(seed):
+    """The library's reduction with a resolution per slice, for Eq. 6 and for the multislice
+    CPM (SS_s = squared community sizes), against the oracle's rational formulas."""
+    rng = random.Random(900 + seed)
+    T = rng.randint(1, 64)
+    N = rng.randint(1, 10 ** 6)
+    comps = np.zeros(3 * T + 1, np.int64)
+    for s in range(T):
+        tm = rng.choice([0, rng.randint(1, 2 ** 31 - 1)])
+        comps[2 * T + s] = tm
+        comps[s] = rng.randint(0, tm) if tm else 0
+        comps[T + s] = rng.randint(0, tm * tm) if tm else 0
+    comps[3 * T] = 2 * rng.randint(0, N * (T - 1))
+    gs = [F(rng.randint(1, 2 ** 31 - 1), rng.randint(1, 2 ** 31 - 1)) for _ in range(T)]
+    omega = F(rng.randint(0, 2 ** 31 - 1), rng.randint(1, 2 ** 31 - 1))
+    assert mslm.q_exact_variant(comps, T, N, 1, omega, mslm.MSLM_NULL_MULTISLICE, gs) == \
+        oracle.q_from_components(comps, N, T, gs, omega)
+    assert mslm.q_exact_variant(comps, T, N, 1, omega, mslm.MSLM_NULL_CPM, gs) == \
+        oracle.q_cpm_from_components(comps, N, T, gs, omega)
+    # one resolution: the same as mslm_q_exact
+    assert mslm.q_exact_variant(comps, T, N, gs[0], omega) == mslm.q_exact(comps, T, N, gs[0], omega)
+
+
+def test_exact_q_variant_refuses_bad_arguments():
+    comps = np.zeros(7, np.int64)
+    with pytest.raises(mslm.MslmError) as e:
+        mslm.q_exact_variant(comps, 2, 2, 1, 1, mslm.MSLM_NULL_GLOBAL, [F(1), F(2)])
+    assert e.value.status == mslm.MSLM_EINVAL
+    with pytest.raises(mslm.MslmError) as e:
+        mslm.q_exact_variant(comps, 2, 2, 1, 1, 7)
+    assert e.value.status == mslm.MSLM_EINVAL
