@@ -70,12 +70,14 @@ def _load():
                            "run oracle.build() (or __graft_entry__.build()) first")
     lib = C.CDLL(_LIB_PATH)
     P = C.c_void_p
-    lib.orc_create.argtypes = [C.c_int32, C.c_int32, P, P, P, P, C.c_int64, C.c_int64,
-                               C.POINTER(C.c_void_p)]
+    lib.orc_create.argtypes = [C.c_int32, C.c_int32, P, P, P, P, C.c_int64, C.c_int64, P,
+                               C.c_int32, C.POINTER(C.c_void_p)]
     lib.orc_create.restype = C.c_int
     lib.orc_destroy.argtypes = [P]
     lib.orc_nnz.argtypes = [P]
     lib.orc_nnz.restype = C.c_int64
+    lib.orc_coupling_total.argtypes = [P]
+    lib.orc_coupling_total.restype = C.c_int64
     lib.orc_csr.argtypes = [P, P, P, P, P, P]
     lib.orc_leiden.argtypes = [P, C.c_int64, C.c_int64, P, P, C.c_int32, C.c_int32, C.c_int32,
                                C.c_uint64, C.c_int32, P, P, C.POINTER(Stats)]
@@ -125,9 +127,11 @@ def gain_sign(p, q, b, S, W, slices, k, y) -> int:
 
 
 class OracleGraph:
-    """Level-0 supra-graph held by the C oracle for one coupling omega."""
+    """Level-0 supra-graph held by the C oracle for one coupling omega: ordinal by default,
+    else omega^(sr) = omega * coupling[s][r] (a T x T integer matrix), optionally only between
+    copies present in both slices."""
 
-    def __init__(self, g, omega):
+    def __init__(self, g, omega, coupling=None, present_only=False):
         lib = _load()
         omega = Fraction(omega)
         self.g = g
@@ -136,9 +140,11 @@ class OracleGraph:
                       np.ascontiguousarray(g.src, dtype=np.int32),
                       np.ascontiguousarray(g.dst, dtype=np.int32),
                       None if g.weight is None else np.ascontiguousarray(g.weight, dtype=np.int32)]
+        self._cm = None if coupling is None else np.ascontiguousarray(coupling, dtype=np.int32)
         h = C.c_void_p()
         rc = lib.orc_create(g.n_nodes, g.n_slices, *[_ptr(a) for a in self._keep],
-                            omega.numerator, omega.denominator, C.byref(h))
+                            omega.numerator, omega.denominator, _ptr(self._cm),
+                            1 if present_only else 0, C.byref(h))
         if rc != 0:
             raise ValueError(f"oracle create failed: {rc}")
         self._h = h
@@ -147,6 +153,10 @@ class OracleGraph:
         if getattr(self, "_h", None):
             _load().orc_destroy(self._h)
             self._h = None
+
+    def coupling_total(self) -> int:
+        """Sum of c_sr over the ordered coupled copy pairs (2mu = sum 2m_s + omega * this)."""
+        return int(_load().orc_coupling_total(self._h))
 
     def csr(self):
         lib = _load()
@@ -200,9 +210,14 @@ def _per_slice(gamma, T):
     return [Fraction(gamma)] * T
 
 
-def q_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
-    """Q = (sum_s [W_s - gamma^(s) SS_s / 2m_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1));
-    gamma: one resolution or T per-slice resolutions."""
+def _coupled(n_nodes, n_slices, coupling_total):
+    return 2 * n_nodes * (n_slices - 1) if coupling_total is None else int(coupling_total)
+
+
+def q_from_components(comps, n_nodes, n_slices, gamma, omega, coupling_total=None) -> Fraction:
+    """Q = (sum_s [W_s - gamma^(s) SS_s / 2m_s] + omega I) / (sum_s 2m_s + omega Ctot);
+    gamma: one resolution or T per-slice resolutions; Ctot: the coupling total of the graph
+    (None: 2 N (T-1), every copy coupled ordinally)."""
     T = n_slices
     gam, omega = _per_slice(gamma, T), Fraction(omega)
     W, SS, tm, I = comps[:T], comps[T:2 * T], comps[2 * T:3 * T], comps[3 * T]
@@ -212,31 +227,33 @@ def q_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
         if int(tm[s]):
             num -= gam[s] * int(SS[s]) / Fraction(int(tm[s]))
     num += omega * int(I)
-    den = sum(int(x) for x in tm) + 2 * omega * n_nodes * (T - 1)
+    den = sum(int(x) for x in tm) + omega * _coupled(n_nodes, T, coupling_total)
     return num / den if den else Fraction(0)
 
 
-def q_cpm_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
+def q_cpm_from_components(comps, n_nodes, n_slices, gamma, omega,
+                          coupling_total=None) -> Fraction:
     """The multislice CPM from its components (SS_s = sum over communities of the squared
     number of their slice-s supra-nodes): (sum_s [W_s - gamma^(s) SS_s] + omega I) / 2mu, the
-    normalisation 2mu = sum_s 2m_s + 2 omega N (T-1) of Eq. 6."""
+    normalisation 2mu = sum_s 2m_s + omega Ctot of Eq. 6."""
     T = n_slices
     gam, omega = _per_slice(gamma, T), Fraction(omega)
     W, SS, tm, I = comps[:T], comps[T:2 * T], comps[2 * T:3 * T], comps[3 * T]
     num = sum(int(W[s]) - gam[s] * int(SS[s]) for s in range(T)) + omega * int(I)
-    den = sum(int(x) for x in tm) + 2 * omega * n_nodes * (T - 1)
+    den = sum(int(x) for x in tm) + omega * _coupled(n_nodes, T, coupling_total)
     return num / den if den else Fraction(0)
 
 
-def q_global_from_components(comps, n_nodes, n_slices, gamma, omega) -> Fraction:
+def q_global_from_components(comps, n_nodes, n_slices, gamma, omega,
+                             coupling_total=None) -> Fraction:
     """Global modularity of the supra-graph from its components: with 2mu = sum_s 2m_s +
-    2 omega N (T-1), Q = (sum_s W_s + omega I - gamma (comps[T] / b^2) / 2mu) / 2mu, where
+    omega Ctot (Ctot = 2 N (T-1) for the ordinal coupling of every copy), Q = (sum_s W_s + omega I - gamma (comps[T] / b^2) / 2mu) / 2mu, where
     comps[T] = sum_C (sum_v kappa'_v)^2 in units scaled by the coupling denominator b."""
     T = n_slices
     gamma, omega = Fraction(gamma), Fraction(omega)
     b = omega.denominator
     W, SS, tm, I = comps[:T], int(comps[T]), comps[2 * T:3 * T], comps[3 * T]
-    two_mu = sum(int(x) for x in tm) + 2 * omega * n_nodes * (T - 1)
+    two_mu = sum(int(x) for x in tm) + omega * _coupled(n_nodes, T, coupling_total)
     if two_mu == 0:
         return Fraction(0)
     num = sum(int(x) for x in W) + omega * int(I) - gamma * Fraction(SS, b * b) / two_mu

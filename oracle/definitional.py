@@ -20,8 +20,12 @@ baseline may use it.  Everything is written straight from the paper's definition
   supra-node, under the same normalisation 1/2mu.
 
 Readings where the paper is silent (all listed with the design notes):
-* 2mu is the total weight of the supra-graph of Eq. 3: sum_s 2m_s + 2*omega*N*(T-1).
+* 2mu is the total weight of the supra-graph of Eq. 3: sum_s 2m_s + 2*omega*N*(T-1) for the
+  ordinal coupling, sum_s 2m_s + sum of omega^(sr) over ordered coupled copy pairs in general.
 * omega^(sr) = omega when |s - r| = 1 and 0 otherwise (ordinal coupling), omega^(ss) = 0.
+  Every function taking omega also takes a Coupling: omega^(sr) = omega * c_sr for an integer
+  matrix c, optionally only between copies present in both slices (a copy is present when it
+  has an edge in its slice; under the CPM an absent copy then has node weight 0).
 * A snapshot without edges (2m_s = 0) contributes no null-model term.
 * Supra-node (i, s) has index s*N + i (slice-major).
 """
@@ -57,6 +61,60 @@ def coupling(s, r, omega):
     return Fraction(omega) if abs(s - r) == 1 else Fraction(0)
 
 
+class Coupling:
+    """omega^(sr) = omega * c_sr between the copies (i, s) and (i, r) (Eq. 6); c is a T x T
+    integer matrix (None: the ordinal coupling, c_sr = 1 for |s - r| = 1); present_only: only
+    between copies that have an edge in their slices."""
+
+    def __init__(self, omega, matrix=None, present_only=False):
+        self.omega = Fraction(omega)
+        self.matrix = None if matrix is None else [[int(x) for x in row] for row in matrix]
+        self.present_only = bool(present_only)
+
+    def c(self, s, r):
+        if s == r:
+            return 0
+        if self.matrix is None:
+            return 1 if abs(s - r) == 1 else 0
+        return self.matrix[s][r]
+
+
+def as_coupling(omega):
+    return omega if isinstance(omega, Coupling) else Coupling(omega)
+
+
+def presence(g):
+    """present[s][i]: the copy (i, s) has an edge in slice s."""
+    out = [[False] * g.n_nodes for _ in range(g.n_slices)]
+    for s in range(g.n_slices):
+        u, x, _ = g.slice_edges(s)
+        for e in range(u.size):
+            out[s][int(u[e])] = out[s][int(x[e])] = True
+    return out
+
+
+def omega_sr(g, omega, i, s, r, pres=None):
+    """The coupling weight between (i, s) and (i, r)."""
+    cp = as_coupling(omega)
+    c = cp.c(s, r)
+    if not c:
+        return Fraction(0)
+    if cp.present_only:
+        pres = pres or presence(g)
+        if not (pres[s][i] and pres[r][i]):
+            return Fraction(0)
+    return cp.omega * c
+
+
+def node_weights(g, omega):
+    """CPM node weight per copy: 1, or 0 for an absent copy when only present copies are
+    coupled (they are then not supra-nodes)."""
+    cp = as_coupling(omega)
+    if not cp.present_only:
+        return [[1] * g.n_nodes for _ in range(g.n_slices)]
+    return [[1 if x else 0 for x in row] for row in presence(g)]
+
+
 def supra_adjacency(g, omega):
     """Dense A^supra of Eq. 3 as a list of lists of Fractions (order N*T, slice-major)."""
     n, t = g.n_nodes, g.n_slices
@@ -67,12 +125,13 @@ def supra_adjacency(g, omega):
         for i in range(n):
             for j in range(n):
                 A[s * n + i][s * n + j] = Fraction(mats[s][i][j])
+    pres = presence(g)
     for s in range(t):
         for r in range(t):
             if s != r:
-                c = coupling(s, r, omega)
-                if c:
-                    for i in range(n):
+                for i in range(n):
+                    c = omega_sr(g, omega, i, s, r, pres)
+                    if c:
                         A[s * n + i][r * n + i] = c
     return A
 
@@ -84,7 +143,10 @@ def degrees(mats):
 def two_mu(g, omega):
     mats = slice_matrices(g)
     tot = sum(sum(sum(row) for row in a) for a in mats)
-    return Fraction(tot) + 2 * Fraction(omega) * g.n_nodes * (g.n_slices - 1)
+    pres = presence(g)
+    return Fraction(tot) + sum((omega_sr(g, omega, i, s, r, pres) for s in range(g.n_slices)
+                                for r in range(g.n_slices) for i in range(g.n_nodes)),
+                               Fraction(0))
 
 
 def gammas(gamma, t):
@@ -95,11 +157,12 @@ def gammas(gamma, t):
     return [Fraction(gamma)] * t
 
 
-def null_term(gam, k, twom, s, i, j, cpm):
+def null_term(gam, k, twom, s, i, j, cpm, nw=None):
     """The null-model term of the pair (i, j) in slice s: gamma^(s) k_i k_j / 2m_s (zero in a
-    slice without edges), or gamma^(s) * 1 * 1 under the multislice CPM."""
+    slice without edges), or gamma^(s) n_i n_j under the multislice CPM (node weights nw,
+    1 by default)."""
     if cpm:
-        return gam[s]
+        return gam[s] * (nw[s][i] * nw[s][j] if nw else 1)
     if not twom[s]:
         return Fraction(0)
     return gam[s] * k[s][i] * k[s][j] / Fraction(twom[s])
@@ -117,10 +180,12 @@ def q_quadruple_sum(g, gamma, omega, membership, cpm=False):
     """Eq. 6 literally: (1/2mu) sum_{ijsr} [(A_ij^s - gamma^(s) k_i^s k_j^s / 2m^s) delta_sr
     + delta_ij omega^sr] delta(c_i^s, c_j^r)  (cpm: gamma^(s) n_i n_j, n = 1)."""
     n, t = g.n_nodes, g.n_slices
-    gam, omega = gammas(gamma, t), Fraction(omega)
+    gam = gammas(gamma, t)
     mats = slice_matrices(g)
     k = degrees(mats)
     twom = [sum(ks) for ks in k]
+    nw = node_weights(g, omega)
+    pres = presence(g)
     c = np.asarray(membership).reshape(t, n)
     total = Fraction(0)
     for i, j, s, r in product(range(n), range(n), range(t), range(t)):
@@ -129,9 +194,9 @@ def q_quadruple_sum(g, gamma, omega, membership, cpm=False):
         term = Fraction(0)
         if s == r:
             term += mats[s][i][j]
-            term -= null_term(gam, k, twom, s, i, j, cpm)
+            term -= null_term(gam, k, twom, s, i, j, cpm, nw)
         if i == j:
-            term += coupling(s, r, omega)
+            term += omega_sr(g, omega, i, s, r, pres)
         total += term
     return _over_two_mu(total, g, omega) 
 
@@ -140,22 +205,24 @@ def modularity_matrix(g, gamma, omega, cpm=False):
     """Supra-modularity matrix: per-slice A - gamma^(s) k k^T / 2m blocks (cpm: A - gamma^(s)
     J), omega couplings off-block."""
     n, t = g.n_nodes, g.n_slices
-    gam, omega = gammas(gamma, t), Fraction(omega)
+    gam = gammas(gamma, t)
     mats = slice_matrices(g)
     k = degrees(mats)
     twom = [sum(ks) for ks in k]
+    nw = node_weights(g, omega)
+    pres = presence(g)
     size = n * t
     M = [[Fraction(0)] * size for _ in range(size)]
     for s in range(t):
         for i in range(n):
             for j in range(n):
                 M[s * n + i][s * n + j] = Fraction(mats[s][i][j]) - null_term(gam, k, twom, s, i,
-                                                                               j, cpm)
+                                                                               j, cpm, nw)
     for s in range(t):
         for r in range(t):
             if s != r:
                 for i in range(n):
-                    M[s * n + i][r * n + i] += coupling(s, r, omega)
+                    M[s * n + i][r * n + i] += omega_sr(g, omega, i, s, r, pres)
     return M
 
 
@@ -180,10 +247,12 @@ def q_component_form(g, gamma, omega, membership, cpm=False):
     """Per-slice form: (sum_s [W_s - gamma^(s) SS_s / 2m_s] + omega I) / 2mu, where W_s is the
     intra weight inside communities (both directions), SS_s the sum over communities of
     the squared slice-s community degree (cpm: of the squared slice-s community size, and no
-    2m_s), and I the number of ordered consecutive-slice pairs (i, s), (i, s+-1) that share a
-    community.  Works on edge lists (no dense matrix)."""
+    2m_s), and omega I the coupling weight of the ordered copy pairs (i, s), (i, r) that share
+    a community.  Works on edge lists (no dense matrix)."""
     n, t = g.n_nodes, g.n_slices
-    gam, omega = gammas(gamma, t), Fraction(omega)
+    gam = gammas(gamma, t)
+    nw = node_weights(g, omega)
+    pres = presence(g)
     c = np.asarray(membership).reshape(t, n)
     num = Fraction(0)
     for s in range(t):
@@ -200,17 +269,18 @@ def q_component_form(g, gamma, omega, membership, cpm=False):
         tm = sum(kdeg)
         sig = {}
         for i in range(n):
-            sig[int(c[s][i])] = sig.get(int(c[s][i]), 0) + (1 if cpm else kdeg[i])
+            sig[int(c[s][i])] = sig.get(int(c[s][i]), 0) + (nw[s][i] if cpm else kdeg[i])
         SS = sum(v * v for v in sig.values())
         num += W
         if cpm:
             num -= gam[s] * SS
         elif tm:
             num -= gam[s] * SS / Fraction(tm)
-    I = 0
-    for s in range(t - 1):
-        I += 2 * int(np.sum(c[s] == c[s + 1]))
-    num += omega * I
+    for s in range(t):
+        for r in range(t):
+            for i in range(n):
+                if c[s][i] == c[r][i]:
+                    num += omega_sr(g, omega, i, s, r, pres)
     return _over_two_mu(num, g, omega)
 
 
@@ -316,11 +386,12 @@ def q_all_singletons(g, gamma, omega, cpm=False):
     mats = slice_matrices(g)
     k = degrees(mats)
     gam = gammas(gamma, g.n_slices)
+    nw = node_weights(g, omega)
     num = Fraction(0)
     for s in range(g.n_slices):
         tm = sum(k[s])
         if cpm:
-            num -= gam[s] * g.n_nodes
+            num -= gam[s] * sum(nw[s])
         elif tm:
             num -= gam[s] * sum(x * x for x in k[s]) / Fraction(tm)
     return _over_two_mu(num, g, omega)
@@ -331,10 +402,11 @@ def q_one_community(g, gamma, omega, cpm=False):
     (cpm: sum_s (2m_s - gamma^(s) N^2) in place of the first sum)."""
     mats = slice_matrices(g)
     gam = gammas(gamma, g.n_slices)
-    num = 2 * Fraction(omega) * g.n_nodes * (g.n_slices - 1)
+    nw = node_weights(g, omega)
+    num = two_mu(g, omega)
     for s, a in enumerate(mats):
         tm = sum(sum(row) for row in a)
-        num += tm - gam[s] * g.n_nodes ** 2 if cpm else (1 - gam[s]) * tm
+        num -= gam[s] * sum(nw[s]) ** 2 if cpm else gam[s] * tm
     return _over_two_mu(num, g, omega)
 
 
@@ -399,10 +471,13 @@ def supra_edges(g, omega):
             key = (min(a, b), max(a, b))
             acc[key] = acc.get(key, 0) + (1 if w is None else int(w[e]))
     out = [(a, b, Fraction(ww)) for (a, b), ww in acc.items()]
-    if Fraction(omega) != 0:
-        for s in range(t - 1):
+    pres = presence(g)
+    for s in range(t):
+        for r in range(s + 1, t):
             for i in range(n):
-                out.append((s * n + i, (s + 1) * n + i, Fraction(omega)))
+                c = omega_sr(g, omega, i, s, r, pres)
+                if c:
+                    out.append((s * n + i, r * n + i, c))
     return out
 
 

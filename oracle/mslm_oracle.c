@@ -7,7 +7,9 @@
  *
  * What it computes
  *   - The supra-graph of Eq. 3 (Section 3.1): per-snapshot adjacency on the diagonal, ordinal
- *     coupling omega between copies (i,s) and (i,s+1) of every node.
+ *     coupling omega between copies (i,s) and (i,s+1) of every node by default; in general
+ *     omega^(sr) = omega * c_sr for a given integer matrix c (Eq. 6), and optionally only
+ *     between copies present in both slices (a copy is present when it has an edge there).
  *   - Leiden optimisation (Section 3.2, citing Traag et al. 2019: local moving, refinement that
  *     keeps communities well connected, aggregation) of the multislice modularity Q_MS of Eq. 6
  *     with its per-slice null model gamma k_i^s k_j^s / 2m^s, made fully deterministic:
@@ -184,7 +186,21 @@ typedef struct orc_graph {
   int64_t twom[MAX_SLICES];    /* 2m_s, unscaled */
   level_t g0;
   int32_t *raw;                /* level-0 raw intra weight per entry, 0 for coupling entries */
+  int32_t cmat[MAX_SLICES * MAX_SLICES];   /* coupling multipliers c_sr (omega^(sr) = omega c_sr) */
+  int present_only;            /* coupling only between copies present in both slices */
+  char *present;               /* [N*T] copy (i,s) has an intra edge */
+  int64_t ctot;                /* sum of c_sr over the ordered coupled copy pairs */
 } orc_graph;
+
+/* The coupling multiplier of copies (i,s) and (i,r), 0 when they are not coupled. */
+static int64_t coupled(const orc_graph *g, int32_t i, int32_t s, int32_t r) {
+  if (s == r) return 0;
+  int64_t c = g->cmat[s * g->T + r];
+  if (c && g->present_only &&
+      !(g->present[(int64_t)s * g->N + i] && g->present[(int64_t)r * g->N + i]))
+    return 0;
+  return c;
+}
 
 static void level_free(level_t *g) {
   free(g->rp); free(g->col); free(g->w); free(g->pp); free(g->ps); free(g->pk);
@@ -201,51 +217,89 @@ static int ent_cmp(const void *x, const void *y) {
 
 static int64_t gcd64(int64_t x, int64_t y) { while (y) { int64_t t = x % y; x = y; y = t; } return x; }
 
+void orc_destroy(orc_graph *g);
+
+/* coupling: T*T multipliers c_sr >= 0 (symmetric, zero diagonal; NULL: 1 for |s-r| = 1, the
+ * ordinal coupling); present_only: coupling entries only between copies that have an edge in
+ * their slices. */
 int orc_create(int32_t N, int32_t T, const int64_t *off, const int32_t *src, const int32_t *dst,
-               const int32_t *w, int64_t omega_num, int64_t omega_den, orc_graph **out) {
+               const int32_t *w, int64_t omega_num, int64_t omega_den, const int32_t *coupling,
+               int32_t present_only, orc_graph **out) {
   *out = NULL;
   if (N < 1 || T < 1 || T > MAX_SLICES || omega_num < 0 || omega_den < 1) return ORC_EINVAL;
   if (omega_num >= ((int64_t)1 << 31) || omega_den >= ((int64_t)1 << 31)) return ORC_EOVERFLOW;
+  int32_t cm[MAX_SLICES * MAX_SLICES];
+  for (int s = 0; s < T; s++)
+    for (int r = 0; r < T; r++) {
+      int32_t c = coupling ? coupling[s * T + r] : (s - r == 1 || r - s == 1);
+      if (c < 0 || c >= (1 << 16) || (s == r && c != 0)) return ORC_EINVAL;
+      cm[s * T + r] = c;
+    }
+  for (int s = 0; s < T; s++)
+    for (int r = 0; r < T; r++) if (cm[s * T + r] != cm[r * T + s]) return ORC_EINVAL;
   int64_t gg = omega_num ? gcd64(omega_num, omega_den) : omega_den;
   int64_t a = omega_num / gg, b = omega_den / gg;
   int64_t E = off[T];
   int64_t n = (int64_t)N * T;
   if (n * 33 >= ((int64_t)1 << 32)) return ORC_EUNSUPPORTED;
-  int64_t ninter = a > 0 ? (int64_t)N * (T - 1) : 0;
+  char *present = calloc(n ? n : 1, 1);
+  for (int32_t s = 0; s < T; s++)
+    for (int64_t k = off[s]; k < off[s + 1]; k++)
+      if (src[k] >= 0 && src[k] < N && dst[k] >= 0 && dst[k] < N) {
+        present[(int64_t)s * N + src[k]] = 1;
+        present[(int64_t)s * N + dst[k]] = 1;
+      }
+  orc_graph tmp;
+  tmp.N = N; tmp.T = T; tmp.present_only = present_only != 0; tmp.present = present;
+  memcpy(tmp.cmat, cm, sizeof(cm));
+  int64_t ninter = 0, ctot = 0;
+  for (int32_t s = 0; s < T; s++)
+    for (int32_t r = 0; r < T; r++)
+      for (int32_t i = 0; i < N; i++) {
+        int64_t c = coupled(&tmp, i, s, r);
+        ctot += c;
+        if (c && s < r && a > 0) ninter++;
+      }
   int64_t cap = 2 * E + 2 * ninter;
   ent_t *e = malloc((cap ? cap : 1) * sizeof(ent_t));
-  if (!e) return ORC_ENOMEM;
+  if (!e) { free(present); return ORC_ENOMEM; }
   int64_t m = 0;
   for (int32_t s = 0; s < T; s++) {
     if (off[s] > off[s + 1]) { free(e); return ORC_EINVAL; }
     for (int64_t k = off[s]; k < off[s + 1]; k++) {
       int32_t u = src[k], x = dst[k], ww = w ? w[k] : 1;
-      if (u < 0 || u >= N || x < 0 || x >= N || u == x || ww < 1) { free(e); return ORC_EINVAL; }
+      if (u < 0 || u >= N || x < 0 || x >= N || u == x || ww < 1) { free(e); free(present); return ORC_EINVAL; }
       int64_t gu = (int64_t)s * N + u, gx = (int64_t)s * N + x;
       e[m++] = (ent_t){gu, (int32_t)gx, ww, 0};
       e[m++] = (ent_t){gx, (int32_t)gu, ww, 0};
     }
   }
+  /* coupling entries: ent_t.raw holds the multiplier c_sr, ent_t.inter marks them */
   if (a > 0)
-    for (int32_t s = 0; s + 1 < T; s++)
-      for (int32_t i = 0; i < N; i++) {
-        int64_t v = (int64_t)s * N + i, x = v + N;
-        e[m++] = (ent_t){v, (int32_t)x, 0, 1};
-        e[m++] = (ent_t){x, (int32_t)v, 0, 1};
-      }
+    for (int32_t s = 0; s < T; s++)
+      for (int32_t r = s + 1; r < T; r++)
+        for (int32_t i = 0; i < N; i++) {
+          int64_t c = coupled(&tmp, i, s, r);
+          if (!c) continue;
+          int64_t v = (int64_t)s * N + i, x = (int64_t)r * N + i;
+          e[m++] = (ent_t){v, (int32_t)x, (int32_t)c, 1};
+          e[m++] = (ent_t){x, (int32_t)v, (int32_t)c, 1};
+        }
   qsort(e, m, sizeof(ent_t), ent_cmp);
   /* merge repeated pairs (their weights add) */
   int64_t u = 0;
   for (int64_t k = 0; k < m; k++) {
     if (u > 0 && e[u - 1].row == e[k].row && e[u - 1].col == e[k].col) {
       int64_t s2 = (int64_t)e[u - 1].raw + e[k].raw;
-      if (s2 >= ((int64_t)1 << 31)) { free(e); return ORC_EOVERFLOW; }
+      if (s2 >= ((int64_t)1 << 31)) { free(e); free(present); return ORC_EOVERFLOW; }
       e[u - 1].raw = (int32_t)s2;
     } else e[u++] = e[k];
   }
   m = u;
   orc_graph *g = calloc(1, sizeof(orc_graph));
   g->N = N; g->T = T; g->a = a; g->b = b;
+  memcpy(g->cmat, cm, sizeof(cm));
+  g->present_only = present_only != 0; g->present = present; g->ctot = ctot;
   level_t *L = &g->g0;
   L->n = n; L->nnz = m;
   L->rp = calloc(n + 1, sizeof(int64_t)); L->col = malloc((m ? m : 1) * sizeof(int32_t));
@@ -254,7 +308,7 @@ int orc_create(int32_t N, int32_t T, const int64_t *off, const int32_t *src, con
   for (int64_t k = 0; k < m; k++) {
     L->rp[e[k].row + 1]++;
     L->col[k] = e[k].col;
-    L->w[k] = e[k].inter ? a : b * (int64_t)e[k].raw;
+    L->w[k] = e[k].inter ? a * (int64_t)e[k].raw : b * (int64_t)e[k].raw;
     g->raw[k] = e[k].inter ? 0 : e[k].raw;
     if (!e[k].inter) kdeg[e[k].row] += e[k].raw;
   }
@@ -263,7 +317,7 @@ int orc_create(int32_t N, int32_t T, const int64_t *off, const int32_t *src, con
   for (int32_t s = 0; s < T; s++) {
     int64_t t2 = 0;
     for (int32_t i = 0; i < N; i++) t2 += kdeg[(int64_t)s * N + i];
-    if (t2 >= ((int64_t)1 << 31)) { free(kdeg); /* leak-free enough for an error path */ return ORC_EOVERFLOW; }
+    if (t2 >= ((int64_t)1 << 31)) { free(kdeg); orc_destroy(g); return ORC_EOVERFLOW; }
     g->twom[s] = t2;
   }
   int64_t np = 0;
@@ -282,10 +336,12 @@ int orc_create(int32_t N, int32_t T, const int64_t *off, const int32_t *src, con
 
 void orc_destroy(orc_graph *g) {
   if (!g) return;
-  level_free(&g->g0); free(g->raw); free(g);
+  level_free(&g->g0); free(g->raw); free(g->present); free(g);
 }
 
 int64_t orc_nnz(const orc_graph *g) { return g->g0.nnz; }
+/* sum over ordered coupled copy pairs of c_sr: 2mu = sum_s 2m_s + omega * this */
+int64_t orc_coupling_total(const orc_graph *g) { return g->ctot; }
 void orc_csr(const orc_graph *g, int64_t *rp, int32_t *col, int64_t *w, int32_t *raw, int64_t *twom) {
   memcpy(rp, g->g0.rp, (g->g0.n + 1) * sizeof(int64_t));
   memcpy(col, g->g0.col, g->g0.nnz * sizeof(int32_t));
@@ -835,7 +891,7 @@ static int64_t split_components(const level_t *g0, const uint32_t *Pf, int32_t *
 /* ------------------------------------------------------------------ Q components */
 /* comps[0..T-1] = W_s (intra weight inside communities, both directions, unscaled),
  * comps[T..2T-1] = SS_s = sum_C Sigma_{C,s}^2, comps[2T..3T-1] = 2m_s,
- * comps[3T] = I = ordered consecutive-slice copy pairs sharing a community. */
+ * comps[3T] = I = sum of c_sr over the ordered coupled copy pairs sharing a community. */
 int orc_q_components(const orc_graph *G, const int32_t *memb, int64_t *comps) {
   int32_t N = G->N, T = G->T;
   const level_t *g = &G->g0;
@@ -855,9 +911,10 @@ int orc_q_components(const orc_graph *G, const int32_t *memb, int64_t *comps) {
   map_free(&sig);
   for (int32_t s = 0; s < T; s++) comps[2 * T + s] = G->twom[s];
   int64_t I = 0;
-  for (int32_t s = 0; s + 1 < T; s++)
-    for (int32_t i = 0; i < N; i++)
-      if (memb[(int64_t)s * N + i] == memb[(int64_t)(s + 1) * N + i]) I += 2;
+  for (int32_t s = 0; s < T; s++)
+    for (int32_t r = 0; r < T; r++)
+      for (int32_t i = 0; i < N; i++)
+        if (memb[(int64_t)s * N + i] == memb[(int64_t)r * N + i]) I += coupled(G, i, s, r);
   comps[3 * T] = I;
   return ORC_OK;
 }
@@ -866,6 +923,12 @@ int orc_q_components(const orc_graph *G, const int32_t *memb, int64_t *comps) {
  * communities of the squared scaled supra-degree sum (sum_C (sum_{v in C} kappa'_v)^2, with
  * kappa' = b * (intra degree) + a * (coupling count)), comps[T+1..2T-1] = 0, comps[2T..3T-1] =
  * 2m_s, comps[3T] = I. */
+/* CPM node weight of supra-node v: 1, or 0 for a copy without edges when only present copies
+ * are supra-nodes (they are then left out of the graph entirely). */
+static int cpm_weight(const orc_graph *G, int64_t v) {
+  return !G->present_only || G->present[v];
+}
+
 /* Components of the multislice CPM (node weight 1 per supra-node): as orc_q_components with
  * comps[T..2T-1] = sum over communities of the squared number of their supra-nodes in slice s. */
 int orc_q_components_cpm(const orc_graph *G, const int32_t *memb, int64_t *comps) {
@@ -873,7 +936,8 @@ int orc_q_components_cpm(const orc_graph *G, const int32_t *memb, int64_t *comps
   const level_t *g = &G->g0;
   orc_q_components(G, memb, comps);
   map_t sig; map_init(&sig, g->n);
-  for (int64_t v = 0; v < g->n; v++) map_add(&sig, (uint32_t)memb[v], (int32_t)(v / N), 1);
+  for (int64_t v = 0; v < g->n; v++)
+    if (cpm_weight(G, v)) map_add(&sig, (uint32_t)memb[v], (int32_t)(v / N), 1);
   for (int32_t s = T; s < 2 * T; s++) comps[s] = 0;
   for (uint64_t h = 0; h < sig.cap; h++) if (sig.key[h] != MAP_EMPTY) {
     int32_t s = (int32_t)(sig.key[h] & 0xff);
@@ -941,13 +1005,16 @@ static level_t global_level(const level_t *g0, int64_t *two_mu) {
  * Eq. 6): the null term gamma^(s) k_i k_j / 2m_s of Eq. 6 becomes gamma^(s) n_i n_j with node
  * weight n = 1 per supra-node, so every supra-node's profile is the single entry (its slice, 1)
  * and every slice's denominator is 1. */
-static level_t cpm_level(const level_t *g0, int32_t N) {
-  level_t g; level_copy(g0, &g);
+static level_t cpm_level(const orc_graph *G) {
+  level_t g; level_copy(&G->g0, &g);
   free(g.pp); free(g.ps); free(g.pk);
-  int64_t n = g.n;
+  int64_t n = g.n, q = 0;
   g.pp = calloc(n + 1, sizeof(int64_t)); g.ps = malloc((n ? n : 1) * sizeof(int32_t));
   g.pk = malloc((n ? n : 1) * sizeof(int64_t));
-  for (int64_t v = 0; v < n; v++) { g.ps[v] = (int32_t)(v / N); g.pk[v] = 1; g.pp[v + 1] = v + 1; }
+  for (int64_t v = 0; v < n; v++) {
+    if (cpm_weight(G, v)) { g.ps[q] = (int32_t)(v / G->N); g.pk[q] = 1; q++; }
+    g.pp[v + 1] = q;
+  }
   return g;
 }
 
@@ -993,7 +1060,7 @@ int orc_leiden(const orc_graph *G, int64_t gamma_num, int64_t gamma_den,
     cx.cf.b = 1;
     base = &gglob;
   } else if (null_model == 2) {
-    gglob = cpm_level(&G->g0, G->N);
+    gglob = cpm_level(G);
     base = &gglob;
   }
   if (max_sweeps <= 0) max_sweeps = DEFAULT_SWEEPS;

@@ -73,12 +73,15 @@ def hash_priority(seed: int, it: int, lvl: int, phase: int, u: int) -> int:
 # --------------------------------------------------------------------------- the supra-graph
 
 class SupraGraph:
-    """Level-0 supra-graph of Eq. 3 with ordinal coupling omega; supra-node v = s*N + i."""
+    """Level-0 supra-graph of Eq. 3; supra-node v = s*N + i.  Coupling omega^(sr) = omega *
+    c_sr between (i, s) and (i, r): c ordinal (1 for |s - r| = 1) unless a T x T integer matrix
+    is given; present_only: only between copies that have an edge in their slices."""
 
-    def __init__(self, g, omega):
+    def __init__(self, g, omega, coupling=None, present_only=False):
         self.N, self.T = g.n_nodes, g.n_slices
         self.n = self.N * self.T
         self.omega = Fraction(omega)
+        self.present_only = bool(present_only)
         nbr = [dict() for _ in range(self.n)]          # v -> {x: weight (Fraction)}
         intra = [dict() for _ in range(self.n)]        # raw intra weights only
         for s in range(self.T):
@@ -91,12 +94,28 @@ class SupraGraph:
         for v in range(self.n):
             for x, ww in intra[v].items():
                 nbr[v][x] = Fraction(ww)
-        if self.omega != 0:
-            for s in range(self.T - 1):
+        self.present = [bool(intra[v]) for v in range(self.n)]
+
+        def c_of(s, r):
+            if coupling is None:
+                return 1 if abs(s - r) == 1 else 0
+            return int(coupling[s][r]) if s != r else 0
+
+        mult = {}                                          # (v, x) -> c_sr of a coupled pair
+        for s in range(self.T):
+            for r in range(self.T):
+                c = c_of(s, r)
+                if not c:
+                    continue
                 for i in range(self.N):
-                    a, b = s * self.N + i, (s + 1) * self.N + i
-                    nbr[a][b] = self.omega
-                    nbr[b][a] = self.omega
+                    a, b = s * self.N + i, r * self.N + i
+                    if self.present_only and not (self.present[a] and self.present[b]):
+                        continue
+                    mult[(a, b)] = c
+        self.mult = mult
+        if self.omega != 0:
+            for (a, b), c in mult.items():
+                nbr[a][b] = self.omega * c
         self.nbr = nbr
         self.intra = intra
         self.slice = [v // self.N for v in range(self.n)]
@@ -104,7 +123,8 @@ class SupraGraph:
         self.two_m = [sum(self.k[s * self.N:(s + 1) * self.N]) for s in range(self.T)]
         # directed entries for the integer score
         self.intra_entries = [(v, x, ww) for v in range(self.n) for x, ww in intra[v].items()]
-        self.inter_entries = [(v, x) for v in range(self.n) for x in nbr[v] if x not in intra[v]]
+        self.inter_entries = [(v, x, mult[(v, x)]) for v in range(self.n) for x in nbr[v]
+                              if x not in intra[v]]
 
 
 class GlobalScore:
@@ -120,7 +140,7 @@ class GlobalScore:
         self.p, self.q = gamma.numerator, gamma.denominator
         a, b = G.omega.numerator, G.omega.denominator
         self.a, self.b = a, b
-        self.kap = [b * G.k[v] + a * sum(1 for x in G.nbr[v] if x not in G.intra[v])
+        self.kap = [b * G.k[v] + a * sum(c for (u, x, c) in G.inter_entries if u == v)
                     for v in range(G.n)]
         self.two_mu = sum(self.kap)
 
@@ -130,9 +150,9 @@ class GlobalScore:
         for v, x, ww in G.intra_entries:
             if lab[v] == lab[x]:
                 W += self.b * ww
-        for v, x in G.inter_entries:
+        for v, x, c in G.inter_entries:
             if lab[v] == lab[x]:
-                W += self.a
+                W += self.a * c
         sig = {}
         for v in range(G.n):
             sig[lab[v]] = sig.get(lab[v], 0) + self.kap[v]
@@ -152,8 +172,11 @@ def per_slice(gamma, T):
 
 def null_weight(G, v, cpm):
     """The weight a supra-node carries into its slice's null term: its intra degree k_{i,s}
-    (Eq. 6), or 1 under the multislice CPM."""
-    return 1 if cpm else G.k[v]
+    (Eq. 6), or 1 under the multislice CPM (0 for an absent copy when only present copies
+    are coupled: it is then not a supra-node)."""
+    if cpm:
+        return 0 if (G.present_only and not G.present[v]) else 1
+    return G.k[v]
 
 
 class Score:
@@ -185,9 +208,9 @@ class Score:
         for v, x, ww in G.intra_entries:
             if lab[v] == lab[x]:
                 total += self.L * ww
-        for v, x in G.inter_entries:
+        for v, x, c in G.inter_entries:
             if lab[v] == lab[x]:
-                total += self.c_inter
+                total += self.c_inter * c
         sig = {}
         for v in range(G.n):
             x = null_weight(G, v, self.cpm)
@@ -200,7 +223,7 @@ class Score:
 
     def q(self, lab) -> Fraction:
         G = self.G
-        two_mu = sum(G.two_m) + 2 * G.omega * G.N * (G.T - 1)
+        two_mu = sum(G.two_m) + G.omega * sum(G.mult.values())
         return Fraction(self(lab), self.L) / two_mu if two_mu else Fraction(0)
 
 
@@ -418,14 +441,14 @@ def split_components(G, flat):
 
 
 def leiden(g, gamma=1, omega=1, max_levels=32, max_iterations=2, max_sweeps=0, seed=0,
-           null_model=0, gamma_slices=None, initial=None):
+           null_model=0, gamma_slices=None, initial=None, coupling=None, present_only=False):
     """Run the schedule; returns (membership, stats, trace).  trace holds one record per
     level: colour, labels at the level's start (p_in), after local moving (p_lm), R, and the
     refined sub-communities (founder -> level-0 members) with their well-connectedness.
     null_model 0 optimises Q_MS of Eq. 6; 1 the global modularity of the supra-graph; 2 the
     multislice CPM.  gamma_slices: T per-slice resolutions in place of gamma; initial: the
     first iteration's start partition."""
-    G = SupraGraph(g, omega)
+    G = SupraGraph(g, omega, coupling, present_only)
     if gamma_slices is not None:
         assert null_model != 1
         gamma = [Fraction(x) for x in gamma_slices]

@@ -19,7 +19,9 @@ struct orc_stats {
   int32_t levels_run, iterations_run, n_communities, colours_first;
 };
 int orc_create(int32_t N, int32_t T, const int64_t *off, const int32_t *src, const int32_t *dst,
-               const int32_t *w, int64_t omega_num, int64_t omega_den, orc_graph **out);
+               const int32_t *w, int64_t omega_num, int64_t omega_den, const int32_t *coupling,
+               int32_t present_only, orc_graph **out);
+int64_t orc_coupling_total(const orc_graph *g);
 void orc_destroy(orc_graph *g);
 int64_t orc_nnz(const orc_graph *g);
 void orc_csr(const orc_graph *g, int64_t *rp, int32_t *col, int64_t *w, int32_t *raw, int64_t *twom);
@@ -212,12 +214,17 @@ void oracle_runs() {
     const bool weighted = rep % 2 == 0;
     orc_graph *og = nullptr;
     const int64_t on = pick(0, 3), od = pick(1, 4);
+    // every third graph with a general coupling matrix, every other with present-only copies
+    std::vector<int32_t> cm(T * T, 0);
+    for (int s = 0; s < T; s++)
+      for (int r = s + 1; r < T; r++) cm[s * T + r] = cm[r * T + s] = (int32_t)pick(0, 3);
     if (orc_create(N, T, g.off.data(), g.src.data(), g.dst.data(), weighted ? g.w.data() : nullptr,
-                   on, od, &og) != 0) {
+                   on, od, rep % 3 == 1 ? cm.data() : nullptr, rep % 2, &og) != 0) {
       expect(false, "oracle create");
       continue;
     }
     const int64_t n = (int64_t)N * T, m = orc_nnz(og);
+    expect(orc_coupling_total(og) >= 0, "coupling total");
     std::vector<int64_t> rp(n + 1), w(m > 0 ? m : 1), twom(T);
     std::vector<int32_t> col(m > 0 ? m : 1), raw(m > 0 ? m : 1);
     orc_csr(og, rp.data(), col.data(), w.data(), raw.data(), twom.data());

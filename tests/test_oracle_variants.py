@@ -202,8 +202,8 @@ VARIANT_MUTATIONS = [
      "out->small = (i128)cf->gq[0] * cf->S[s] * W - (i128)(cf->gp[0] * cf->b) * ((i128)pk[0] * y[0]);"),
     ("resolution numerator dropped on multi-slice units",
      "bn_mul_u64(&t1, (uint64_t)cf->gp[s]);", ""),
-    ("CPM node weight 2", "g.ps[v] = (int32_t)(v / N); g.pk[v] = 1;",
-     "g.ps[v] = (int32_t)(v / N); g.pk[v] = 2;"),
+    ("CPM node weight 2", "g.ps[q] = (int32_t)(v / G->N); g.pk[q] = 1; q++;",
+     "g.ps[q] = (int32_t)(v / G->N); g.pk[q] = 2; q++;"),
     ("CPM keeps 2m_s", "S[s] = null_model == 2 ? 1 : (G->twom[s] > 0 ? G->twom[s] : 1);",
      "S[s] = G->twom[s] > 0 ? G->twom[s] : 1;"),
     ("start partition not canonical",
