@@ -41,7 +41,8 @@ typedef enum {
 typedef struct mslm_graph mslm_graph;   /* owns the device supra-CSR of one temporal graph */
 typedef struct mslm_server mslm_server; /* continuous-batching request loop               */
 
-enum { MSLM_INPUT_ON_DEVICE = 1u, MSLM_OUTPUT_ON_DEVICE = 2u, MSLM_PROFILE = 4u, MSLM_COUNT = 8u };
+enum { MSLM_INPUT_ON_DEVICE = 1u, MSLM_OUTPUT_ON_DEVICE = 2u, MSLM_PROFILE = 4u, MSLM_COUNT = 8u,
+       MSLM_COUPLE_PRESENT = 16u };
 
 /* The objective a solve maximises.  MULTISLICE: Q_MS of Eq. 6, a null model per snapshot
  * (gamma^(s) k_i^s k_j^s / 2m_s).  GLOBAL: the modularity of Eq. 5 over the whole supra-graph
@@ -57,7 +58,16 @@ enum { MSLM_NULL_MULTISLICE = 0, MSLM_NULL_GLOBAL = 1, MSLM_NULL_CPM = 2 };
  * no self-loops, weight >= 1 (NULL = unit weights).  Repeated pairs inside a slice add
  * their weights.  slice_offsets is always host memory; src/dst/weight are device
  * pointers when flags has MSLM_INPUT_ON_DEVICE.  Limits: 1 <= T <= 64, N >= 1,
- * N*T*33 < 2^32, every slice's total degree 2m_s < 2^31. */
+ * N*T*33 < 2^32, every slice's total degree 2m_s < 2^31.
+ * Coupling (Eq. 6's omega^(sr)): coupling (host, NULL = ordinal) is a T*T row-major matrix of
+ * integers c_sr in [0, 2^16), symmetric with a zero diagonal; copies (i,s) and (i,r) are
+ * coupled with weight omega^(sr) = omega * c_sr (the ordinal coupling of Eq. 3 is c_sr = 1 for
+ * |s - r| = 1; categorical coupling is c_sr = 1 for all s != r).  With MSLM_COUPLE_PRESENT in
+ * flags only copies present in both slices are coupled, a copy being present when it has an
+ * edge in its slice (the supra-graph of data whose nodes are absent from some snapshots);
+ * under the CPM an absent copy then carries node weight 0.  2mu = sum_s 2m_s + omega * C with
+ * C the coupling total (sum of c_sr over ordered coupled copy pairs; 2N(T-1) for the ordinal
+ * coupling of every copy), reported in mslm_result.coupling_total. */
 typedef struct {
   int32_t n_nodes;
   int32_t n_slices;
@@ -67,6 +77,7 @@ typedef struct {
   const int32_t *weight;
   int64_t omega_num, omega_den;   /* default coupling omega = num/den, num >= 0, den >= 1 */
   uint32_t flags;
+  const int32_t *coupling;
 } mslm_graph_desc;
 
 /* One solve.  gamma = gamma_num/gamma_den (num >= 0, den >= 1).  omega_den == 0 keeps the
@@ -105,7 +116,8 @@ typedef struct {
 /* Per-solve outcome.  q_components (3T+1 int64) are the exact integer pieces of Q:
  * W_s (weight inside communities in slice s, both directions), SS_s (sum over communities
  * of the squared slice-s degree; for the CPM of the squared slice-s supra-node count), 2m_s,
- * and I (ordered coupled copy pairs sharing a community); mslm_q_exact (mslm_q_exact_variant
+ * and I (sum of c_sr over the ordered coupled copy pairs sharing a community: their count for
+ * the ordinal coupling); mslm_q_exact (mslm_q_exact_variant
  * for per-slice resolutions and the CPM) turns them into the reduced fraction Q.  For the GLOBAL null model
  * the T slots of SS hold one value, SS' = sum over communities of (sum of kappa')^2 with
  * kappa' = b * (intra degree) + a * (coupling count), then zeros; mslm_q_exact_global reduces
@@ -128,10 +140,12 @@ typedef struct {
   double lm0_kernel_ms;           /* level-0 decision kernel time (MSLM_PROFILE)              */
   int64_t lm0_launches;           /* level-0 decision launches (MSLM_PROFILE)                 */
   int64_t lm0_units, lm0_entries, lm0_candidates;   /* level-0 share of the work (COUNT)   */
+  int64_t coupling_total;         /* the graph's coupling total C (2mu = sum 2m_s + omega C)  */
 } mslm_result;
 
 /* Build the device supra-CSR (Eq. 3) of a temporal graph: both directions of every intra
- * edge with repeated pairs summed, plus the coupling entries (i,s)<->(i,s+1) for all i.
+ * edge with repeated pairs summed, plus the coupling entries (i,s)<->(i,r) of every coupled
+ * pair of copies (for the ordinal coupling (i,s)<->(i,s+1) for all i).
  * *out is NULL on failure.  Errors: EINVAL (ids, self-loops, weights, sizes), EOVERFLOW
  * (2m_s >= 2^31), EUNSUPPORTED (T > 64 or N*T too large), ENOMEM, EHIP. */
 mslm_status mslm_create(const mslm_graph_desc *desc, void *hip_stream, mslm_graph **out);
@@ -166,14 +180,15 @@ mslm_status mslm_q_exact_global(const int64_t *q_components, int32_t n_slices, i
 /* Exact value of any objective from a solve's 3T+1 components: null_model MULTISLICE (Eq. 6,
  * as mslm_q_exact), GLOBAL (as mslm_q_exact_global) or CPM, whose SS_s slots hold the sum over
  * communities of the squared number of their slice-s supra-nodes:
- *   Q = (sum_s [W_s - gamma^(s) SS_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1)).
+ *   Q = (sum_s [W_s - gamma^(s) SS_s] + omega I) / (sum_s 2m_s + omega C).
  * gamma_slices as in mslm_params (NULL: gamma_num/gamma_den in every slice; not with GLOBAL).
- * Errors: EINVAL. */
+ * coupling_total: the graph's C (mslm_result.coupling_total); < 0 means 2N(T-1), the ordinal
+ * coupling of every copy that mslm_q_exact and mslm_q_exact_global assume.  Errors: EINVAL. */
 mslm_status mslm_q_exact_variant(const int64_t *q_components, int32_t n_slices, int32_t n_nodes,
                                  int32_t null_model, const int64_t *gamma_slices,
                                  int64_t gamma_num, int64_t gamma_den, int64_t omega_num,
-                                 int64_t omega_den, char *num, size_t num_cap, char *den,
-                                 size_t den_cap);
+                                 int64_t omega_den, int64_t coupling_total, char *num,
+                                 size_t num_cap, char *den, size_t den_cap);
 
 /* Execution choices that change the speed of a solve and never its result (the same
  * memberships, Q components and statistics for every value).  Each graph handle holds one;

@@ -20,8 +20,9 @@ namespace mslm {
 void api_finish(const GraphDev &g, const SolveSpec &sp, SolveOut &o, mslm_result *res) {
   std::string a, b;
   double qd = 0;
-  api_q_exact_spec(o.res.q_components, g.T, g.N, sp, a, b, qd);
+  api_q_exact_spec(o.res.q_components, g.T, g.N, g.ctot, sp, a, b, qd);
   o.res.q = qd;
+  o.res.coupling_total = g.ctot;
   if (res) *res = o.res;
 }
 }  // namespace mslm
@@ -122,7 +123,8 @@ mslm_status mslm_q_exact_global(const int64_t *qc, int32_t T, int32_t N, int64_t
   int64_t go = omega_num ? api_gcd(omega_num, omega_den) : omega_den;
   std::string a, b;
   double qd;
-  api_q_exact_global(qc, T, N, gamma_num / gg, gamma_den / gg, omega_num / go, omega_den / go, a, b, qd);
+  api_q_exact_global(qc, T, N, 2 * (int64_t)N * (T - 1), gamma_num / gg, gamma_den / gg,
+                     omega_num / go, omega_den / go, a, b, qd);
   if (a.size() + 1 > num_cap || b.size() + 1 > den_cap) return fail(MSLM_EINVAL, "buffer too small");
   memcpy(num, a.c_str(), a.size() + 1);
   memcpy(den, b.c_str(), b.size() + 1);
@@ -132,11 +134,27 @@ mslm_status mslm_q_exact_global(const int64_t *qc, int32_t T, int32_t N, int64_t
 mslm_status mslm_q_exact_variant(const int64_t *qc, int32_t T, int32_t N, int32_t null_model,
                                  const int64_t *gamma_slices, int64_t gamma_num,
                                  int64_t gamma_den, int64_t omega_num, int64_t omega_den,
-                                 char *num, size_t num_cap, char *den, size_t den_cap) {
+                                 int64_t coupling_total, char *num, size_t num_cap, char *den,
+                                 size_t den_cap) {
   if (!qc || !num || !den || T < 1 || T > 64 || N < 1) return fail(MSLM_EINVAL, "bad arguments");
-  if (null_model == MSLM_NULL_GLOBAL && !gamma_slices)
-    return mslm_q_exact_global(qc, T, N, gamma_num, gamma_den, omega_num, omega_den, num,
-                               num_cap, den, den_cap);
+  const int64_t ctot = coupling_total < 0 ? 2 * (int64_t)N * (T - 1) : coupling_total;
+  if (null_model == MSLM_NULL_GLOBAL && !gamma_slices) {
+    mslm_status s = api_check_fraction(gamma_num, gamma_den, "gamma");
+    if (s != MSLM_OK) return s;
+    s = api_check_fraction(omega_num, omega_den, "omega");
+    if (s != MSLM_OK) return s;
+    int64_t gg = gamma_num ? api_gcd(gamma_num, gamma_den) : gamma_den;
+    int64_t go = omega_num ? api_gcd(omega_num, omega_den) : omega_den;
+    std::string a, b;
+    double qd;
+    api_q_exact_global(qc, T, N, ctot, gamma_num / gg, gamma_den / gg, omega_num / go,
+                       omega_den / go, a, b, qd);
+    if (a.size() + 1 > num_cap || b.size() + 1 > den_cap)
+      return fail(MSLM_EINVAL, "buffer too small");
+    memcpy(num, a.c_str(), a.size() + 1);
+    memcpy(den, b.c_str(), b.size() + 1);
+    return MSLM_OK;
+  }
   if (null_model != MSLM_NULL_MULTISLICE && null_model != MSLM_NULL_CPM)
     return fail(MSLM_EINVAL, "null_model: one resolution for the global null model, else "
                              "MSLM_NULL_MULTISLICE or MSLM_NULL_CPM");
@@ -155,7 +173,7 @@ mslm_status mslm_q_exact_variant(const int64_t *qc, int32_t T, int32_t N, int32_
   int64_t go = omega_num ? api_gcd(omega_num, omega_den) : omega_den;
   std::string a, b;
   double qd;
-  api_q_exact_slices(qc, T, N, gn.data(), gd.data(), null_model == MSLM_NULL_CPM,
+  api_q_exact_slices(qc, T, N, ctot, gn.data(), gd.data(), null_model == MSLM_NULL_CPM,
                      omega_num / go, omega_den / go, a, b, qd);
   if (a.size() + 1 > num_cap || b.size() + 1 > den_cap) return fail(MSLM_EINVAL, "buffer too small");
   memcpy(num, a.c_str(), a.size() + 1);

@@ -104,6 +104,7 @@ struct Workspace {
   Buf qW, qSS, qI, ranges_lo, ranges_hi, ranges_off;
   Buf sm_maxsw, sm_stat, sm_nz, sm_start;
   Buf b_src, b_dst, b_w, b_off, b_twom;   // graph build inputs and per-slice sums
+  Buf b_pairs, b_present;                 // coupled slice pairs, present copies (build)
   Buf hubpart;                            // per-block best candidates of hub units
   Buf jph0, jph1;                         // heavy frontier lists of the colouring
   Buf sig_count;                          // profile entries per slice of a level
@@ -140,7 +141,7 @@ void workspace_free(Workspace *ws) {
 void workspace_release_build(Workspace *ws) {
   if (!ws) return;
   for (Buf *b : {&ws->b_src, &ws->b_dst, &ws->b_w, &ws->akeys, &ws->akeys2, &ws->avals,
-                 &ws->avals2, &ws->temp})
+                 &ws->avals2, &ws->temp, &ws->b_pairs, &ws->b_present})
     b->release();
 }
 
@@ -183,16 +184,56 @@ __global__ void k_build_intra(const int32_t *src, const int32_t *dst, const int3
   vals[2 * e + 1] = ww;
 }
 
-// coupling entries (i,s)<->(i,s+1) for every node i, raw weight 0 (scaled by a at use)
-__global__ void k_build_inter(int32_t N, int32_t T, int shift, uint64_t *keys, int64_t *vals) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t m = (int64_t)N * (T - 1);
-  if (i >= m) return;
-  uint64_t v = (uint64_t)i, x = (uint64_t)(i + N);
-  keys[2 * i] = (v << shift) | x;
-  vals[2 * i] = 0;
-  keys[2 * i + 1] = (x << shift) | v;
-  vals[2 * i + 1] = 0;
+// copies with an intra edge (present): both ends of every edge of a slice
+__global__ void k_mark_present(const int32_t *src, const int32_t *dst, const int64_t *off,
+                               int32_t T, int32_t N, int64_t E, uint8_t *present) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  int lo = 0, hi = T;   // off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid;
+  }
+  present[(int64_t)lo * N + src[e]] = 1;
+  present[(int64_t)lo * N + dst[e]] = 1;
+}
+
+// coupling entries (i,s)<->(i,r) of the coupled slice pairs p = (ps[p], pr[p], c[p]), raw weight
+// c_sr (scaled by a at use); with `present`, a pair of copies not both present gets the key
+// all-ones in the sort's 2*shift bits (never an entry: it would be a self-loop), which sorts
+// last and is dropped
+__global__ void k_build_inter(int32_t N, int64_t P, const int32_t *ps, const int32_t *pr,
+                              const int32_t *pc, const uint8_t *present, int shift,
+                              uint64_t *keys, int64_t *vals) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * P) return;
+  const int64_t p = t / N, i = t - p * N;
+  uint64_t v = (uint64_t)((int64_t)ps[p] * N + i), x = (uint64_t)((int64_t)pr[p] * N + i);
+  int64_t c = pc[p];
+  if (present && !(present[v] && present[x])) {
+    v = x = (1ull << shift) - 1;
+    c = 0;
+  }
+  keys[2 * t] = (v << shift) | x;
+  vals[2 * t] = c;
+  keys[2 * t + 1] = (x << shift) | v;
+  vals[2 * t + 1] = c;
+}
+
+// coupling total: sum of the raw coupling weights over all entries (both directions)
+__global__ void k_coupling_total(const int64_t *rp, const int32_t *col, const int32_t *w,
+                                 int64_t n, int32_t N, unsigned long long *out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long t = 0;
+  if (v < n) {
+    const int64_t lo = (v / N) * N, hi = lo + N;
+    for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+      const int32_t x = col[e];
+      if (x < lo || x >= hi) t += (unsigned long long)w[e];
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+  if ((threadIdx.x & 63) == 0 && t) atomicAdd(out, t);
 }
 
 __global__ void k_build_csr(const uint64_t *keys, const int64_t *vals, int64_t m, int shift,
@@ -275,12 +316,26 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   const int32_t N = d.n_nodes, T = d.n_slices;
   const int64_t E = d.slice_offsets[T];
   const int64_t n = (int64_t)N * T;
-  const int64_t ninter = (int64_t)N * (T - 1);
+  // the coupled slice pairs (s < r, c_sr > 0) of the coupling matrix
+  const std::vector<int32_t> cm = api_coupling_matrix(&d);
+  std::vector<int32_t> hps, hpr, hpc;
+  for (int s = 0; s < T; s++)
+    for (int r = s + 1; r < T; r++)
+      if (cm[(size_t)s * T + r]) {
+        hps.push_back(s);
+        hpr.push_back(r);
+        hpc.push_back(cm[(size_t)s * T + r]);
+      }
+  const int64_t P = (int64_t)hps.size();
+  const int64_t ninter = (int64_t)N * P;
   const int64_t mraw = 2 * E + 2 * ninter;
   const bool on_dev = d.flags & MSLM_INPUT_ON_DEVICE;
+  const bool present_only = d.flags & MSLM_COUPLE_PRESENT;
   g.N = N;
   g.T = T;
   g.n = n;
+  g.crow = api_coupling_rows(cm, T);
+  g.present_only = present_only;
   // edge lists on the device (workspace buffers: repeated builds allocate nothing new)
   const int32_t *src = d.src, *dst = d.dst, *w = d.weight;
   if (!on_dev) {
@@ -309,7 +364,20 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   uint64_t *k1 = ws->akeys.get<uint64_t>(mraw);
   int64_t *v1 = ws->avals.get<int64_t>(mraw);
   if (E > 0) k_build_intra<<<nblk(E), kBS, 0, st>>>(src, dst, w, off, T, N, E, shift, k1, v1);
-  if (ninter > 0) k_build_inter<<<nblk(ninter), kBS, 0, st>>>(N, T, shift, k1 + 2 * E, v1 + 2 * E);
+  if (ninter > 0) {
+    int32_t *dp = ws->b_pairs.get<int32_t>(3 * P);
+    h2d(dp, hps.data(), P, st);
+    h2d(dp + P, hpr.data(), P, st);
+    h2d(dp + 2 * P, hpc.data(), P, st);
+    uint8_t *pres = nullptr;
+    if (present_only) {
+      pres = ws->b_present.get<uint8_t>(n);
+      MSLM_HIP(hipMemsetAsync(pres, 0, n, st));
+      if (E > 0) k_mark_present<<<nblk(E), kBS, 0, st>>>(src, dst, off, T, N, E, pres);
+    }
+    k_build_inter<<<nblk(ninter), kBS, 0, st>>>(N, P, dp, dp + P, dp + 2 * P, pres, shift,
+                                                k1 + 2 * E, v1 + 2 * E);
+  }
   uint64_t *k2 = ws->akeys2.get<uint64_t>(mraw);
   int64_t *v2 = ws->avals2.get<int64_t>(mraw);
   MSLM_PRIM(sort_pairs_u64_i64(k1, k2, v1, v2, mraw, 2 * shift, st, temp_alloc(ws)));
@@ -318,6 +386,13 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   int64_t m = 0;
   d2h(&m, dn, 1, st);
   MSLM_HIP(hipStreamSynchronize(st));
+  if (present_only && m > 0) {   // the dropped pairs' key sorts last
+    uint64_t last = 0;
+    d2h(&last, k1 + m - 1, 1, st);
+    MSLM_HIP(hipStreamSynchronize(st));
+    const uint64_t drop = (2 * shift >= 64) ? ~0ull : ((1ull << (2 * shift)) - 1);
+    if (last == drop) m--;
+  }
   g.nnz = m;
   int32_t *col = g.col.get<int32_t>(m);
   int32_t *wv = g.w.get<int32_t>(m);
@@ -335,11 +410,17 @@ void build_graph(GraphDev &g, const mslm_graph_desc &d, hipStream_t st, Workspac
   MSLM_HIP(hipMemsetAsync(twom, 0, sizeof(int64_t) * 2 * T, st));
   k_build_degree<<<nblk(n), kBS, 0, st>>>(rp, col, wv, n, N, kd, twom, twom + T);
   k_max_degree<<<nblk(n), kBS, 0, st>>>(rp, n, flags + 1);
+  unsigned long long *ct = reinterpret_cast<unsigned long long *>(ws->nuniq.get<int64_t>(1));
+  MSLM_HIP(hipMemsetAsync(ct, 0, sizeof(unsigned long long), st));
+  k_coupling_total<<<nblk(n), kBS, 0, st>>>(rp, col, wv, n, N, ct);
   std::vector<int64_t> h(2 * T);
   int hf[2] = {0, 0};
+  unsigned long long hct = 0;
   d2h(h.data(), twom, 2 * T, st);
   d2h(hf, flags, 2, st);
+  d2h(&hct, ct, 1, st);
   MSLM_HIP(hipStreamSynchronize(st));
+  g.ctot = (int64_t)hct;
   g.twom.assign(h.begin(), h.begin() + T);
   g.nzslice.assign(h.begin() + T, h.end());
   for (int s = 0; s < T; s++)

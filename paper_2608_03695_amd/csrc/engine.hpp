@@ -131,6 +131,12 @@ struct GraphDev {
   int32_t maxdeg = 0;
   std::vector<int64_t> twom;     // per slice, host copy
   std::vector<int64_t> nzslice;  // per slice: units of nonzero degree
+  // coupling omega^(sr) = omega * c_sr: per slice the sum over r of c_sr (bounds a copy's
+  // coupling weight), and the coupling total C = sum of c_sr over ordered coupled copy pairs
+  // (2mu = sum_s 2m_s + omega * C)
+  std::vector<int64_t> crow;
+  int64_t ctot = 0;
+  bool present_only = false;   // only copies with an intra edge are coupled (CPM weight 0 else)
   Buf rp, col, w, k;
   Buf rev;   // per entry (u, x): offset of the entry (x, u) within x's row
 };

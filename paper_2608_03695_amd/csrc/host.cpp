@@ -5,6 +5,7 @@
 #include "host.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -50,10 +51,21 @@ mslm_status check_desc_shape(const mslm_graph_desc *d) {
   if (E > 0 && (!d->src || !d->dst)) return fail(MSLM_EINVAL, "src/dst are NULL");
   const int64_t n = (int64_t)d->n_nodes * d->n_slices;
   if ((uint64_t)n * 33u >= 0xffffffffull) return fail(MSLM_EUNSUPPORTED, "N*T*33 must stay below 2^32");
-  if (2 * E + 2 * (int64_t)d->n_nodes * (d->n_slices - 1) >= ((int64_t)1 << 40))
+  if (2 * E + (int64_t)d->n_nodes * d->n_slices * (d->n_slices - 1) >= ((int64_t)1 << 40))
     return fail(MSLM_EUNSUPPORTED, "too many edges");
   mslm_status s = check_fraction(d->omega_num, d->omega_den, "omega");
   if (s != MSLM_OK) return s;
+  if (d->coupling) {
+    const int T = d->n_slices;
+    for (int a = 0; a < T; a++)
+      for (int b = 0; b < T; b++) {
+        const int32_t c = d->coupling[a * T + b];
+        if (c < 0 || c >= (1 << 16))
+          return fail(MSLM_EINVAL, "coupling: entries must lie in [0, 2^16)");
+        if (a == b && c != 0) return fail(MSLM_EINVAL, "coupling: the diagonal must be 0");
+        if (c != d->coupling[b * T + a]) return fail(MSLM_EINVAL, "coupling: must be symmetric");
+      }
+  }
   return MSLM_OK;
 }
 
@@ -289,19 +301,14 @@ BigS mk(int64_t v) {
   r.m = BigU::from(v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v);
   return r;
 }
-double to_double(const BigU &a) {
-  double x = 0;
-  for (size_t i = a.d.size(); i-- > 0;) x = x * 4294967296.0 + a.d[i];
-  return x;
-}
 
-// Q = (sum_s [W_s - gamma^(s) SS_s / D_s] + omega I) / (sum_s 2m_s + 2 omega N (T-1)) with
+// Q = (sum_s [W_s - gamma^(s) SS_s / D_s] + omega I) / (sum_s 2m_s + omega ctot) with
 // D_s = 2m_s (Eq. 6; a slice without edges has no null term) or 1 (the multislice CPM),
 // multiplied through by b * L, L = prod over the slices with a null term of gd_s * D_s, and
 // reduced.
-mslm_status q_exact_gen(const int64_t *c, int T, int N, const int64_t *gn, const int64_t *gd,
-                        bool cpm, int64_t oa, int64_t ob, std::string &num, std::string &den,
-                        double &qd) {
+mslm_status q_exact_gen(const int64_t *c, int T, int64_t ctot, const int64_t *gn,
+                        const int64_t *gd, bool cpm, int64_t oa, int64_t ob, std::string &num,
+                        std::string &den, double &qd) {
   std::vector<uint64_t> dn(T, 0);   // gd_s * D_s (< 2^62), 0: no null term
   for (int s = 0; s < T; s++) {
     const int64_t D = cpm ? 1 : c[2 * T + s];
@@ -335,15 +342,13 @@ mslm_status q_exact_gen(const int64_t *c, int T, int N, const int64_t *gn, const
   for (uint64_t m : dn)
     if (m) iv.m.mul(m);
   sumN = adds(sumN, iv);
-  // denominator: b*L*sum 2m_s + 2*a*L*N*(T-1)
+  // denominator: b*L*sum 2m_s + a*L*ctot
   BigU d1 = BigU::from((uint64_t)sum2m);
   d1.mul((uint64_t)ob);
   for (uint64_t m : dn)
     if (m) d1.mul(m);
-  BigU d2 = BigU::from(2);
+  BigU d2 = BigU::from((uint64_t)ctot);
   d2.mul((uint64_t)oa);
-  d2.mul((uint64_t)N);
-  d2.mul((uint64_t)(T - 1));
   for (uint64_t m : dn)
     if (m) d2.mul(m);
   BigU D = addu(d1, d2);
@@ -365,21 +370,27 @@ mslm_status q_exact_gen(const int64_t *c, int T, int N, const int64_t *gn, const
   divmodu(D, g, qdn, rdn);
   num = (sumN.neg ? "-" : "") + decimal(qn);
   den = decimal(qdn);
-  // double: scale both to their top 64 bits
-  size_t sh = std::max(qn.d.size(), qdn.d.size());
-  sh = sh > 2 ? sh - 2 : 0;
-  BigU a = qn, b = qdn;
-  a.d.erase(a.d.begin(), a.d.begin() + std::min(sh, a.d.size()));
-  b.d.erase(b.d.begin(), b.d.begin() + std::min(sh, b.d.size()));
-  qd = (sumN.neg ? -1.0 : 1.0) * to_double(a) / to_double(b);
+  // double: each value as its top three limbs (96 bits, rounded to 53) times a power of two,
+  // so the ratio keeps full double precision whatever the two sizes
+  auto top = [](const BigU &x, int &e) {
+    const size_t n = x.d.size(), k = std::min<size_t>(3, n);
+    double t = 0;
+    for (size_t i = n; i-- > n - k;) t = t * 4294967296.0 + x.d[i];
+    e = 32 * (int)(n - k);
+    return t;
+  };
+  int ea = 0, eb = 0;
+  const double ta = top(qn, ea), tb = top(qdn, eb);
+  qd = (sumN.neg ? -1.0 : 1.0) * std::ldexp(ta / tb, ea - eb);
   return MSLM_OK;
 }
 
-// Eq. 6 with one resolution gp/gq in every slice.
+// Eq. 6 with one resolution gp/gq in every slice and the ordinal coupling of every copy.
 mslm_status q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa, int64_t ob,
                     std::string &num, std::string &den, double &qd) {
   std::vector<int64_t> gn(T, gp), gd(T, gq);
-  return q_exact_gen(c, T, N, gn.data(), gd.data(), false, oa, ob, num, den, qd);
+  return q_exact_gen(c, T, 2 * (int64_t)N * (T - 1), gn.data(), gd.data(), false, oa, ob, num,
+                     den, qd);
 }
 
 }  // namespace
@@ -399,7 +410,8 @@ size_t footprint_estimate(const mslm_graph_desc *d) {
   if (check_desc_shape(d) != MSLM_OK) return 0;
   const int64_t n = (int64_t)d->n_nodes * d->n_slices;
   const int64_t E = d->slice_offsets[d->n_slices];
-  const int64_t nnz = 2 * E + 2 * (int64_t)d->n_nodes * (d->n_slices - 1);
+  const int64_t P = api_coupled_pairs(api_coupling_matrix(d), d->n_slices);
+  const int64_t nnz = 2 * E + 2 * (int64_t)d->n_nodes * P;
   // resident graph + peak of one solve
   return (size_t)(8 * (n + 1) + 12 * nnz + 4 * n) + solve_scratch_estimate(n, nnz) + (64u << 20);
 }
@@ -430,8 +442,8 @@ std::string dec128(u128 x) {
 }
 }  // namespace
 
-int64_t global_two_mu(int64_t sum_two_m, int64_t N, int T, const SolveSpec &sp) {
-  const i128 v = (i128)sp.b * sum_two_m + (i128)2 * sp.a * N * (T > 1 ? T - 1 : 0);
+int64_t global_two_mu(int64_t sum_two_m, int64_t ctot, const SolveSpec &sp) {
+  const i128 v = (i128)sp.b * sum_two_m + (i128)sp.a * ctot;
   return v >= ((i128)1 << 62) ? ((int64_t)1 << 62) : (int64_t)v;
 }
 
@@ -445,7 +457,7 @@ bool api_global_headroom(int64_t two_mu, const SolveSpec &sp) {
   return true;
 }
 
-mslm_status api_q_exact_global(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
+mslm_status api_q_exact_global(const int64_t *c, int T, int N, int64_t ctot, int64_t gp, int64_t gq, int64_t oa,
                                int64_t ob, std::string &num, std::string &den, double &qd) {
   // every factor is below 2^31 or (SS') below 2^62, so the numerator and the denominator
   // stay below 2^94 and int128 holds them exactly
@@ -454,7 +466,8 @@ mslm_status api_q_exact_global(const int64_t *c, int T, int N, int64_t gp, int64
     W += c[s];
     tm += c[2 * T + s];
   }
-  const i128 two_mu = (i128)ob * tm + (i128)2 * oa * N * (T - 1);
+  (void)N;
+  const i128 two_mu = (i128)ob * tm + (i128)oa * ctot;
   const i128 Wp = (i128)ob * W + (i128)oa * c[3 * T];
   if (two_mu == 0) {
     num = "0";
@@ -530,7 +543,8 @@ mslm_status api_make_spec(const mslm_params *p, int64_t on, int64_t od, int32_t 
   return MSLM_OK;
 }
 
-bool api_slice_denominator(const SolveSpec &sp, int s, int64_t two_m, int64_t N, int64_t &Sdev) {
+bool api_slice_denominator(const SolveSpec &sp, int s, int64_t two_m, int64_t N, int64_t crow_s,
+                           int64_t &Sdev) {
   const bool cpm = sp.null_model == MSLM_NULL_CPM;
   const int64_t S = two_m > 0 ? two_m : 1;
   const i128h sd = (i128h)(cpm ? 1 : S) * (sp.smul.empty() ? 1 : sp.smul[s]);
@@ -539,7 +553,7 @@ bool api_slice_denominator(const SolveSpec &sp, int s, int64_t two_m, int64_t N,
     return false;
   }
   const i128h K = cpm ? N : S;
-  const i128h a1 = (i128h)sp.qe * sd * ((i128h)sp.b * S + 2 * sp.a);
+  const i128h a1 = (i128h)sp.qe * sd * ((i128h)sp.b * S + (i128h)sp.a * crow_s);
   const i128h a2 = (i128h)sp.pe * sp.b * K * K;
   if (a1 >= ((i128h)1 << 62) || a2 >= ((i128h)1 << 62)) {
     fail(MSLM_EOVERFLOW, "gain head-room: q*2m_s*w or p*b*k*Sigma reaches 2^62");
@@ -549,23 +563,74 @@ bool api_slice_denominator(const SolveSpec &sp, int s, int64_t two_m, int64_t N,
   return true;
 }
 
-mslm_status api_q_exact_spec(const int64_t *c, int T, int N, const SolveSpec &sp,
+mslm_status api_q_exact_spec(const int64_t *c, int T, int N, int64_t ctot, const SolveSpec &sp,
                              std::string &num, std::string &den, double &qd) {
   if (sp.null_model == MSLM_NULL_GLOBAL)
-    return api_q_exact_global(c, T, N, sp.p, sp.q, sp.a, sp.b, num, den, qd);
+    return api_q_exact_global(c, T, N, ctot, sp.p, sp.q, sp.a, sp.b, num, den, qd);
   std::vector<int64_t> gn(sp.gn), gd(sp.gd);
   if (gn.empty()) {
     gn.assign(T, sp.p);
     gd.assign(T, sp.q);
   }
-  return q_exact_gen(c, T, N, gn.data(), gd.data(), sp.null_model == MSLM_NULL_CPM, sp.a, sp.b,
-                     num, den, qd);
+  (void)N;
+  return q_exact_gen(c, T, ctot, gn.data(), gd.data(), sp.null_model == MSLM_NULL_CPM, sp.a,
+                     sp.b, num, den, qd);
 }
 
-mslm_status api_q_exact_slices(const int64_t *c, int T, int N, const int64_t *gn,
+mslm_status api_q_exact_slices(const int64_t *c, int T, int N, int64_t ctot, const int64_t *gn,
                                const int64_t *gd, bool cpm, int64_t oa, int64_t ob,
                                std::string &num, std::string &den, double &qd) {
-  return q_exact_gen(c, T, N, gn, gd, cpm, oa, ob, num, den, qd);
+  (void)N;
+  return q_exact_gen(c, T, ctot, gn, gd, cpm, oa, ob, num, den, qd);
+}
+
+std::vector<int32_t> api_coupling_matrix(const mslm_graph_desc *d) {
+  const int T = d->n_slices;
+  std::vector<int32_t> cm((size_t)T * T, 0);
+  for (int a = 0; a < T; a++)
+    for (int b = 0; b < T; b++)
+      cm[(size_t)a * T + b] = d->coupling ? d->coupling[a * T + b] : (a - b == 1 || b - a == 1);
+  return cm;
+}
+
+std::vector<int64_t> api_coupling_rows(const std::vector<int32_t> &cm, int T) {
+  std::vector<int64_t> row(T, 0);
+  for (int a = 0; a < T; a++)
+    for (int b = 0; b < T; b++) row[a] += cm[(size_t)a * T + b];
+  return row;
+}
+
+int64_t api_coupled_pairs(const std::vector<int32_t> &cm, int T) {
+  int64_t P = 0;
+  for (int a = 0; a < T; a++)
+    for (int b = a + 1; b < T; b++) P += cm[(size_t)a * T + b] != 0;
+  return P;
+}
+
+int64_t api_coupling_total_host(const mslm_graph_desc *d) {
+  const int T = d->n_slices;
+  const int64_t N = d->n_nodes;
+  const std::vector<int32_t> cm = api_coupling_matrix(d);
+  if (!(d->flags & MSLM_COUPLE_PRESENT)) {
+    int64_t t = 0;
+    for (int32_t c : cm) t += c;
+    return t * N;
+  }
+  std::vector<uint8_t> pres((size_t)N * T, 0);
+  for (int s = 0; s < T; s++)
+    for (int64_t e = d->slice_offsets[s]; e < d->slice_offsets[s + 1]; e++) {
+      pres[(size_t)s * N + d->src[e]] = 1;
+      pres[(size_t)s * N + d->dst[e]] = 1;
+    }
+  int64_t t = 0;
+  for (int a = 0; a < T; a++)
+    for (int b = 0; b < T; b++) {
+      const int32_t c = cm[(size_t)a * T + b];
+      if (!c) continue;
+      for (int64_t i = 0; i < N; i++)
+        if (pres[(size_t)a * N + i] && pres[(size_t)b * N + i]) t += c;
+    }
+  return t;
 }
 mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, int64_t oa,
                         int64_t ob, std::string &num, std::string &den, double &qd) {
@@ -576,6 +641,7 @@ mslm_status api_q_exact(const int64_t *c, int T, int N, int64_t gp, int64_t gq, 
 // p*b*S^2 < 2^62 with S = max(2m_s, 1) (level-0 gains); the same checks the device path
 // makes, so a request that passes them cannot fail on them later.
 mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp) {
+  const std::vector<int64_t> crow = api_coupling_rows(api_coupling_matrix(d), d->n_slices);
   int64_t sum_two_m = 0;
   for (int s = 0; s < d->n_slices; s++) {
     int64_t two_m = 0;
@@ -586,10 +652,10 @@ mslm_status api_check_headroom(const mslm_graph_desc *d, const SolveSpec &sp) {
     sum_two_m += two_m;
     if (sp.null_model == MSLM_NULL_GLOBAL) continue;
     int64_t Sdev = 0;
-    if (!api_slice_denominator(sp, s, two_m, d->n_nodes, Sdev)) return MSLM_EOVERFLOW;
+    if (!api_slice_denominator(sp, s, two_m, d->n_nodes, crow[s], Sdev)) return MSLM_EOVERFLOW;
   }
   if (sp.null_model == MSLM_NULL_GLOBAL &&
-      !api_global_headroom(global_two_mu(sum_two_m, d->n_nodes, d->n_slices, sp), sp))
+      !api_global_headroom(global_two_mu(sum_two_m, api_coupling_total_host(d), sp), sp))
     return MSLM_EOVERFLOW;
   return MSLM_OK;
 }

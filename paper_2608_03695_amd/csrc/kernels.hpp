@@ -46,13 +46,14 @@ __device__ inline uint32_t fresh_of(const SolveDev &sd, uint32_t fresh_base) {
 }
 
 // ------------------------------------------------------------------ level views
-// Level 0: the supra-CSR of Eq. 3 with raw intra weights; an entry whose column lies
-// outside the unit's slice is a coupling entry of scaled weight a (absent when a == 0).
+// Level 0: the supra-CSR of Eq. 3 with raw weights; an entry whose column lies outside the
+// unit's slice is a coupling entry of raw weight c_sr and scaled weight a * c_sr (absent when
+// a == 0).
 struct View0 {
   static constexpr bool kLevel0 = true;
   const int64_t *rp;
   const int32_t *col;
-  const int32_t *w;        // raw intra weight per entry, or nullptr for unit weights
+  const int32_t *w;        // raw weight per entry (intra w, coupling c_sr), or nullptr: all 1
   // degree in the null model of the unit's solve: the intra degree k_i^s (Eq. 6), or the
   // scaled supra-degree b*k_i^s + a*(coupling entries of the unit) (the global null model)
   const int32_t *k;
@@ -86,7 +87,7 @@ struct View0 {
     return Row{rp[v], rp[v + 1], slo, shi, sd.a[j], sd.b[j]};
   }
   __device__ int64_t wt(const Row &r, int64_t e, int32_t x) const {
-    return (x >= r.slo && x < r.shi) ? r.b * (w ? (int64_t)w[e] : 1) : r.a;
+    return (x >= r.slo && x < r.shi ? r.b : r.a) * (w ? (int64_t)w[e] : 1);
   }
   // neighbour of entry e and its scaled weight
   __device__ int64_t nbr(const Row &r, int64_t e, int64_t &ww) const {
@@ -136,12 +137,8 @@ struct ViewP {
   }
   __device__ int64_t nbr(const Row &r, int64_t e, int64_t &ww) const {
     const int32_t raw = col[e];
-    if (raw < 0) {
-      ww = r.a;
-      return raw & 0x7fffffff;
-    }
-    ww = r.b * (w ? (int64_t)w[e] : 1);
-    return raw;
+    ww = (raw < 0 ? r.a : r.b) * (w ? (int64_t)w[e] : 1);
+    return raw & 0x7fffffff;
   }
   __device__ int64_t orig(int64_t i) const { return uid[i]; }
   __device__ uint32_t lab_at(const uint32_t *comm, int64_t e, int64_t x) const {
@@ -1186,7 +1183,7 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
     c[u] = (kCopy && has) ? g.elab[e] : kNone;
     const uint32_t w = (has && g.w) ? (uint32_t)g.w[e] : 1u;
     tb[u].open(sig, gs[u]);
-    val[u] = !has ? 0u : (cr[u] < 0 ? 0x80000000u : w);
+    val[u] = !has ? 0u : (cr[u] < 0 ? 0x80000000u | w : w);
   }
   // a coupling entry of zero weight is no entry; the own community's first probe
   uint32_t hD[U];
@@ -1201,7 +1198,7 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
     if (gl == 0 && kv[u] > 0) eD[u] = tb[u].first(D[u], hD[u]);
   }
   // equal labels merged inside the group in a small LDS table per (group, unit): each entry
-  // adds its raw weight (low half) and coupling count (high half) to its label's slot; the
+  // adds its raw weight (low half) or coupling multiplier (high half) to its label's slot; the
   // lane that claims a slot leads that label.  Three LDS steps instead of G shuffle rounds.
   constexpr int kSlots = 2 * G;   // load at most one half
   uint32_t *sk = lm0_keys + (threadIdx.x >> 6) * (U * 128) + (gbase / G) * kSlots;
@@ -1234,7 +1231,7 @@ __device__ inline void lm0_lockstep(const ViewP &g, const SolveDev &sd, int64_t 
       }
       slot[u] = (int)h;
       const unsigned long long add =
-          (val[u] >> 31) ? (1ull << 32) : (unsigned long long)(val[u] & 0x7fffffffu);
+          (unsigned long long)(val[u] & 0x7fffffffu) << ((val[u] >> 31) ? 32 : 0);
       atomicAdd(sv + u * 128 + h, add);
     }
   }
@@ -3516,13 +3513,25 @@ __global__ void k_sigma_build_memb(View0 g, int64_t n, const int32_t *memb, Slic
 // Scaled supra-degree of every unit of one solve under the global null model:
 // b*k_i^s + a*c with c the unit's coupling entries (1 in the first and last slice, 2 between,
 // none for one slice).
-__global__ void k_null_degree_global(const int32_t *k, int64_t n, int64_t N, int T, int64_t a,
-                                     int64_t b, int32_t *out) {
+__global__ void k_null_degree_global(const int32_t *k, const int64_t *rp, const int32_t *col,
+                                     const int32_t *w, int64_t n, int64_t N, int64_t a, int64_t b,
+                                     int32_t *out) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int64_t s = v / N;
-  const int c = T == 1 ? 0 : ((s == 0 || s == T - 1) ? 1 : 2);
+  const int64_t lo = (v / N) * N, hi = lo + N;
+  int64_t c = 0;   // the copy's coupling multipliers
+  for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+    const int32_t x = col[e];
+    if (x < lo || x >= hi) c += w ? w[e] : 1;
+  }
   out[v] = (int32_t)(b * k[v] + a * c);
+}
+
+// CPM node weight: 1 per copy, or 0 for a copy without an intra edge when only present copies
+// are coupled (it is then no supra-node)
+__global__ void k_cpm_weight(const int32_t *kd, int64_t n, bool present_only, int32_t *out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) out[v] = (!present_only || kd[v] > 0) ? 1 : 0;
 }
 
 // SS per Sigma slice: sum over the slice's sub-table of value^2
@@ -3545,17 +3554,17 @@ __global__ void k_q_ss(const uint64_t *slots, const int64_t *base, int nslices, 
 }
 
 // I: ordered coupled copy pairs (i,s),(i,s+1) sharing a community, per solve
-__global__ void k_q_inter(View0 g, int64_t n, const int32_t *memb, const int32_t *slast,
-                          int64_t *I) {
+__global__ void k_q_inter(View0 g, int64_t n, const int32_t *memb, int64_t *I) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t add = 0;
   int j = 0;
-  if (v < n) {
-    int gs = g.uslice[v];
+  if (v < n) {   // the coupling entries of v (both directions are counted, one per row)
+    const int gs = g.uslice[v];
+    const int64_t lo = g.sstart[gs], hi = g.sstart[gs + 1];
     j = g.usolve[v];
-    if (gs < slast[j]) {   // not the last slice of its solve
-      int64_t N = g.sstart[gs + 1] - g.sstart[gs];
-      if (memb[v] == memb[v + N]) add = 2;
+    for (int64_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
+      const int32_t x = g.col[e];
+      if ((x < lo || x >= hi) && memb[x] == memb[v]) add += g.w ? g.w[e] : 1;
     }
   }
   wave_add64(I, j, add);

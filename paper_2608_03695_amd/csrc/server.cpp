@@ -50,6 +50,8 @@ struct Request {
   std::vector<int32_t> src, dst, w;
   bool weighted = false;
   int64_t omega_num = 1, omega_den = 1;
+  std::vector<int32_t> coupling;   // T*T, empty: ordinal
+  uint32_t couple_flags = 0;       // MSLM_COUPLE_PRESENT
   SolveSpec spec;
   size_t footprint = 0;
   Clock::time_point t_submit;
@@ -129,7 +131,8 @@ void solve_group(std::vector<std::shared_ptr<Request>> &grp, hipStream_t st, Wor
     d.weight = r.weighted ? r.w.data() : nullptr;
     d.omega_num = r.omega_num;
     d.omega_den = r.omega_den;
-    d.flags = 0;
+    d.flags = r.couple_flags;
+    d.coupling = r.coupling.empty() ? nullptr : r.coupling.data();
     graphs[i]->omega_num = r.omega_num;
     graphs[i]->omega_den = r.omega_den;
     build_graph(*graphs[i], d, st, ws);
@@ -320,6 +323,8 @@ mslm_status mslm_server_submit(mslm_server *s, const mslm_graph_desc *d, const m
   if (r->weighted) r->w.assign(d->weight, d->weight + E);
   r->omega_num = d->omega_num;
   r->omega_den = d->omega_den;
+  if (d->coupling) r->coupling.assign(d->coupling, d->coupling + (size_t)d->n_slices * d->n_slices);
+  r->couple_flags = d->flags & MSLM_COUPLE_PRESENT;
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);

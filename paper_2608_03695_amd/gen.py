@@ -253,6 +253,27 @@ def erdos_renyi(n, t, p, seed=0, weights_max=1, name="er"):
     return _assemble(n, t, per_slice, None, name, weighted=weights_max > 1)
 
 
+def with_absences(g, frac, seed=0):
+    """g with every edge of a node dropped in the snapshots where it is absent: each node is
+    absent from each snapshot with probability frac (the data of the paper's Table 1, whose
+    nodes appear in only some snapshots)."""
+    rng = np.random.default_rng(seed)
+    absent = rng.random((g.n_slices, g.n_nodes)) < frac
+    src, dst, w, off = [], [], [], [0]
+    for s in range(g.n_slices):
+        u, x, ww = g.slice_edges(s)
+        keep = ~(absent[s][u] | absent[s][x])
+        src.append(u[keep])
+        dst.append(x[keep])
+        if ww is not None:
+            w.append(ww[keep])
+        off.append(off[-1] + int(keep.sum()))
+    return TemporalGraph(g.n_nodes, g.n_slices, np.array(off, np.int64),
+                         np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32),
+                         None if g.weight is None else np.concatenate(w).astype(np.int32),
+                         g.planted, g.name + "_absent")
+
+
 def from_edge_lists(n, slices, weighted=False, name="custom"):
     """Build a graph from a list of per-slice [(u, x[, w]), ...] edge lists."""
     per = []

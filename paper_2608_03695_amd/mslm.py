@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmslm.so")
 MSLM_OK, MSLM_EINVAL, MSLM_ENOMEM, MSLM_EOVERFLOW, MSLM_EUNSUPPORTED, MSLM_EHIP, MSLM_EBUSY = \
     0, -1, -2, -3, -4, -5, -6
 MSLM_INPUT_ON_DEVICE, MSLM_OUTPUT_ON_DEVICE, MSLM_PROFILE, MSLM_COUNT = 1, 2, 4, 8
+MSLM_COUPLE_PRESENT = 16
 MSLM_NULL_MULTISLICE, MSLM_NULL_GLOBAL, MSLM_NULL_CPM = 0, 1, 2
 
 EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_q_exact_global",
@@ -44,7 +45,7 @@ class GraphDesc(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_slices", C.c_int32),
                 ("slice_offsets", C.c_void_p), ("src", C.c_void_p), ("dst", C.c_void_p),
                 ("weight", C.c_void_p), ("omega_num", C.c_int64), ("omega_den", C.c_int64),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("coupling", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -82,7 +83,7 @@ class Result(C.Structure):
                 ("lm_candidates", C.c_int64), ("q_components", C.c_int64 * (3 * 64 + 1)),
                 ("lm0_kernel_ms", C.c_double), ("lm0_launches", C.c_int64),
                 ("lm0_units", C.c_int64), ("lm0_entries", C.c_int64),
-                ("lm0_candidates", C.c_int64)]
+                ("lm0_candidates", C.c_int64), ("coupling_total", C.c_int64)]
 
     def as_dict(self, n_slices):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "q_components"}
@@ -130,8 +131,8 @@ def load():
     lib.mslm_q_exact_global.argtypes = lib.mslm_q_exact.argtypes
     lib.mslm_q_exact_global.restype = C.c_int
     lib.mslm_q_exact_variant.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int64,
-                                         C.c_int64, C.c_int64, C.c_int64, C.c_char_p, C.c_size_t,
-                                         C.c_char_p, C.c_size_t]
+                                         C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_char_p,
+                                         C.c_size_t, C.c_char_p, C.c_size_t]
     lib.mslm_q_exact_variant.restype = C.c_int
     lib.mslm_get_tuning.argtypes = [P, C.POINTER(Tuning)]
     lib.mslm_get_tuning.restype = C.c_int
@@ -177,15 +178,20 @@ def _ptr(a):
     return None if a is None else C.c_void_p(a.ctypes.data)
 
 
-def _desc(tg, omega):
+def _desc(tg, omega, coupling=None, present_only=False):
+    """mslm_graph_desc of a temporal graph; coupling: T x T integer matrix c_sr (omega^(sr) =
+    omega * c_sr; None: ordinal); present_only: couple only copies with an edge."""
     omega = Fraction(omega)
     keep = [np.ascontiguousarray(tg.offsets, dtype=np.int64),
             np.ascontiguousarray(tg.src, dtype=np.int32),
             np.ascontiguousarray(tg.dst, dtype=np.int32),
-            None if tg.weight is None else np.ascontiguousarray(tg.weight, dtype=np.int32)]
+            None if tg.weight is None else np.ascontiguousarray(tg.weight, dtype=np.int32),
+            None if coupling is None else np.ascontiguousarray(coupling, dtype=np.int32)]
     d = GraphDesc(tg.n_nodes, tg.n_slices, keep[0].ctypes.data, keep[1].ctypes.data,
                   keep[2].ctypes.data, None if keep[3] is None else keep[3].ctypes.data,
-                  omega.numerator, omega.denominator, 0)
+                  omega.numerator, omega.denominator,
+                  MSLM_COUPLE_PRESENT if present_only else 0,
+                  None if keep[4] is None else keep[4].ctypes.data)
     return d, keep
 
 
@@ -224,11 +230,11 @@ def stream_handle(stream=None):
 class Graph:
     """A temporal graph resident on the device (mslm_create / mslm_destroy)."""
 
-    def __init__(self, tg, omega=Fraction(1), stream=None):
+    def __init__(self, tg, omega=Fraction(1), stream=None, coupling=None, present_only=False):
         lib = load()
         self.n_nodes, self.n_slices = tg.n_nodes, tg.n_slices
         self.omega = Fraction(omega)
-        d, keep = _desc(tg, omega)
+        d, keep = _desc(tg, omega, coupling, present_only)
         h = C.c_void_p()
         _check(lib.mslm_create(C.byref(d), stream_handle(stream), C.byref(h)))
         self._h = h
@@ -327,9 +333,10 @@ def q_exact_global(components, n_slices, n_nodes, gamma, omega) -> Fraction:
 
 
 def q_exact_variant(components, n_slices, n_nodes, gamma, omega, null_model=MSLM_NULL_MULTISLICE,
-                    gamma_slices=None) -> Fraction:
+                    gamma_slices=None, coupling_total=None) -> Fraction:
     """Exact value of any objective (Eq. 6 with per-slice resolutions, the global null model,
-    the multislice CPM) from a solve's components, via the library's reduction."""
+    the multislice CPM) from a solve's components, via the library's reduction; coupling_total
+    is the graph's (a result's "coupling_total"; None: the ordinal coupling of every copy)."""
     lib = load()
     gamma, omega = Fraction(gamma), Fraction(omega)
     comps = np.ascontiguousarray(components, dtype=np.int64)
@@ -338,12 +345,14 @@ def q_exact_variant(components, n_slices, n_nodes, gamma, omega, null_model=MSLM
     den = C.create_string_buffer(1 << 16)
     _check(lib.mslm_q_exact_variant(_ptr(comps), n_slices, n_nodes, null_model, _ptr(gs),
                                     gamma.numerator, gamma.denominator, omega.numerator,
-                                    omega.denominator, num, 1 << 16, den, 1 << 16))
+                                    omega.denominator,
+                                    -1 if coupling_total is None else int(coupling_total),
+                                    num, 1 << 16, den, 1 << 16))
     return Fraction(int(num.value.decode()), int(den.value.decode()))
 
 
-def footprint_bytes(tg, omega=Fraction(1)) -> int:
-    d, keep = _desc(tg, omega)
+def footprint_bytes(tg, omega=Fraction(1), coupling=None) -> int:
+    d, keep = _desc(tg, omega, coupling)
     return int(load().mslm_footprint_bytes(C.byref(d)))
 
 
@@ -385,8 +394,9 @@ class Server:
         self._shape = {}
 
     def submit(self, tg, gamma=Fraction(1), omega=Fraction(1), max_levels=32, max_iterations=2,
-               seed=0, null_model=MSLM_NULL_MULTISLICE, gamma_slices=None, initial=None) -> int:
-        d, keep = _desc(tg, omega)
+               seed=0, null_model=MSLM_NULL_MULTISLICE, gamma_slices=None, initial=None,
+               coupling=None, present_only=False) -> int:
+        d, keep = _desc(tg, omega, coupling, present_only)
         p, pkeep = params(gamma, None, max_levels, max_iterations, 0, seed, 0, null_model,
                           gamma_slices, initial)
         t = C.c_uint64()

@@ -155,7 +155,7 @@ void host_checks() {
         ok = (__int128)sv.gn[s] * sv.qe * sv.smul[s] == (__int128)sv.pe * sv.gd[s];
       expect(ok, "per-slice constants");
       int64_t Sd = 0;
-      (void)api_slice_denominator(sv, 3, pick(0, 1 << 20), 5, Sd);
+      (void)api_slice_denominator(sv, 3, pick(0, 1 << 20), 5, pick(0, 1 << 20), Sd);
     }
     init[7] = 64 * 5;
     expect(api_make_spec(&pv, 1, 1, 5, 64, sv) == MSLM_EINVAL, "start label out of range");
@@ -178,6 +178,31 @@ void host_checks() {
   SolveSpec one;
   expect(api_check_headroom(&dd, one) == MSLM_OK, "head-room ok");
   expect(footprint_estimate(&dd) > 0, "footprint");
+  // general coupling: a random symmetric matrix, present-only copies, the global null model
+  {
+    Graph gc = random_graph(50, 5, 30);
+    mslm_graph_desc dc = gc.desc(true);
+    std::vector<int32_t> cm(25, 0);
+    for (int s = 0; s < 5; s++)
+      for (int r = s + 1; r < 5; r++) cm[s * 5 + r] = cm[r * 5 + s] = (int32_t)pick(0, 4);
+    dc.coupling = cm.data();
+    dc.flags = MSLM_COUPLE_PRESENT;
+    expect(api_check_desc(&dc) == MSLM_OK, "coupling accepted");
+    const int64_t ct = api_coupling_total_host(&dc);
+    dc.flags = 0;
+    const int64_t ct_all = api_coupling_total_host(&dc);
+    expect(ct >= 0 && ct <= ct_all, "coupling totals");
+    SolveSpec gs;
+    gs.null_model = MSLM_NULL_GLOBAL;
+    expect(api_check_headroom(&dc, gs) == MSLM_OK, "global head-room with coupling");
+    expect(footprint_estimate(&dc) > 0, "footprint with coupling");
+    cm[1] = 3;
+    cm[5] = 2;   // not symmetric
+    expect(api_check_desc(&dc) == MSLM_EINVAL, "asymmetric coupling");
+    cm[5] = 3;
+    cm[0] = 1;   // diagonal
+    expect(api_check_desc(&dc) == MSLM_EINVAL, "coupling diagonal");
+  }
   // exact Q from random components, all slice counts
   for (int rep = 0; rep < 200; rep++) {
     const int T = (int)pick(1, 64), N = (int)pick(1, 1 << 20);
@@ -199,7 +224,8 @@ void host_checks() {
       gn[s] = pick(1, ((int64_t)1 << 31) - 1);
       gd[s] = pick(1, ((int64_t)1 << 31) - 1);
     }
-    expect(api_q_exact_slices(c.data(), T, N, gn.data(), gd.data(), rep % 2 == 1,
+    expect(api_q_exact_slices(c.data(), T, N, pick(0, (int64_t)1 << 40), gn.data(), gd.data(),
+                              rep % 2 == 1,
                               pick(0, 1 << 30), pick(1, 1 << 30), num, den, q) == MSLM_OK &&
                !num.empty() && den != "0",
            "exact Q, per-slice resolutions");
