@@ -8,6 +8,7 @@ already resident in HBM.  Prints one JSON line (see the keys below).
                     [--no-cpu-baseline]
     python bench.py --workload cfg4 [--graphs 512]         # batched grid vs plain calls
     python bench.py --workload cfg5 [--requests 1000]      # served Poisson trace vs plain FIFO
+    python bench.py --workload sweep                      # doubling N, edges, T (Table 1 SBMs)
     python bench.py --copy-calibration                     # 3 plain 1 GiB device copies
 
 The default workload is config 3 (T=64 x N=1M DC-SBM, omega=1/2), the largest instance that
@@ -359,6 +360,55 @@ def bench_served(args):
     }
 
 
+def bench_sweep(args):
+    """The doubling study of the paper's Fig. 2b on the SBM shapes of its Table 1: full solves
+    (2 iterations) of the base graph and of the graphs with N, the edges and T doubled, under
+    the multislice objective (Eq. 6) and the global null model (the objective the paper timed),
+    with inputs resident; the ratio of each doubled shape's time to the base's."""
+    from paper_2608_03695_amd import gen
+    spec = gen.SWEEP_SOLVE
+    graphs = {name: gen.sweep_graph(name, workers=min(args.gen_workers, 10))
+              for name in gen.SWEEP_SHAPES}
+    import torch
+    from paper_2608_03695_amd import mslm
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    stream = torch.cuda.current_stream()
+    rows = {}
+    for name, tg in graphs.items():
+        g = mslm.Graph(tg, spec.omega, stream=stream)
+        info = g.info()
+        row = dict(N=tg.n_nodes, T=tg.n_slices, edges=int(tg.n_edges),
+                   supra_edges=info["nnz"] // 2)
+        for nm, key in ((0, "multislice"), (1, "global")):
+            kw = dict(gamma=spec.gamma, max_levels=spec.max_levels,
+                      max_iterations=spec.max_iterations, seed=spec.seed, null_model=nm)
+            for _ in range(args.warmup):
+                g.leiden(**kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, r = g.leiden(**kw)
+            torch.cuda.synchronize()
+            row[f"ms_{key}"] = (time.perf_counter() - t0) * 1000.0 / args.steps
+            row[f"communities_{key}"] = r["n_communities"]
+            row[f"q_{key}"] = r["q"]
+        g.close()
+        rows[name] = row
+        log(f"{name}: {row}")
+    base = rows["sbm"]
+    for name, row in rows.items():
+        for key in ("multislice", "global"):
+            row[f"x_{key}"] = row[f"ms_{key}"] / base[f"ms_{key}"]
+    return {"metric": "solve time of the SBM doubling study (Table 1 shapes)",
+            "value": base["ms_multislice"], "unit": "ms per solve (base shape)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": "sweep_sbm_table1_doubling", "gamma": str(spec.gamma),
+                       "omega": str(spec.omega), "iterations": spec.max_iterations},
+            "shapes": rows}
+
+
 def copy_calibration():
     """Three plain 1 GiB device-to-device copies (2^30 bytes read and 2^30 written each): the
     run that calibrates the FETCH_SIZE / WRITE_SIZE counters under rocprofv3 --pmc."""
@@ -408,8 +458,8 @@ def main():
         copy_calibration()
         return
 
-    if args.workload in ("cfg4", "cfg5"):
-        out = bench_batched(args) if args.workload == "cfg4" else bench_served(args)
+    if args.workload in ("cfg4", "cfg5", "sweep"):
+        out = {"cfg4": bench_batched, "cfg5": bench_served, "sweep": bench_sweep}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     # inputs are drawn before anything touches the GPU (the generator may use child processes)

@@ -312,6 +312,25 @@ CONFIG_SOLVE = {
     3: SolveSpec(Fraction(1), Fraction(1, 2)),
 }
 
+# The SBM rows of the paper's Table 1 (the snapshot graphs of its Fig. 2b doubling study):
+# nodes N, snapshots T and mean degree per snapshot, with 10 communities: the base (50k nodes,
+# 5 snapshots, 1.25M edges), then N, the edges and T doubled in turn.
+SWEEP_SHAPES = {
+    "sbm": (50_000, 5, 10),
+    "sbm_n": (100_000, 5, 10),
+    "sbm_e": (50_000, 5, 20),
+    "sbm_t": (50_000, 10, 10),
+}
+SWEEP_SOLVE = SolveSpec(Fraction(1), Fraction(1))
+
+
+def sweep_graph(name, workers=1):
+    """A DC-SBM of one of the SWEEP_SHAPES (exponent 2.5, mu 0.3, churn 0.05, unit weights)."""
+    n, t, mean = SWEEP_SHAPES[name]
+    return dcsbm(n, t, mean, 10, 0.3, 2.5, 0.05, seed=11, name=f"{name}_dcsbm_N{n}_T{t}_d{mean}",
+                 workers=workers)
+
+
 GAMMA_GRID = (Fraction(1, 2), Fraction(1), Fraction(2))
 OMEGA_GRID = (Fraction(1, 10), Fraction(1), Fraction(10))
 

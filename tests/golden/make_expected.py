@@ -4,12 +4,14 @@ Runs only the oracle (oracle/), never the HIP library: for each workload it reco
 sha256 of the oracle's int32 membership, its Q components and schedule statistics.  The
 GPU parity tests compare the HIP path's output against these files.
 
-    python tests/golden/make_expected.py [cfg2] [cfg3] [cfg4]
+    python tests/golden/make_expected.py [cfg2] [cfg3] [cfg4] [sweep]
 
 Config 3 needs about 45 GB of host memory and tens of minutes on 8 threads.  cfg4 records the
 oracle's digest (sha256 of the int32 membership and the int64 Q components) and statistics of
 every solve of the batched workload's grid (gamma in {1/2, 1, 2} x omega in {1/10, 1, 10}) on
-every 8th of its 512 graphs: 576 solves, run in parallel processes.
+every 8th of its 512 graphs: 576 solves, run in parallel processes.  sweep records the same
+digests for the four SBM shapes of the doubling study (Table 1) under the multislice and the
+global null model.
 """
 import hashlib
 import json
@@ -72,10 +74,36 @@ def make_cfg4():
     print("cfg4", len(solves), "solves", out["oracle_seconds"], "s")
 
 
+def make_sweep():
+    spec = gen.SWEEP_SOLVE
+    out = dict(workload="SBM shapes of the doubling study", gamma=str(spec.gamma),
+               omega=str(spec.omega), max_levels=spec.max_levels,
+               max_iterations=spec.max_iterations, seed=spec.seed, solves=[])
+    for name in gen.SWEEP_SHAPES:
+        tg = gen.sweep_graph(name, workers=4)
+        og = oracle.OracleGraph(tg, spec.omega)
+        for nm in (0, 1):
+            t0 = time.time()
+            memb, comps, st = og.leiden(spec.gamma, max_levels=spec.max_levels,
+                                        max_iterations=spec.max_iterations, seed=spec.seed,
+                                        null_model=nm)
+            out["solves"].append(dict(shape=name, graph=tg.name, n_edges=int(tg.n_edges),
+                                      null_model=nm, digest=_digest(memb, comps),
+                                      stats={k: int(v) for k, v in st.items()},
+                                      oracle_s=round(time.time() - t0, 1)))
+            print(name, nm, out["solves"][-1]["oracle_s"], "s", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sweep_expected.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+
+
 def main(names):
     for name in names:
         if name == "cfg4":
             make_cfg4()
+            continue
+        if name == "sweep":
+            make_sweep()
             continue
         make, spec = WORKLOADS[name]
         t0 = time.time()

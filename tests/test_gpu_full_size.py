@@ -5,7 +5,9 @@ calls only the oracle):
   components, Q as a reduced fraction and every schedule statistic;
 * the batched workload: every (gamma, omega) of the 3x3 grid on every 8th of its 512 graphs
   (576 solves) run as batched calls, each solve's membership and Q components against the
-  oracle's digest and statistics.
+  oracle's digest and statistics;
+* the four SBM shapes of the doubling study (Table 1: base, N, edges and T doubled) under the
+  multislice and the global null model, against the oracle's digests and statistics.
 
 The inputs are drawn at the start of the GPU session (tests/full_size_inputs.py).
 """
@@ -78,3 +80,24 @@ def test_batched_workload_sample_matches_oracle_digests():
     for h in handles:
         h.close()
     assert checked == len(exp["solves"]) == 576
+
+
+def test_doubling_study_shapes_match_oracle_digests():
+    from paper_2608_03695_amd import mslm
+    exp = _golden("sweep")
+    spec = gen.SWEEP_SOLVE
+    graphs = {}
+    for s in exp["solves"]:
+        if s["shape"] not in graphs:
+            graphs[s["shape"]] = gen.sweep_graph(s["shape"])
+        tg = graphs[s["shape"]]
+        assert tg.name == s["graph"] and tg.n_edges == s["n_edges"]
+        g = mslm.Graph(tg, spec.omega)
+        m, r = g.leiden(spec.gamma, max_levels=spec.max_levels,
+                        max_iterations=spec.max_iterations, seed=spec.seed,
+                        null_model=s["null_model"])
+        g.close()
+        case = f"{s['shape']} null_model={s['null_model']}"
+        assert _digest(m, r["q_components"][:3 * tg.n_slices + 1]) == s["digest"], case
+        for k in STAT_KEYS:
+            assert r[k] == s["stats"][k], f"{case}: {k}"
