@@ -283,6 +283,62 @@ typedef struct {
 mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs,
                               const mslm_solve *solves, int32_t n_solves, void *hip_stream);
 
+/* ------------------------------------------------------------------ spectral pathway */
+/* The Bethe-Hessian pathway of Section 3.1 (the paragraphs after Eq. 4) on a resident graph:
+ * H(r) = (r^2 - 1) I - r A + D with A the supra-adjacency of Eq. 3 (intra weights, coupling
+ * omega * c_sr) and D its weighted degrees; the k algebraically smallest eigenpairs of H (its
+ * informative, negative end) by Lanczos with full reorthogonalisation in float64; k-means of
+ * the n = N*T rows of the eigenvector embedding into k clusters.
+ *   k                  eigenvectors and clusters, 1..32 and below n
+ *   lanczos_steps      Krylov dimension m, k..min(256, n) (0: min(n, 256, max(4k, k + 60)))
+ *   kmeans_iterations  Lloyd iteration cap (0: 100)
+ *   r                  0: sqrt(<d^2>/<d> - 1) (1 when that is not above 1), the degree-corrected
+ *                      sqrt(average degree); else the value given (1 gives the Laplacian D - A)
+ *   omega_den == 0     keeps the graph's coupling omega
+ *   seed               the Lanczos start vector (SplitMix64 of seed ^ i, uniform in [-1, 1))
+ * k-means is deterministic: the first point, then the point farthest from the centroids chosen
+ * so far (lowest index on ties), then Lloyd steps until no label changes (nearest centroid,
+ * lowest index on ties; distances summed over the coordinates in order, each operation
+ * rounded; centroid sums exact on the fixed-point values round(x * 2^40)). */
+typedef struct {
+  int32_t k;
+  int32_t lanczos_steps;
+  int32_t kmeans_iterations;
+  int32_t reserved;
+  double r;
+  int64_t omega_num, omega_den;
+  uint64_t seed;
+} mslm_spectral_params;
+
+typedef struct {
+  double r;                /* the r used                                                     */
+  double residual_max;     /* largest ||H y - lambda y|| of the returned eigenpairs         */
+  int32_t lanczos_steps;   /* Krylov dimension reached (less than asked when it closed)     */
+  int32_t jacobi_sweeps;   /* sweeps of the tridiagonal eigensolver                           */
+  int32_t kmeans_iterations;
+  int32_t reserved;
+  double spmv_ms;          /* summed duration of the Lanczos operator launches (HIP events) */
+  int64_t spmv_launches;
+  double ms_total;         /* host wall clock of the call                                     */
+} mslm_spectral_result;
+
+/* eigenvalues[k] (host, ascending), embedding (host n x k row-major, may be NULL), labels
+ * (host n, may be NULL: no k-means).  Errors: EINVAL (arguments), EUNSUPPORTED (the Krylov
+ * space closed before k vectors), ENOMEM, EHIP. */
+mslm_status mslm_bethe_hessian(mslm_graph *g, const mslm_spectral_params *params,
+                               double *eigenvalues, double *embedding, int32_t *labels,
+                               mslm_spectral_result *res);
+/* y = H(r) x for host vectors of n = N*T (the operator alone, for checking it).  omega_den == 0
+ * keeps the graph's coupling.  Errors: EINVAL, ENOMEM, EHIP. */
+mslm_status mslm_bh_apply(mslm_graph *g, double r, int64_t omega_num, int64_t omega_den,
+                          const double *x, double *y);
+/* The k-means of the pathway on caller points (host, n x dim row-major, 1 <= dim <= 32,
+ * 1 <= k <= 32, k <= n): labels[n], centroids[k x dim] (may be NULL) and the Lloyd iterations
+ * run; work on hip_stream (NULL: the default stream).  Errors: EINVAL, ENOMEM, EHIP. */
+mslm_status mslm_kmeans(const double *points, int64_t n, int32_t dim, int32_t k,
+                        int32_t max_iterations, int32_t *labels, double *centroids,
+                        int32_t *iterations, void *hip_stream);
+
 /* ------------------------------------------------------------------ serving */
 /* A continuous-batching request loop (no counterpart in the paper: a systems layer around the
  * solve).  Requests are admitted in arrival order; each of max_slots worker slots takes all

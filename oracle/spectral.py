@@ -28,18 +28,22 @@ import numpy as np
 FIX_SHIFT = 40
 
 
-def supra_coo(g, omega, coupling=None):
+def supra_coo(g, omega, coupling=None, present_only=False):
     """Entries (row, col, weight) of the supra-adjacency as float64 arrays: both directions of
     every intra edge (repeated pairs summed), and omega * c_sr between (i,s) and (i,r)
-    (c: T x T integers, ordinal when None)."""
+    (c: T x T integers, ordinal when None; with present_only only between copies that have an
+    edge in their slices)."""
     n, T = g.n_nodes, g.n_slices
     rows, cols, vals = [], [], []
+    present = np.zeros((T, n), bool)
     for s in range(T):
         u, x, w = g.slice_edges(s)
         ww = np.ones(u.size) if w is None else w.astype(np.float64)
         rows += [s * n + u, s * n + x]
         cols += [s * n + x, s * n + u]
         vals += [ww, ww]
+        present[s, u] = True
+        present[s, x] = True
     om = float(Fraction(omega))
     if om != 0.0:
         for s in range(T):
@@ -47,9 +51,11 @@ def supra_coo(g, omega, coupling=None):
                 c = (1 if abs(s - r) == 1 else 0) if coupling is None else int(coupling[s][r])
                 if s != r and c:
                     i = np.arange(n)
+                    if present_only:
+                        i = i[present[s] & present[r]]
                     rows.append(s * n + i)
                     cols.append(r * n + i)
-                    vals.append(np.full(n, om * c))
+                    vals.append(np.full(i.size, om * c))
     if not rows:
         z = np.zeros(0, np.int64)
         return z, z, np.zeros(0)
@@ -57,9 +63,9 @@ def supra_coo(g, omega, coupling=None):
             np.concatenate(vals))
 
 
-def adjacency(g, omega, coupling=None):
+def adjacency(g, omega, coupling=None, present_only=False):
     import scipy.sparse as sp
-    r, c, v = supra_coo(g, omega, coupling)
+    r, c, v = supra_coo(g, omega, coupling, present_only)
     N = g.n_supra
     return sp.csr_matrix((v, (r, c)), shape=(N, N))   # duplicates are summed
 

@@ -14,7 +14,8 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
-SOURCES = ["prims.hip", "engine.hip", "static_entry.hip", "host.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["prims.hip", "engine.hip", "static_entry.hip", "spectral.hip", "host.cpp", "api.cpp",
+           "server.cpp"]
 
 
 def _needs(obj, deps):

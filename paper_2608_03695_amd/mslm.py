@@ -27,7 +27,8 @@ EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_
             "mslm_graph_info", "mslm_last_error", "mslm_set_allocator", "mslm_leiden_static",
             "mslm_batch_leiden", "mslm_get_tuning", "mslm_set_tuning", "mslm_autotune",
             "mslm_server_create", "mslm_server_submit", "mslm_server_wait",
-            "mslm_server_memory", "mslm_server_destroy"]
+            "mslm_server_memory", "mslm_server_destroy", "mslm_bethe_hessian", "mslm_bh_apply",
+            "mslm_kmeans"]
 
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -89,6 +90,22 @@ class Result(C.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "q_components"}
         d["q_components"] = np.array(self.q_components[:3 * n_slices + 1], dtype=np.int64)
         return d
+
+
+class SpectralParams(C.Structure):
+    _fields_ = [("k", C.c_int32), ("lanczos_steps", C.c_int32),
+                ("kmeans_iterations", C.c_int32), ("reserved", C.c_int32), ("r", C.c_double),
+                ("omega_num", C.c_int64), ("omega_den", C.c_int64), ("seed", C.c_uint64)]
+
+
+class SpectralResult(C.Structure):
+    _fields_ = [("r", C.c_double), ("residual_max", C.c_double), ("lanczos_steps", C.c_int32),
+                ("jacobi_sweeps", C.c_int32), ("kmeans_iterations", C.c_int32),
+                ("reserved", C.c_int32), ("spmv_ms", C.c_double), ("spmv_launches", C.c_int64),
+                ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Solve(C.Structure):
@@ -165,6 +182,14 @@ def load():
     lib.mslm_server_memory.restype = C.c_int
     lib.mslm_server_destroy.argtypes = [P]
     lib.mslm_server_destroy.restype = None
+    lib.mslm_bethe_hessian.argtypes = [P, C.POINTER(SpectralParams), P, P, P,
+                                       C.POINTER(SpectralResult)]
+    lib.mslm_bethe_hessian.restype = C.c_int
+    lib.mslm_bh_apply.argtypes = [P, C.c_double, C.c_int64, C.c_int64, P, P]
+    lib.mslm_bh_apply.restype = C.c_int
+    lib.mslm_kmeans.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P, P,
+                                C.POINTER(C.c_int32), P]
+    lib.mslm_kmeans.restype = C.c_int
     _lib = lib
     return lib
 
@@ -304,6 +329,52 @@ class Graph:
         entry = lib.mslm_leiden_static if no_alloc else lib.mslm_leiden
         _check(entry(self._h, C.byref(p), dest, C.byref(res)))
         return memb, res.as_dict(self.n_slices)
+
+
+def _graph_bethe_hessian(self, k, r=0.0, lanczos_steps=0, kmeans_iterations=0, omega=None,
+                        seed=0, embedding=True, labels=True):
+    """The Bethe-Hessian pathway (mslm_bethe_hessian): (eigenvalues[k], embedding n x k or
+    None, labels n or None, result dict)."""
+    n = self.n_nodes * self.n_slices
+    if omega is None:
+        on, od = 0, 0
+    else:
+        omega = Fraction(omega)
+        on, od = omega.numerator, omega.denominator
+    p = SpectralParams(int(k), int(lanczos_steps), int(kmeans_iterations), 0, float(r), on, od,
+                       int(seed))
+    ev = np.zeros(int(k), np.float64)
+    emb = np.zeros((n, int(k)), np.float64) if embedding else None
+    lab = np.zeros(n, np.int32) if labels else None
+    res = SpectralResult()
+    _check(load().mslm_bethe_hessian(self._h, C.byref(p), _ptr(ev), _ptr(emb), _ptr(lab),
+                                     C.byref(res)))
+    return ev, emb, lab, res.as_dict()
+
+
+def _graph_bh_apply(self, x, r, omega=None):
+    """y = H(r) x (mslm_bh_apply)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros_like(x)
+    on, od = (0, 0) if omega is None else (Fraction(omega).numerator, Fraction(omega).denominator)
+    _check(load().mslm_bh_apply(self._h, float(r), on, od, _ptr(x), _ptr(y)))
+    return y
+
+
+Graph.bethe_hessian = _graph_bethe_hessian
+Graph.bh_apply = _graph_bh_apply
+
+
+def kmeans(points, k, max_iterations=0, stream=None):
+    """The pathway's deterministic k-means (mslm_kmeans): (labels, centroids, iterations)."""
+    P = np.ascontiguousarray(points, dtype=np.float64)
+    n, dim = P.shape
+    lab = np.zeros(n, np.int32)
+    cen = np.zeros((int(k), dim), np.float64)
+    it = C.c_int32()
+    _check(load().mslm_kmeans(_ptr(P), n, dim, int(k), int(max_iterations), _ptr(lab), _ptr(cen),
+                              C.byref(it), stream_handle(stream)))
+    return lab, cen, it.value
 
 
 def q_exact(components, n_slices, n_nodes, gamma, omega) -> Fraction:

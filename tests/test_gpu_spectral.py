@@ -1,0 +1,130 @@
+"""GPU parity of the Bethe-Hessian pathway (Section 3.1) against the oracle's (oracle/spectral.py):
+
+* the operator H(r) x against the oracle's sparse H(r) @ x, to float64 rounding;
+* the k-means entry on seeded synthetic points: labels, centroids and iteration counts bit for
+  bit (both sides take every decision in float64 on the same values, and the centroid sums are
+  exact);
+* the k smallest eigenpairs against scipy's symmetric eigensolver: eigenvalues to 1e-8 of the
+  spectral scale, residuals, the same invariant subspace (principal angles), H(1) = Laplacian;
+* the whole pathway's labels against the oracle's (up to relabelling) on planted graphs.
+"""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+from oracle import spectral as SP
+from paper_2608_03695_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _mslm():
+    from paper_2608_03695_amd import mslm
+    return mslm
+
+
+GRAPHS = [
+    ("planted_static", lambda: gen.planted_partition(800, 1, 4, 0.06, 0.003, 0.0, seed=5), F(0), None, False),
+    ("planted_T4_strong", lambda: gen.planted_partition(600, 4, 4, 0.06, 0.003, 0.0, seed=5), F(3), None, False),
+    ("dcsbm_weighted", lambda: gen.dcsbm(2000, 4, 8, 6, 0.2, 2.5, 0.02, weights_max=4, seed=8), F(1), None, False),
+    ("categorical_absent", lambda: gen.with_absences(gen.dcsbm(1500, 4, 10, 5, 0.2, 2.5, 0.02, seed=9), 0.2, seed=1),
+     F(1, 2), [[0, 1, 1, 1], [1, 0, 1, 1], [1, 1, 0, 1], [1, 1, 1, 0]], True),
+]
+IDS = [g[0] for g in GRAPHS]
+
+
+def _handle(tg, omega, cm, po):
+    return _mslm().Graph(tg, omega, coupling=cm, present_only=po)
+
+
+def _oracle_H(tg, omega, cm, po, r):
+    A = SP.adjacency(tg, omega, cm, po)
+    rr = SP.default_r(A) if r is None else r
+    return SP.bethe_hessian(A, rr), rr
+
+
+@pytest.mark.parametrize("name,make,omega,cm,po", GRAPHS, ids=IDS)
+def test_operator_matches_oracle(name, make, omega, cm, po):
+    tg = make()
+    g = _handle(tg, omega, cm, po)
+    rng = np.random.default_rng(7)
+    for r in (1.0, 2.75):
+        H, _ = _oracle_H(tg, omega, cm, po, r)
+        x = rng.standard_normal(tg.n_supra)
+        y = g.bh_apply(x, r)
+        want = H @ x
+        scale = abs(H).max() * np.abs(x).max() * 64
+        assert np.max(np.abs(y - want)) <= 1e-14 * scale, name
+    g.close()
+
+
+@pytest.mark.parametrize("n,dim,k,seed", [(5000, 3, 4, 1), (20000, 8, 8, 2), (3000, 16, 12, 3),
+                                          (40000, 5, 6, 4)])
+def test_kmeans_entry_bit_exact(n, dim, k, seed):
+    mslm = _mslm()
+    rng = np.random.default_rng(seed)
+    centres = rng.normal(scale=3.0, size=(k, dim))
+    P = centres[rng.integers(0, k, n)] + rng.normal(size=(n, dim))
+    lab, cen, it = mslm.kmeans(P, k, max_iterations=200)
+    olab, ocen, oit = SP.kmeans(P, k, max_iter=200)
+    assert np.array_equal(lab, olab)
+    assert np.array_equal(cen.view(np.int64), ocen.view(np.int64))   # bitwise
+    assert it == oit
+
+
+@pytest.mark.parametrize("name,make,omega,cm,po", GRAPHS, ids=IDS)
+def test_eigenpairs_match_oracle(name, make, omega, cm, po):
+    tg = make()
+    k = 6
+    g = _handle(tg, omega, cm, po)
+    ev, Y, _, res = g.bethe_hessian(k, lanczos_steps=160, labels=False)
+    g.close()
+    H, r = _oracle_H(tg, omega, cm, po, None)
+    assert res["r"] == pytest.approx(r, rel=1e-12)
+    w, V = SP.smallest_eigenpairs(H, k + 1)
+    scale = abs(H).sum(axis=1).max()   # a bound of the spectral radius
+    assert np.max(np.abs(ev - w[:k])) <= 1e-8 * scale, (ev, w)
+    assert res["residual_max"] <= 1e-7 * scale
+    # the same invariant subspace where the k-th eigenvalue is separated from the next
+    if w[k] - w[k - 1] > 1e-6 * scale:
+        s = np.linalg.svd(Y.T @ V[:, :k], compute_uv=False)
+        assert s.min() > 1 - 1e-6
+    assert np.allclose(Y.T @ Y, np.eye(k), atol=1e-8)
+
+
+def test_r_one_is_the_laplacian():
+    tg = gen.planted_partition(500, 3, 4, 0.08, 0.004, 0.0, seed=2)
+    g = _handle(tg, F(1), None, False)
+    ev, Y, _, res = g.bethe_hessian(3, r=1.0, lanczos_steps=120, labels=False)
+    g.close()
+    assert res["r"] == 1.0
+    assert abs(ev[0]) < 1e-9 * 100          # the Laplacian's zero eigenvalue (connected graph)
+    L = SP.bethe_hessian(SP.adjacency(tg, F(1)), 1.0)
+    w, _ = SP.smallest_eigenpairs(L, 3)
+    assert np.max(np.abs(ev - w)) < 1e-8 * 100
+
+
+@pytest.mark.parametrize("T,omega", [(1, F(0)), (4, F(3))])
+def test_pathway_labels_match_oracle(T, omega):
+    from sklearn.metrics import normalized_mutual_info_score as nmi
+    tg = gen.planted_partition(600, T, 4, 0.06, 0.003, 0.0, seed=5)
+    g = _handle(tg, omega, None, False)
+    ev, Y, lab, res = g.bethe_hessian(4, lanczos_steps=120)
+    g.close()
+    olab, ow, _, _ = SP.spectral_communities(tg, omega, 4)
+    assert nmi(lab, olab) > 0.99
+    assert nmi(lab, tg.planted.ravel()) > 0.95
+
+
+def test_invalid_spectral_arguments():
+    mslm = _mslm()
+    tg = gen.planted_partition(100, 2, 2, 0.1, 0.01, 0.0, seed=1)
+    g = _handle(tg, F(1), None, False)
+    for kw in (dict(k=0), dict(k=33), dict(k=4, lanczos_steps=3), dict(k=2, r=-1.0)):
+        with pytest.raises(mslm.MslmError) as e:
+            g.bethe_hessian(**kw)
+        assert e.value.status == mslm.MSLM_EINVAL, kw
+    with pytest.raises(mslm.MslmError):
+        mslm.kmeans(np.zeros((3, 2)), 4)
+    g.close()

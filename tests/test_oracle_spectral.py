@@ -70,6 +70,15 @@ def test_ihara_bass_real_eigenvalues_of_b_make_h_singular(seed):
     assert np.linalg.svd(H, compute_uv=False)[-1] > 1e-6
 
 
+def test_present_only_adjacency_equals_the_definitional_one():
+    g = gen.with_absences(gen.erdos_renyi(5, 3, 0.6, seed=2), 0.3, seed=4)
+    cm = [[0, 2, 1], [2, 0, 1], [1, 1, 0]]
+    A = SP.adjacency(g, F(1, 2), cm, True).toarray()
+    dense = np.array([[float(x) for x in row]
+                      for row in D.supra_adjacency(g, D.Coupling(F(1, 2), cm, True))])
+    assert np.array_equal(A, dense)
+
+
 def test_default_r_of_a_regular_graph():
     # a ring of 12 nodes in every slice, T = 1: 2-regular, r = sqrt(1) -> 1; a 4-regular
     # circulant: r = sqrt(3)
