@@ -9,6 +9,7 @@ already resident in HBM.  Prints one JSON line (see the keys below).
     python bench.py --workload cfg4 [--graphs 512]         # batched grid vs plain calls
     python bench.py --workload cfg5 [--requests 1000]      # served Poisson trace vs plain FIFO
     python bench.py --workload sweep                      # doubling N, edges, T (Table 1 SBMs)
+    python bench.py --workload spectral [--spectral-graph cfg2|cfg3]   # Bethe-Hessian pathway
     python bench.py --copy-calibration                     # 3 plain 1 GiB device copies
 
 The default workload is config 3 (T=64 x N=1M DC-SBM, omega=1/2), the largest instance that
@@ -409,6 +410,49 @@ def bench_sweep(args):
             "shapes": rows}
 
 
+def bench_spectral(args):
+    """The Bethe-Hessian pathway (Section 3.1) on a config graph: H(r) with the default r, the
+    k smallest eigenpairs by Lanczos, k-means of the embedding; inputs resident.  The roofline
+    is that of the operator launches (HBM-bound): per launch the row pointers, columns, raw
+    weights (weighted graphs), one 8-byte x read per entry, and d, x and y once per row."""
+    tg, spec = workload(args.spectral_graph, args.gen_workers, args.graph_cache)
+    import torch
+    from paper_2608_03695_amd import mslm
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    stream = torch.cuda.current_stream()
+    g = mslm.Graph(tg, spec.omega, stream=stream)
+    info = g.info()
+    n, nnz = info["n_supra"], info["nnz"]
+    k = args.spectral_k
+    kw = dict(seed=1, embedding=False, lanczos_steps=args.spectral_steps)
+    for _ in range(args.warmup):
+        g.bethe_hessian(k, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(args.steps):
+        ev, _, lab, res = g.bethe_hessian(k, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    weighted = tg.weight is not None
+    per_launch = 8 * (n + 1) + nnz * (4 + (4 if weighted else 0) + 8) + 24 * n
+    launch_ms = res["spmv_ms"] / max(1, res["spmv_launches"])
+    achieved = per_launch / (launch_ms * 1e-3) / 1e9
+    g.close()
+    return {"metric": "Bethe-Hessian pathway (Lanczos + k-means) per solve", "value": ms,
+            "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"spectral_{tg.name}", "k": k, "omega": str(spec.omega),
+                       "supra_nodes": n, "csr_entries": nnz},
+            "eigenvalues": [float(x) for x in ev], "result": res,
+            "roofline": {"bound": "hbm", "kernel": "k_bh_apply", "achieved": achieved,
+                         "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                         "bytes_per_launch": per_launch, "kernel_ms_per_launch": launch_ms,
+                         "traffic": None}}
+
+
 def copy_calibration():
     """Three plain 1 GiB device-to-device copies (2^30 bytes read and 2^30 written each): the
     run that calibrates the FETCH_SIZE / WRITE_SIZE counters under rocprofv3 --pmc."""
@@ -447,6 +491,11 @@ def main():
                     help="only run three plain 1 GiB device copies (counter calibration)")
     ap.add_argument("--graph-cache", default=None,
                     help=".npz file holding the drawn graph (read when present, else written)")
+    ap.add_argument("--spectral-graph", default="cfg2",
+                    help="spectral: the config graph the Bethe-Hessian pathway runs on")
+    ap.add_argument("--spectral-k", type=int, default=8, help="spectral: eigenvectors/clusters")
+    ap.add_argument("--spectral-steps", type=int, default=0,
+                    help="spectral: Lanczos steps (0: the library's default)")
     ap.add_argument("--gen-only", action="store_true",
                     help="draw the workload's graph (into --graph-cache) and stop")
     args = ap.parse_args()
@@ -458,8 +507,9 @@ def main():
         copy_calibration()
         return
 
-    if args.workload in ("cfg4", "cfg5", "sweep"):
-        out = {"cfg4": bench_batched, "cfg5": bench_served, "sweep": bench_sweep}[args.workload](args)
+    if args.workload in ("cfg4", "cfg5", "sweep", "spectral"):
+        out = {"cfg4": bench_batched, "cfg5": bench_served, "sweep": bench_sweep,
+               "spectral": bench_spectral}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     # inputs are drawn before anything touches the GPU (the generator may use child processes)

@@ -290,7 +290,9 @@ mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs,
  * informative, negative end) by Lanczos with full reorthogonalisation in float64; k-means of
  * the n = N*T rows of the eigenvector embedding into k clusters.
  *   k                  eigenvectors and clusters, 1..32 and below n
- *   lanczos_steps      Krylov dimension m, k..min(256, n) (0: min(n, 256, max(4k, k + 60)))
+ *   lanczos_steps      Krylov dimension m, k..min(256, n) (0: min(n, 256, max(4k, k + 152));
+ *                      without restarts the returned pairs converge only when m is large enough
+ *                      for the graph: res->residual_max reports how far they are)
  *   kmeans_iterations  Lloyd iteration cap (0: 100)
  *   r                  0: sqrt(<d^2>/<d> - 1) (1 when that is not above 1), the degree-corrected
  *                      sqrt(average degree); else the value given (1 gives the Laplacian D - A)

@@ -103,12 +103,14 @@ __global__ void k_dot_partial(const double *x, const double *y, int64_t n, doubl
   s = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
+// out[i] = sum over b of partial[b * cnt + i]: one block per i (the same order every run)
 __global__ void k_sum_partials(const double *partial, int nb, int cnt, double *out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
+  __shared__ double sh[kSB / 64];
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; b++) s += partial[(int64_t)b * cnt + i];
-  out[i] = s;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[(int64_t)b * cnt + i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[i] = s;
 }
 
 // sum of d and of d^2 (the default r)
@@ -471,7 +473,7 @@ void d2h_raw(void *h, const void *d, size_t bytes, hipStream_t st) {
 double dot_dev(const double *x, const double *y, int64_t n, double *partial, double *out,
                hipStream_t st) {
   k_dot_partial<<<kDotBlocks, kSB, 0, st>>>(x, y, n, partial);
-  k_sum_partials<<<1, 64, 0, st>>>(partial, kDotBlocks, 1, out);
+  k_sum_partials<<<1, kSB, 0, st>>>(partial, kDotBlocks, 1, out);
   double h = 0.0;
   d2h_raw(&h, out, sizeof(double), st);
   MSLM_HIP(hipStreamSynchronize(st));
@@ -539,7 +541,7 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
   double r = r_in;
   if (r <= 0.0) {   // sqrt(<d^2>/<d> - 1), or 1 when that is not above 1
     k_deg_moments<<<kDotBlocks, kSB, 0, st>>>(d, n, partial);
-    k_sum_partials<<<1, 64, 0, st>>>(partial, kDotBlocks, 2, dout);
+    k_sum_partials<<<2, kSB, 0, st>>>(partial, kDotBlocks, 2, dout);
     double m2[2] = {0.0, 0.0};
     d2h_raw(m2, dout, sizeof(m2), st);
     MSLM_HIP(hipStreamSynchronize(st));
@@ -576,7 +578,7 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
                                               beta[j], n);
     for (int pass = 0; pass < 2; pass++) {
       k_mdot_partial<<<kDotBlocks, kSB, 0, st>>>(V, j + 1, w, n, partial);
-      k_sum_partials<<<blocks(j + 1, 64), 64, 0, st>>>(partial, kDotBlocks, j + 1, dout);
+      k_sum_partials<<<j + 1, kSB, 0, st>>>(partial, kDotBlocks, j + 1, dout);
       k_msub<<<blocks(n), kSB, 0, st>>>(V, j + 1, dout, w, n);
     }
     if (j == msteps - 1) break;
@@ -716,7 +718,7 @@ mslm_status mslm_bethe_hessian(mslm_graph *g, const mslm_spectral_params *p, dou
   if (K < 1 || K > kMaxK || K >= n)
     return api_fail(MSLM_EINVAL, "k must lie in 1..32 and below the number of supra-nodes");
   int m = p->lanczos_steps;
-  if (m == 0) m = (int)std::min<int64_t>(n, std::min(kMaxSteps, std::max(4 * K, K + 60)));
+  if (m == 0) m = (int)std::min<int64_t>(n, std::min(kMaxSteps, std::max(4 * K, K + 152)));
   if (m < K || m > kMaxSteps || m > n)
     return api_fail(MSLM_EINVAL, "lanczos_steps must lie in k..min(256, supra-nodes)");
   int64_t on = g->g.omega_num, od = g->g.omega_den;
