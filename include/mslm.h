@@ -283,6 +283,29 @@ typedef struct {
 mslm_status mslm_batch_leiden(mslm_graph *const *graphs, int32_t n_graphs,
                               const mslm_solve *solves, int32_t n_solves, void *hip_stream);
 
+/* ------------------------------------------------------------------ long sequences */
+/* Windowed optimisation of a snapshot sequence of any length T (Section 4 names it for the
+ * 7375-snapshot School data, whose one supra-graph is out of reach): windows of `window`
+ * consecutive snapshots (1..64), each starting window - overlap snapshots after the previous
+ * one (0 <= overlap < window), the last one ending at the last snapshot.  Each window is solved
+ * as mslm_leiden solves its supra-graph (same parameters, ordinal coupling, MSLM_COUPLE_PRESENT
+ * honoured); a later window starts from the earlier windows' labels on its overlapping
+ * snapshots and singletons elsewhere.  A window's community that holds overlapping copies takes
+ * the label of its first such copy (smallest supra-node), any other a new label; overlapping
+ * copies keep their labels, the window labels its other snapshots; labels are finally
+ * renumbered by first appearance.  desc: host edge lists, slice_offsets[T+1], coupling NULL;
+ * params: initial_membership NULL, gamma_slices (if given) T pairs.  membership[T*N] (host).
+ * Errors: EINVAL (arguments), and those of mslm_create / mslm_leiden for a window. */
+typedef struct {
+  int32_t windows;         /* windows solved                                                 */
+  int32_t n_communities;   /* communities of the final labels                                */
+  double ms_total;         /* host wall clock of the call                                    */
+} mslm_window_result;
+
+mslm_status mslm_leiden_windowed(const mslm_graph_desc *desc, const mslm_params *params,
+                                 int32_t window, int32_t overlap, void *hip_stream,
+                                 int32_t *membership, mslm_window_result *res);
+
 /* ------------------------------------------------------------------ spectral pathway */
 /* The Bethe-Hessian pathway of Section 3.1 (the paragraphs after Eq. 4) on a resident graph:
  * H(r) = (r^2 - 1) I - r A + D with A the supra-adjacency of Eq. 3 (intra weights, coupling

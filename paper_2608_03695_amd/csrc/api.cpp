@@ -6,6 +6,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mslm.h"
@@ -178,6 +179,92 @@ mslm_status mslm_q_exact_variant(const int64_t *qc, int32_t T, int32_t N, int32_
   if (a.size() + 1 > num_cap || b.size() + 1 > den_cap) return fail(MSLM_EINVAL, "buffer too small");
   memcpy(num, a.c_str(), a.size() + 1);
   memcpy(den, b.c_str(), b.size() + 1);
+  return MSLM_OK;
+}
+
+mslm_status mslm_leiden_windowed(const mslm_graph_desc *desc, const mslm_params *params,
+                                 int32_t window, int32_t overlap, void *hip_stream,
+                                 int32_t *membership, mslm_window_result *res) {
+  if (!desc || !params || !membership) return fail(MSLM_EINVAL, "desc, params or membership is NULL");
+  if (window < 1 || window > 64 || overlap < 0 || overlap >= window)
+    return fail(MSLM_EINVAL, "windowed: need 1 <= window <= 64 and 0 <= overlap < window");
+  if (desc->flags & MSLM_INPUT_ON_DEVICE) return fail(MSLM_EINVAL, "windowed: host edge lists only");
+  if (desc->coupling) return fail(MSLM_EINVAL, "windowed: ordinal coupling only (coupling NULL)");
+  if (params->initial_membership) return fail(MSLM_EINVAL, "windowed: no start partition");
+  const int32_t T = desc->n_slices, N = desc->n_nodes;
+  if (T < 1 || N < 1 || !desc->slice_offsets || desc->slice_offsets[0] != 0)
+    return fail(MSLM_EINVAL, "windowed: need n_nodes >= 1, n_slices >= 1, slice_offsets[0] = 0");
+  for (int s = 0; s < T; s++)
+    if (desc->slice_offsets[s + 1] < desc->slice_offsets[s])
+      return fail(MSLM_EINVAL, "slice_offsets must be non-decreasing");
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = (int64_t)N * T;
+  std::vector<int64_t> glob(n, -1);
+  int64_t fresh = 0;
+  int windows = 0;
+  int32_t prev_end = 0;
+  for (int32_t s0 = 0;;) {
+    const int32_t s1 = std::min(T, s0 + window);
+    const int32_t ov = windows == 0 ? 0 : prev_end - s0;   // overlapping snapshots
+    const int64_t nw = (int64_t)(s1 - s0) * N;
+    std::vector<int64_t> off(s1 - s0 + 1);
+    for (int s = s0; s <= s1; s++) off[s - s0] = desc->slice_offsets[s] - desc->slice_offsets[s0];
+    mslm_graph_desc sub = *desc;
+    sub.n_slices = s1 - s0;
+    sub.slice_offsets = off.data();
+    const int64_t e0 = desc->slice_offsets[s0];
+    sub.src = desc->src ? desc->src + e0 : nullptr;
+    sub.dst = desc->dst ? desc->dst + e0 : nullptr;
+    sub.weight = desc->weight ? desc->weight + e0 : nullptr;
+    std::vector<int32_t> init;
+    if (ov > 0) {   // the overlapping copies' labels so far, as labels of this window
+      init.resize(nw);
+      for (int64_t v = 0; v < nw; v++) init[v] = (int32_t)v;
+      std::unordered_map<int64_t, int32_t> seen;
+      for (int64_t v = 0; v < (int64_t)ov * N; v++) {
+        const int64_t lab = glob[(int64_t)s0 * N + v];
+        auto it = seen.find(lab);
+        if (it == seen.end()) it = seen.emplace(lab, (int32_t)v).first;
+        init[v] = it->second;
+      }
+    }
+    mslm_params p = *params;
+    p.gamma_slices = params->gamma_slices ? params->gamma_slices + 2 * (int64_t)s0 : nullptr;
+    p.initial_membership = ov > 0 ? init.data() : nullptr;
+    p.flags &= ~(uint32_t)(MSLM_OUTPUT_ON_DEVICE | MSLM_PROFILE | MSLM_COUNT);
+    mslm_graph *g = nullptr;
+    mslm_status st = mslm_create(&sub, hip_stream, &g);
+    if (st != MSLM_OK) return st;
+    std::vector<int32_t> m(nw);
+    st = mslm_leiden(g, &p, m.data(), nullptr);
+    mslm_destroy(g);
+    if (st != MSLM_OK) return st;
+    std::unordered_map<int32_t, int64_t> label_of;
+    for (int64_t v = 0; v < (int64_t)ov * N; v++)   // communities holding overlapping copies
+      label_of.emplace(m[v], glob[(int64_t)s0 * N + v]);
+    for (int64_t v = (int64_t)ov * N; v < nw; v++) {
+      auto it = label_of.find(m[v]);
+      if (it == label_of.end()) it = label_of.emplace(m[v], fresh++).first;
+      glob[(int64_t)s0 * N + v] = it->second;
+    }
+    windows++;
+    prev_end = s1;
+    if (s1 == T) break;
+    s0 = s1 - overlap;
+  }
+  std::unordered_map<int64_t, int32_t> first;   // labels by first appearance
+  for (int64_t v = 0; v < n; v++) {
+    auto it = first.find(glob[v]);
+    if (it == first.end()) it = first.emplace(glob[v], (int32_t)first.size()).first;
+    membership[v] = it->second;
+  }
+  if (res) {
+    res->windows = windows;
+    res->n_communities = (int32_t)first.size();
+    res->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  api_clear_error();
   return MSLM_OK;
 }
 

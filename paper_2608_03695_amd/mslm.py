@@ -28,7 +28,7 @@ EXPORTED = ["mslm_create", "mslm_leiden", "mslm_destroy", "mslm_q_exact", "mslm_
             "mslm_batch_leiden", "mslm_get_tuning", "mslm_set_tuning", "mslm_autotune",
             "mslm_server_create", "mslm_server_submit", "mslm_server_wait",
             "mslm_server_memory", "mslm_server_destroy", "mslm_bethe_hessian", "mslm_bh_apply",
-            "mslm_kmeans"]
+            "mslm_kmeans", "mslm_leiden_windowed"]
 
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -106,6 +106,10 @@ class SpectralResult(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class WindowResult(C.Structure):
+    _fields_ = [("windows", C.c_int32), ("n_communities", C.c_int32), ("ms_total", C.c_double)]
 
 
 class Solve(C.Structure):
@@ -190,6 +194,9 @@ def load():
     lib.mslm_kmeans.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P, P,
                                 C.POINTER(C.c_int32), P]
     lib.mslm_kmeans.restype = C.c_int
+    lib.mslm_leiden_windowed.argtypes = [C.POINTER(GraphDesc), C.POINTER(Params), C.c_int32,
+                                         C.c_int32, P, P, C.POINTER(WindowResult)]
+    lib.mslm_leiden_windowed.restype = C.c_int
     _lib = lib
     return lib
 
@@ -375,6 +382,21 @@ def kmeans(points, k, max_iterations=0, stream=None):
     _check(load().mslm_kmeans(_ptr(P), n, dim, int(k), int(max_iterations), _ptr(lab), _ptr(cen),
                               C.byref(it), stream_handle(stream)))
     return lab, cen, it.value
+
+
+def leiden_windowed(tg, omega, window, overlap, gamma=Fraction(1), max_levels=32,
+                    max_iterations=2, seed=0, null_model=MSLM_NULL_MULTISLICE, gamma_slices=None,
+                    present_only=False, stream=None):
+    """Windowed optimisation of a sequence of any length (mslm_leiden_windowed):
+    (membership int32[T*N], {"windows", "n_communities", "ms_total"})."""
+    d, keep = _desc(tg, omega, None, present_only)
+    p, pkeep = params(gamma, None, max_levels, max_iterations, 0, seed, 0, null_model,
+                      gamma_slices)
+    memb = np.empty(tg.n_nodes * tg.n_slices, dtype=np.int32)
+    res = WindowResult()
+    _check(load().mslm_leiden_windowed(C.byref(d), C.byref(p), int(window), int(overlap),
+                                       stream_handle(stream), _ptr(memb), C.byref(res)))
+    return memb, {k: getattr(res, k) for k, _ in res._fields_}
 
 
 def q_exact(components, n_slices, n_nodes, gamma, omega) -> Fraction:

@@ -1,0 +1,70 @@
+"""GPU parity of the windowed optimisation of long sequences (mslm_leiden_windowed) against the
+oracle's driver (oracle/windows.py), which applies the same window and labelling rules to
+oracle solves: identical memberships, for sequences beyond the 64 snapshots of one supra-graph,
+with and without overlap, under Eq. 6, the CPM and per-slice resolutions, with present-only
+coupling; one window equals the plain solve.
+"""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import windows as WN
+from paper_2608_03695_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _mslm():
+    from paper_2608_03695_amd import mslm
+    return mslm
+
+
+CASES = [
+    ("dcsbm_T150_W64_o4", lambda: gen.dcsbm(400, 150, 8, 8, 0.2, 2.5, 0.05, seed=21), 64, 4, {}),
+    ("dcsbm_T150_W16_o1", lambda: gen.dcsbm(400, 150, 8, 8, 0.2, 2.5, 0.05, seed=21), 16, 1, {}),
+    ("planted_T130_W32_o0", lambda: gen.planted_partition(200, 130, 5, 0.08, 0.005, 0.05, seed=22), 32, 0, {}),
+    ("planted_T130_cpm", lambda: gen.planted_partition(200, 130, 5, 0.08, 0.005, 0.05, seed=22), 40, 3,
+     dict(null_model=2, gamma=F(1, 30))),
+    ("long_T1000_absent", lambda: gen.with_absences(gen.dcsbm(60, 1000, 6, 4, 0.2, 2.5, 0.05, seed=23), 0.3, seed=2),
+     64, 2, dict(present_only=True)),
+]
+
+
+@pytest.mark.parametrize("name,make,W,o,kw", CASES, ids=[c[0] for c in CASES])
+def test_windowed_parity(name, make, W, o, kw):
+    mslm = _mslm()
+    tg = make()
+    gm, res = mslm.leiden_windowed(tg, F(1, 2), W, o, **kw)
+    om, nw = WN.leiden_windowed(tg, F(1, 2), W, o, **kw)
+    assert res["windows"] == nw
+    bad = np.nonzero(gm != om)[0]
+    assert bad.size == 0, f"{name}: {bad.size} labels differ, first at {bad[:5]}"
+    assert res["n_communities"] == int(om.max()) + 1
+
+
+def test_windowed_per_slice_resolutions():
+    mslm = _mslm()
+    tg = gen.dcsbm(300, 100, 8, 6, 0.2, 2.5, 0.05, seed=24)
+    gs = [F(1, 2), F(1), F(2)] * 33 + [F(1)]
+    gm, _ = mslm.leiden_windowed(tg, 1, 48, 2, gamma_slices=gs)
+    om, _ = WN.leiden_windowed(tg, 1, 48, 2, gamma_slices=gs)
+    assert np.array_equal(gm, om)
+
+
+def test_one_window_is_the_plain_solve():
+    mslm = _mslm()
+    tg = gen.planted_partition(300, 12, 4, 0.08, 0.005, 0.1, seed=25)
+    gm, res = mslm.leiden_windowed(tg, 1, 64, 3)
+    pm, _ = mslm.Graph(tg, 1).leiden(1)
+    assert res["windows"] == 1 and np.array_equal(gm, pm)
+
+
+def test_windowed_refusals():
+    mslm = _mslm()
+    tg = gen.planted_partition(50, 70, 3, 0.1, 0.01, 0.1, seed=26)
+    for W, o in ((0, 0), (65, 1), (8, 8), (8, -1)):
+        with pytest.raises(mslm.MslmError) as e:
+            mslm.leiden_windowed(tg, 1, W, o)
+        assert e.value.status == mslm.MSLM_EINVAL
