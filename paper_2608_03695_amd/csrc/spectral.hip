@@ -31,10 +31,12 @@ namespace {
 
 constexpr int kSB = 256;          // threads per block
 constexpr int kDotBlocks = 512;   // fixed grid of the reductions
+constexpr int kMdotBlocks = 4096; // grid of the reorthogonalisation dot products (8 per CU)
 constexpr int kMaxK = 32;         // eigenvectors / clusters
 constexpr int kMaxSteps = 256;    // Krylov dimension
 constexpr int kFixShift = 40;     // fixed-point scale of the k-means sums
 constexpr int kSplit = 20;        // a fixed-point value as hi * 2^20 + lo, 0 <= lo < 2^20
+constexpr int kJacobiThreads = 1024;
 
 inline unsigned blocks(int64_t n, int bs = kSB) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + bs - 1) / bs, 1 << 30));
@@ -151,18 +153,26 @@ __global__ void k_lanczos_sub(double *w, const double *vj, const double *vp, dou
   w[i] = t;
 }
 
-// partial[b * cnt + i] = block b's share of V_i . w, i < cnt (V column-major, n per vector)
+// partial[b * cnt + i] = block b's share of V_i . w, i < cnt (V column-major, n per vector);
+// four vectors per pass over the block's rows, so w is read once per four
 __global__ void k_mdot_partial(const double *V, int cnt, const double *w, int64_t n,
                                double *partial) {
   __shared__ double sh[kSB / 64];
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per, hi = std::min<int64_t>(n, lo + per);
-  for (int i = 0; i < cnt; i++) {
-    const double *vi = V + (int64_t)i * n;
-    double s = 0.0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) s += vi[k] * w[k];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * cnt + i] = s;
+  for (int i0 = 0; i0 < cnt; i0 += 4) {
+    const int q = std::min(4, cnt - i0);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      const double wk = w[k];
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        if (u < q) s[u] += V[(int64_t)(i0 + u) * n + k] * wk;
+    }
+    for (int u = 0; u < q; u++) {
+      const double t = block_sum(s[u], sh);
+      if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * cnt + i0 + u] = t;
+    }
   }
 }
 
@@ -188,12 +198,13 @@ __global__ void k_start_vector(double *v, int64_t n, uint64_t seedmix) {
 // with a dummy when m is odd) to the rows, then to the columns and to the eigenvector matrix Z;
 // sweeps until the off-diagonal norm is below tol times the matrix norm.  Ends with the
 // eigenvalue order (ascending, ties to the lower index) in order[].
-__global__ void k_jacobi(double *A, double *Z, int m, double tol, int max_sweeps, int *order,
-                         double *eval, int *sweeps_out) {
+__global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double *A, double *Z, int m, double tol,
+                                                          int max_sweeps, int *order,
+                                                          double *eval, int *sweeps_out) {
   __shared__ int pp[kMaxSteps / 2 + 1], qq[kMaxSteps / 2 + 1];
   __shared__ double cs[kMaxSteps / 2 + 1], sn[kMaxSteps / 2 + 1];
   __shared__ int player[kMaxSteps + 1];
-  __shared__ double red[kSB / 64];
+  __shared__ double red[kJacobiThreads / 64];
   __shared__ int done;
   const int M = m + (m & 1);   // players, a dummy index m when m is odd
   for (int i = threadIdx.x; i < m * m; i += blockDim.x) Z[i] = (i / m == i % m) ? 1.0 : 0.0;
@@ -535,7 +546,7 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
   DevVec<double> bd, bpart, bout, bV, bW, bT, bZ, beval, bY, bx, by;
   DevVec<int> bord, bsw;
   double *d = bd.get(n);
-  double *partial = bpart.get((int64_t)kDotBlocks * (kMaxSteps + 2));
+  double *partial = bpart.get((int64_t)kMdotBlocks * (kMaxSteps + 2));
   double *dout = bout.get(kMaxSteps + 2);
   k_bh_degree<<<blocks(n), kSB, 0, st>>>(g, d);
   double r = r_in;
@@ -577,8 +588,8 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
     k_lanczos_sub<<<blocks(n), kSB, 0, st>>>(w, vj, j ? V + (int64_t)(j - 1) * n : nullptr, a,
                                               beta[j], n);
     for (int pass = 0; pass < 2; pass++) {
-      k_mdot_partial<<<kDotBlocks, kSB, 0, st>>>(V, j + 1, w, n, partial);
-      k_sum_partials<<<j + 1, kSB, 0, st>>>(partial, kDotBlocks, j + 1, dout);
+      k_mdot_partial<<<kMdotBlocks, kSB, 0, st>>>(V, j + 1, w, n, partial);
+      k_sum_partials<<<j + 1, kSB, 0, st>>>(partial, kMdotBlocks, j + 1, dout);
       k_msub<<<blocks(n), kSB, 0, st>>>(V, j + 1, dout, w, n);
     }
     if (j == msteps - 1) break;
@@ -610,7 +621,7 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
   int *order = bord.get(steps);
   int *sw = bsw.get(1);
   h2d_raw(T, Th.data(), sizeof(double) * Th.size(), st);
-  k_jacobi<<<1, kSB, 0, st>>>(T, Z, steps, 1e-15, 60, order, eval, sw);
+  k_jacobi<<<1, kJacobiThreads, 0, st>>>(T, Z, steps, 1e-15, 60, order, eval, sw);
   std::vector<double> ev(steps);
   std::vector<int> ord(steps);
   d2h_raw(ev.data(), eval, sizeof(double) * steps, st);
