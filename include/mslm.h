@@ -339,9 +339,9 @@ typedef struct {
   double r;                /* the r used                                                     */
   double residual_max;     /* largest ||H y - lambda y|| of the returned eigenpairs         */
   int32_t lanczos_steps;   /* Krylov dimension reached (less than asked when it closed)     */
-  int32_t jacobi_sweeps;   /* sweeps of the tridiagonal eigensolver                           */
+  int32_t tridiagonal_steps; /* implicit QR steps of the tridiagonal eigensolver             */
   int32_t kmeans_iterations;
-  int32_t reserved;
+  int32_t second_passes;   /* Lanczos steps whose reorthogonalisation took a second pass     */
   double spmv_ms;          /* summed duration of the Lanczos operator launches (HIP events) */
   int64_t spmv_launches;
   double ms_total;         /* host wall clock of the call                                     */

@@ -5,8 +5,8 @@
 //
 // Kernels: the operator (16 lanes per row), block-partial dot products with a fixed grid (the
 // same sums in the same order on every run), a multi-vector dot / update pair for the
-// reorthogonalisation, a one-workgroup parallel Jacobi eigensolver for the small tridiagonal
-// matrix (disjoint rotations per round, round-robin pairing), the Ritz vectors, and k-means
+// reorthogonalisation, a one-workgroup implicit-QR eigensolver for the small tridiagonal
+// matrix (rotations found by one thread, applied by one thread per row), the Ritz vectors, and k-means
 // (maximin start, Lloyd steps; distances rounded operation by operation, centroid sums exact in
 // fixed point through integer atomics, so the labels do not depend on the order of the sums).
 #include <hip/hip_runtime.h>
@@ -31,12 +31,12 @@ namespace {
 
 constexpr int kSB = 256;          // threads per block
 constexpr int kDotBlocks = 512;   // fixed grid of the reductions
-constexpr int kMdotBlocks = 4096; // grid of the reorthogonalisation dot products (8 per CU)
+constexpr int kMdotBlocks = 512;  // row ranges of the reorthogonalisation dot products
+constexpr int kMdotVec = 8;       // vectors per pass over a block's rows
 constexpr int kMaxK = 32;         // eigenvectors / clusters
 constexpr int kMaxSteps = 256;    // Krylov dimension
 constexpr int kFixShift = 40;     // fixed-point scale of the k-means sums
 constexpr int kSplit = 20;        // a fixed-point value as hi * 2^20 + lo, 0 <= lo < 2^20
-constexpr int kJacobiThreads = 1024;
 
 inline unsigned blocks(int64_t n, int bs = kSB) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + bs - 1) / bs, 1 << 30));
@@ -105,8 +105,11 @@ __global__ void k_dot_partial(const double *x, const double *y, int64_t n, doubl
   s = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
-// out[i] = sum over b of partial[b * cnt + i]: one block per i (the same order every run)
-__global__ void k_sum_partials(const double *partial, int nb, int cnt, double *out) {
+// out[i] = sum over b of partial[b * cnt + i]: one block per i (the same order every run);
+// gate as for k_mdot_partial
+__global__ void k_sum_partials(const double *partial, int nb, int cnt, const int *gate,
+                               double *out) {
+  if (gate && *gate == 0) return;
   __shared__ double sh[kSB / 64];
   const int i = blockIdx.x;
   double s = 0.0;
@@ -153,36 +156,69 @@ __global__ void k_lanczos_sub(double *w, const double *vj, const double *vp, dou
   w[i] = t;
 }
 
-// partial[b * cnt + i] = block b's share of V_i . w, i < cnt (V column-major, n per vector);
-// four vectors per pass over the block's rows, so w is read once per four
-__global__ void k_mdot_partial(const double *V, int cnt, const double *w, int64_t n,
-                               double *partial) {
-  __shared__ double sh[kSB / 64];
+// partial[b * stride + i] = block b's share of V_i . w for i < cnt and, with norm, of w . w at
+// i = cnt (stride = cnt + norm; V column-major, n per vector).  Block (b, y) takes the
+// contiguous row range b and the eight vectors 8y..8y+7 (a grid of kMdotBlocks x
+// ceil(stride / 8) blocks): many short blocks keep enough loads in flight.
+__global__ __launch_bounds__(kSB) void k_mdot_partial(const double *V, int cnt, const double *w,
+                                                     int64_t n, int norm, const int *gate,
+                                                     double *partial) {
+  if (gate && *gate == 0) return;
+  __shared__ double sh[kMdotVec][kSB / 64];
+  const int stride = cnt + norm;
+  const int i0 = blockIdx.y * kMdotVec;
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per, hi = std::min<int64_t>(n, lo + per);
-  for (int i0 = 0; i0 < cnt; i0 += 4) {
-    const int q = std::min(4, cnt - i0);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-      const double wk = w[k];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double s[kMdotVec];
 #pragma unroll
-      for (int u = 0; u < 4; u++)
-        if (u < q) s[u] += V[(int64_t)(i0 + u) * n + k] * wk;
+  for (int u = 0; u < kMdotVec; u++) s[u] = 0.0;
+#pragma unroll 4
+  for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+    const double wk = w[k];
+#pragma unroll
+    for (int u = 0; u < kMdotVec; u++) {
+      const int i = i0 + u;
+      if (i < cnt) s[u] += V[(int64_t)i * n + k] * wk;
+      else if (i == cnt && norm) s[u] += wk * wk;
     }
-    for (int u = 0; u < q; u++) {
-      const double t = block_sum(s[u], sh);
-      if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * cnt + i0 + u] = t;
-    }
+  }
+  // the eight sums of the block: wave shuffles, then the four waves in index order
+#pragma unroll
+  for (int u = 0; u < kMdotVec; u++) {
+    double v = s[u];
+    for (int msk = 32; msk >= 1; msk >>= 1) v += __shfl_xor(v, msk, 64);
+    if (lane == 0) sh[u][wv] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < kMdotVec && i0 + (int)threadIdx.x < stride) {
+    double v = 0.0;
+    for (int q = 0; q < kSB / 64; q++) v += sh[threadIdx.x][q];
+    partial[(int64_t)blockIdx.x * stride + i0 + threadIdx.x] = v;
   }
 }
 
-// w -= V h (cnt vectors)
-__global__ void k_msub(const double *V, int cnt, const double *h, double *w, int64_t n) {
+// w -= V h (cnt vectors); gate as for k_mdot_partial
+__global__ void k_msub(const double *V, int cnt, const double *h, const int *gate, double *w,
+                       int64_t n) {
+  if (gate && *gate == 0) return;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double s = 0.0;
   for (int i = 0; i < cnt; i++) s += V[(int64_t)i * n + k] * h[i];
   w[k] -= s;
+}
+
+// The second reorthogonalisation pass is needed when the first removed more than half of
+// w's squared norm (||w - V h|| < ||w|| / sqrt(2), Daniel, Gragg, Kaufman and Stewart 1976):
+// flag = (sum h_i^2 > ||w||^2 / 2), from h[0..cnt) and ||w||^2 in h[cnt]; count[0] counts them
+__global__ void k_reorth_gate(const double *h, int cnt, int *flag, int *count) {
+  if (threadIdx.x != 0) return;
+  double hh = 0.0;
+  for (int i = 0; i < cnt; i++) hh += h[i] * h[i];
+  const int f = hh > 0.5 * h[cnt];
+  *flag = f;
+  count[0] += f;
 }
 
 // deterministic start vector: SplitMix64 of (seed, i) as a uniform value in [-1, 1)
@@ -193,93 +229,125 @@ __global__ void k_start_vector(double *v, int64_t n, uint64_t seedmix) {
   v[i] = (double)(z >> 11) * 0x1p-52 - 1.0;
 }
 
-// Parallel cyclic Jacobi on the symmetric m x m matrix A (row-major, global memory), one
-// workgroup: every round applies m/2 disjoint rotations (round-robin pairing of the indices,
-// with a dummy when m is odd) to the rows, then to the columns and to the eigenvector matrix Z;
-// sweeps until the off-diagonal norm is below tol times the matrix norm.  Ends with the
-// eigenvalue order (ascending, ties to the lower index) in order[].
-__global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double *A, double *Z, int m, double tol,
-                                                          int max_sweeps, int *order,
-                                                          double *eval, int *sweeps_out) {
-  __shared__ int pp[kMaxSteps / 2 + 1], qq[kMaxSteps / 2 + 1];
-  __shared__ double cs[kMaxSteps / 2 + 1], sn[kMaxSteps / 2 + 1];
-  __shared__ int player[kMaxSteps + 1];
-  __shared__ double red[kJacobiThreads / 64];
-  __shared__ int done;
-  const int M = m + (m & 1);   // players, a dummy index m when m is odd
-  for (int i = threadIdx.x; i < m * m; i += blockDim.x) Z[i] = (i / m == i % m) ? 1.0 : 0.0;
+// Eigen-decomposition of the symmetric tridiagonal matrix with diagonal a[0..m) and
+// off-diagonal b[0..m-1) by implicit QR steps with the Wilkinson shift (Golub & Van Loan,
+// Section 8.3).  Wave 0 finds the trailing unreduced block, thread 0 chases the bulge of one
+// step through it and keeps the step's rotations in LDS; then thread t applies them, in order, to
+// row t of the eigenvector matrix Z (column-major, Z[c * m + t]: the same column for every
+// thread, so the accesses are coalesced).  Off-diagonal entries at or below 2^-52 times the
+// sum of their two diagonal neighbours are set to zero.  The entries must be scaled to
+// magnitudes of at most 1 (the caller scales by a power of two).  Ends with the eigenvalues in eval[]
+// (column c of Z belongs to eval[c]), their ascending order (ties to the lower index) in
+// order[], and the number of QR steps in *steps_out (-1 when max_steps did not converge).
+constexpr int kQrThreads = kMaxSteps;   // one thread per row of Z
+__global__ __launch_bounds__(kQrThreads) void k_tridiag_qr(const double *a, const double *b, int m,
+                                                          int max_steps, double *Z, double *eval,
+                                                          int *order, int *steps_out) {
+  __shared__ double dd[kMaxSteps], ee[kMaxSteps];
+  __shared__ double cs[kMaxSteps], sn[kMaxSteps];
+  __shared__ int blk_lo, blk_hi, state;   // state 0: a step to apply, 1: converged, 2: failed
+  const double eps = 0x1p-52;
+  const int t = threadIdx.x;
+  for (int i = t; i < m; i += blockDim.x) {
+    dd[i] = a[i];
+    ee[i] = i + 1 < m ? b[i] : 0.0;
+  }
+  for (int i = t; i < m * m; i += blockDim.x) Z[i] = (i / m == i % m) ? 1.0 : 0.0;
   __syncthreads();
-  int sweep = 0;
-  for (; sweep < max_sweeps; sweep++) {
-    double off = 0.0, tot = 0.0;
-    for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
-      const double a = A[i];
-      tot += a * a;
-      if (i / m != i % m) off += a * a;
-    }
-    off = block_sum(off, red);
-    tot = block_sum(tot, red);
-    if (threadIdx.x == 0) done = !(off > tol * tol * tot);
-    __syncthreads();
-    if (done) break;
-    for (int i = threadIdx.x; i < M; i += blockDim.x) player[i] = i;
-    __syncthreads();
-    for (int round = 0; round < M - 1; round++) {
-      // pairs (player[i], player[M-1-i]); rotation parameters from the current matrix
-      for (int i = threadIdx.x; i < M / 2; i += blockDim.x) {
-        int p = player[i], q = player[M - 1 - i];
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < m) {
-          const double apq = A[p * m + q];
-          if (apq != 0.0) {
-            const double th = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
+  // hi and steps are kept alike by every lane of wave 0, which searches for the block together
+  int steps = 0, hi = m - 1;
+  auto negligible = [&](int j) {   // ee[j] against its diagonal neighbours
+    return fabs(ee[j]) <= eps * (fabs(dd[j]) + fabs(dd[j + 1]));
+  };
+  for (;;) {
+    if (t < 64) {
+      int st = 1;
+      while (hi > 0) {
+        if (negligible(hi - 1)) {   // deflate
+          if (t == 0) ee[hi - 1] = 0.0;
+          hi--;
+          continue;
+        }
+        // lo: one past the largest j < hi - 1 with a negligible ee[j] (0 when there is none),
+        // 64 entries per ballot
+        int lo = 0;
+        for (int base = hi - 2; base >= 0; base -= 64) {
+          const int j = base - t;
+          const unsigned long long bal = __ballot(j >= 0 && negligible(j));
+          if (bal) {
+            lo = base - (__ffsll(bal) - 1) + 1;
+            break;
           }
         }
-        pp[i] = p;
-        qq[i] = q;
-        cs[i] = c;
-        sn[i] = s;
+        if (steps >= max_steps) {
+          st = 2;
+          break;
+        }
+        steps++;
+        st = 0;
+        if (t != 0) break;
+        if (lo > 0) ee[lo - 1] = 0.0;
+        // the shift: the eigenvalue of the trailing 2 x 2 block nearer its last entry
+        const double p = dd[hi - 1], q = ee[hi - 1], r = dd[hi];
+        const double del = 0.5 * (p - r);
+        const double mu = r - q * q / (del + copysign(hypot(del, q), del));
+        double x = dd[lo] - mu, z = ee[lo];
+        // ak, bk: T[k][k] and T[k][k+1] as the previous rotation left them (kept in registers,
+        // so the chain of rotations waits on no LDS load)
+        double ak = dd[lo], bk = ee[lo];
+        for (int k = lo; k < hi; k++) {
+          const double ck = dd[k + 1], f = k + 1 < hi ? ee[k + 1] : 0.0;
+          // G = [[c, s], [-s, c]] on (k, k+1) zeroes z against x; T <- G^T T G.  The matrix
+          // comes scaled to entries of magnitude at most 1, so x^2 + z^2 cannot overflow
+          const double q2 = x * x + z * z;
+          const double rh = q2 > 0.0 ? rsqrt(q2) : 0.0;
+          const double h = q2 * rh;
+          const double c = q2 > 0.0 ? x * rh : 1.0, s = -z * rh;
+          if (k > lo) ee[k - 1] = h;
+          const double ek = c * s * (ak - ck) + (c * c - s * s) * bk;
+          dd[k] = c * c * ak - 2.0 * c * s * bk + s * s * ck;
+          ee[k] = ek;
+          ak = s * s * ak + 2.0 * c * s * bk + c * c * ck;   // T[k+1][k+1]
+          bk = c * f;                                        // T[k+1][k+2]
+          z = -s * f;                                        // the bulge at (k, k+2)
+          x = ek;
+          cs[k] = c;
+          sn[k] = s;
+        }
+        dd[hi] = ak;
+        blk_lo = lo;
+        blk_hi = hi;
+        break;
       }
-      __syncthreads();
-      // rows p, q of every pair (A <- J^T A)
-      for (int t = threadIdx.x; t < (M / 2) * m; t += blockDim.x) {
-        const int i = t / m, k = t % m;
-        const int p = pp[i], q = qq[i];
-        if (q >= m || sn[i] == 0.0) continue;
-        const double a = A[p * m + k], b = A[q * m + k];
-        A[p * m + k] = cs[i] * a - sn[i] * b;
-        A[q * m + k] = sn[i] * a + cs[i] * b;
-      }
-      __syncthreads();
-      // columns p, q (A <- A J) and the eigenvectors (Z <- Z J)
-      for (int t = threadIdx.x; t < (M / 2) * m; t += blockDim.x) {
-        const int i = t / m, k = t % m;
-        const int p = pp[i], q = qq[i];
-        if (q >= m || sn[i] == 0.0) continue;
-        const double a = A[k * m + p], b = A[k * m + q];
-        A[k * m + p] = cs[i] * a - sn[i] * b;
-        A[k * m + q] = sn[i] * a + cs[i] * b;
-        const double za = Z[k * m + p], zb = Z[k * m + q];
-        Z[k * m + p] = cs[i] * za - sn[i] * zb;
-        Z[k * m + q] = sn[i] * za + cs[i] * zb;
-      }
-      __syncthreads();
-      // next round: player 0 stays, the others rotate by one place
-      if (threadIdx.x == 0) {
-        const int last = player[M - 1];
-        for (int i = M - 1; i > 1; i--) player[i] = player[i - 1];
-        player[1] = last;
-      }
-      __syncthreads();
+      if (t == 0) state = st;
     }
+    __syncthreads();
+    if (state != 0) break;
+    const int lo = blk_lo, h2 = blk_hi;
+    if (t < m) {   // Z <- Z G_lo G_lo+1 ... on row t, the next 16 columns loaded ahead
+      constexpr int kAhead = 16;
+      double carry = Z[(int64_t)lo * m + t];
+      for (int k0 = lo; k0 < h2; k0 += kAhead) {
+        double nx[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; u++)
+          nx[u] = k0 + 1 + u <= h2 ? Z[(int64_t)(k0 + 1 + u) * m + t] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kAhead; u++) {
+          const int k = k0 + u;
+          if (k < h2) {
+            Z[(int64_t)k * m + t] = cs[k] * carry - sn[k] * nx[u];
+            carry = sn[k] * carry + cs[k] * nx[u];
+          }
+        }
+      }
+      Z[(int64_t)h2 * m + t] = carry;
+    }
+    __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     for (int i = 0; i < m; i++) {
-      eval[i] = A[i * m + i];
+      eval[i] = dd[i];
       order[i] = i;
     }
     for (int i = 1; i < m; i++) {   // insertion sort by eigenvalue, stable
@@ -291,11 +359,11 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double *A, double *Z,
       }
       order[j + 1] = o;
     }
-    *sweeps_out = sweep;
+    *steps_out = state == 2 ? -1 : steps;
   }
 }
 
-// Ritz vectors: Y[v * K + c] = sum_i V_i[v] Z[i, order[c]]
+// Ritz vectors: Y[v * K + c] = sum_i V_i[v] Z[i, order[c]] (Z column-major)
 __global__ void k_ritz(const double *V, int msteps, const double *Z, int m, const int *order,
                        int K, int64_t n, double *Y) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,7 +375,7 @@ __global__ void k_ritz(const double *V, int msteps, const double *Z, int m, cons
     const double x = V[(int64_t)i * n + v];
 #pragma unroll
     for (int c = 0; c < kMaxK; c++)
-      if (c < K) acc[c] += x * Z[i * m + order[c]];
+      if (c < K) acc[c] += x * Z[(int64_t)order[c] * m + i];
   }
 #pragma unroll
   for (int c = 0; c < kMaxK; c++)
@@ -484,7 +552,7 @@ void d2h_raw(void *h, const void *d, size_t bytes, hipStream_t st) {
 double dot_dev(const double *x, const double *y, int64_t n, double *partial, double *out,
                hipStream_t st) {
   k_dot_partial<<<kDotBlocks, kSB, 0, st>>>(x, y, n, partial);
-  k_sum_partials<<<1, kSB, 0, st>>>(partial, kDotBlocks, 1, out);
+  k_sum_partials<<<1, kSB, 0, st>>>(partial, kDotBlocks, 1, nullptr, out);
   double h = 0.0;
   d2h_raw(&h, out, sizeof(double), st);
   MSLM_HIP(hipStreamSynchronize(st));
@@ -531,7 +599,7 @@ int kmeans_dev(const double *P, int64_t n, int dim, int k, int max_iter, int32_t
 
 struct Spectral {
   double r = 1.0, residual_max = 0.0, ms_spmv = 0.0;
-  int steps = 0, sweeps = 0, km_iters = 0;
+  int steps = 0, sweeps = 0, km_iters = 0, second_passes = 0;
   int64_t spmv_launches = 0;
 };
 
@@ -552,7 +620,7 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
   double r = r_in;
   if (r <= 0.0) {   // sqrt(<d^2>/<d> - 1), or 1 when that is not above 1
     k_deg_moments<<<kDotBlocks, kSB, 0, st>>>(d, n, partial);
-    k_sum_partials<<<2, kSB, 0, st>>>(partial, kDotBlocks, 2, dout);
+    k_sum_partials<<<2, kSB, 0, st>>>(partial, kDotBlocks, 2, nullptr, dout);
     double m2[2] = {0.0, 0.0};
     d2h_raw(m2, dout, sizeof(m2), st);
     MSLM_HIP(hipStreamSynchronize(st));
@@ -569,6 +637,8 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
     k_scale_into<<<blocks(n), kSB, 0, st>>>(1.0 / nv, V, V, n);
   }
   std::vector<double> alpha, beta(1, 0.0);
+  int *flag = bsw.get(3);   // [0] second pass wanted, [1] second passes taken, [2] QR steps
+  fill_i32(flag, 0, 3, st);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   MSLM_HIP(hipEventCreate(&e0));
   MSLM_HIP(hipEventCreate(&e1));
@@ -587,11 +657,17 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
     alpha.push_back(a);
     k_lanczos_sub<<<blocks(n), kSB, 0, st>>>(w, vj, j ? V + (int64_t)(j - 1) * n : nullptr, a,
                                               beta[j], n);
-    for (int pass = 0; pass < 2; pass++) {
-      k_mdot_partial<<<kMdotBlocks, kSB, 0, st>>>(V, j + 1, w, n, partial);
-      k_sum_partials<<<j + 1, kSB, 0, st>>>(partial, kMdotBlocks, j + 1, dout);
-      k_msub<<<blocks(n), kSB, 0, st>>>(V, j + 1, dout, w, n);
-    }
+    // classical Gram-Schmidt against every Lanczos vector, a second time when the first
+    // pass cancelled most of w
+    const dim3 g1(kMdotBlocks, (j + 2 + kMdotVec - 1) / kMdotVec);
+    const dim3 g2(kMdotBlocks, (j + 1 + kMdotVec - 1) / kMdotVec);
+    k_mdot_partial<<<g1, kSB, 0, st>>>(V, j + 1, w, n, 1, nullptr, partial);
+    k_sum_partials<<<j + 2, kSB, 0, st>>>(partial, kMdotBlocks, j + 2, nullptr, dout);
+    k_msub<<<blocks(n), kSB, 0, st>>>(V, j + 1, dout, nullptr, w, n);
+    k_reorth_gate<<<1, 64, 0, st>>>(dout, j + 1, flag, flag + 1);
+    k_mdot_partial<<<g2, kSB, 0, st>>>(V, j + 1, w, n, 0, flag, partial);
+    k_sum_partials<<<j + 1, kSB, 0, st>>>(partial, kMdotBlocks, j + 1, flag, dout);
+    k_msub<<<blocks(n), kSB, 0, st>>>(V, j + 1, dout, flag, w, n);
     if (j == msteps - 1) break;
     const double b = std::sqrt(dot_dev(w, w, n, partial, dout, st));
     if (!std::isfinite(b)) throw Error(MSLM_EHIP, "Lanczos: a non-finite residual norm");
@@ -606,29 +682,31 @@ Spectral bethe_hessian_run(const GraphDev &gd, hipStream_t st, double omega, dou
   (void)hipEventDestroy(e1);
   out.steps = steps;
   if (K > steps) throw Error(MSLM_EUNSUPPORTED, "the Krylov space closed before k vectors");
-  // the tridiagonal matrix, its eigenpairs (one workgroup), the K smallest
-  std::vector<double> Th((size_t)steps * steps, 0.0);
-  for (int i = 0; i < steps; i++) {
-    Th[(size_t)i * steps + i] = alpha[i];
-    if (i + 1 < steps) {
-      Th[(size_t)i * steps + i + 1] = beta[i + 1];
-      Th[(size_t)(i + 1) * steps + i] = beta[i + 1];
-    }
-  }
-  double *T = bT.get((int64_t)steps * steps);
+  // the tridiagonal matrix's eigenpairs (one workgroup), the K smallest
+  double *T = bT.get(2 * (int64_t)steps);
   double *Z = bZ.get((int64_t)steps * steps);
   double *eval = beval.get(steps);
   int *order = bord.get(steps);
-  int *sw = bsw.get(1);
-  h2d_raw(T, Th.data(), sizeof(double) * Th.size(), st);
-  k_jacobi<<<1, kJacobiThreads, 0, st>>>(T, Z, steps, 1e-15, 60, order, eval, sw);
+  int *sw = flag + 2;
+  // scaled by a power of two (exact) to entries of magnitude at most 1
+  double big = 0.0;
+  for (int i = 0; i < steps; i++) big = std::max(big, std::fabs(alpha[i]));
+  for (int i = 1; i < steps; i++) big = std::max(big, std::fabs(beta[i]));
+  const int ex = big > 0.0 ? std::ilogb(big) + 1 : 0;
+  std::vector<double> tri(2 * (size_t)steps, 0.0);
+  for (int i = 0; i < steps; i++) tri[i] = std::ldexp(alpha[i], -ex);
+  for (int i = 1; i < steps; i++) tri[steps + i - 1] = std::ldexp(beta[i], -ex);
+  h2d_raw(T, tri.data(), sizeof(double) * tri.size(), st);
+  k_tridiag_qr<<<1, kQrThreads, 0, st>>>(T, T + steps, steps, 30 * steps, Z, eval, order, sw);
   std::vector<double> ev(steps);
   std::vector<int> ord(steps);
   d2h_raw(ev.data(), eval, sizeof(double) * steps, st);
   d2h_raw(ord.data(), order, sizeof(int) * steps, st);
   d2h_raw(&out.sweeps, sw, sizeof(int), st);
+  d2h_raw(&out.second_passes, flag + 1, sizeof(int), st);
   MSLM_HIP(hipStreamSynchronize(st));
-  for (int c = 0; c < K; c++) eigenvalues[c] = ev[ord[c]];
+  if (out.sweeps < 0) throw Error(MSLM_EHIP, "the tridiagonal eigensolver did not converge");
+  for (int c = 0; c < K; c++) eigenvalues[c] = std::ldexp(ev[ord[c]], ex);
   double *Y = bY.get(n * K);
   k_ritz<<<blocks(n), kSB, 0, st>>>(V, steps, Z, steps, order, K, n, Y);
   // residuals ||H y - lambda y|| of the returned pairs
@@ -750,7 +828,8 @@ mslm_status mslm_bethe_hessian(mslm_graph *g, const mslm_spectral_params *p, dou
       res->r = s.r;
       res->residual_max = s.residual_max;
       res->lanczos_steps = s.steps;
-      res->jacobi_sweeps = s.sweeps;
+      res->tridiagonal_steps = s.sweeps;
+      res->second_passes = s.second_passes;
       res->kmeans_iterations = s.km_iters;
       res->spmv_ms = s.ms_spmv;
       res->spmv_launches = s.spmv_launches;

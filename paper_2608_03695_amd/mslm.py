@@ -100,8 +100,8 @@ class SpectralParams(C.Structure):
 
 class SpectralResult(C.Structure):
     _fields_ = [("r", C.c_double), ("residual_max", C.c_double), ("lanczos_steps", C.c_int32),
-                ("jacobi_sweeps", C.c_int32), ("kmeans_iterations", C.c_int32),
-                ("reserved", C.c_int32), ("spmv_ms", C.c_double), ("spmv_launches", C.c_int64),
+                ("tridiagonal_steps", C.c_int32), ("kmeans_iterations", C.c_int32),
+                ("second_passes", C.c_int32), ("spmv_ms", C.c_double), ("spmv_launches", C.c_int64),
                 ("ms_total", C.c_double)]
 
     def as_dict(self):

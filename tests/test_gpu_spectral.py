@@ -91,6 +91,26 @@ def test_eigenpairs_match_oracle(name, make, omega, cm, po):
         s = np.linalg.svd(Y.T @ V[:, :k], compute_uv=False)
         assert s.min() > 1 - 1e-6
     assert np.allclose(Y.T @ Y, np.eye(k), atol=1e-8)
+    assert res["tridiagonal_steps"] > 0
+    assert 0 <= res["second_passes"] <= res["lanczos_steps"]
+
+
+def test_full_krylov_space_takes_second_passes():
+    """Lanczos run to (nearly) the whole space: late vectors lose most of their norm to the
+    projection, so the second Gram-Schmidt pass is taken, and the eigenpairs still equal a
+    dense eigensolver's."""
+    tg = gen.planted_partition(40, 2, 2, 0.3, 0.05, 0.0, seed=3)
+    n = tg.n_supra
+    g = _handle(tg, F(1), None, False)
+    ev, Y, _, res = g.bethe_hessian(6, lanczos_steps=n, labels=False)
+    g.close()
+    H, _ = _oracle_H(tg, F(1), None, False, None)
+    w = np.linalg.eigvalsh(H.toarray())
+    scale = abs(H).sum(axis=1).max()
+    assert res["second_passes"] > 0
+    assert np.max(np.abs(ev - w[:6])) <= 1e-10 * scale, (ev, w[:6])
+    assert res["residual_max"] <= 1e-9 * scale
+    assert np.allclose(Y.T @ Y, np.eye(6), atol=1e-10)
 
 
 def test_r_one_is_the_laplacian():
