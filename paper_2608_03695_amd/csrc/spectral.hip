@@ -31,8 +31,8 @@ namespace {
 
 constexpr int kSB = 256;          // threads per block
 constexpr int kDotBlocks = 512;   // fixed grid of the reductions
-constexpr int kMdotBlocks = 512;  // row ranges of the reorthogonalisation dot products
-constexpr int kMdotVec = 8;       // vectors per pass over a block's rows
+constexpr int kMdotBlocks = 1024; // row ranges of the reorthogonalisation dot products
+constexpr int kMdotVec = 4;       // vectors per block (a timing sweep of 4/8/16)
 constexpr int kMaxK = 32;         // eigenvectors / clusters
 constexpr int kMaxSteps = 256;    // Krylov dimension
 constexpr int kFixShift = 40;     // fixed-point scale of the k-means sums
@@ -158,8 +158,8 @@ __global__ void k_lanczos_sub(double *w, const double *vj, const double *vp, dou
 
 // partial[b * stride + i] = block b's share of V_i . w for i < cnt and, with norm, of w . w at
 // i = cnt (stride = cnt + norm; V column-major, n per vector).  Block (b, y) takes the
-// contiguous row range b and the eight vectors 8y..8y+7 (a grid of kMdotBlocks x
-// ceil(stride / 8) blocks): many short blocks keep enough loads in flight.
+// contiguous row range b and the four vectors 4y..4y+3 (a grid of kMdotBlocks x
+// ceil(stride / 4) blocks): many short blocks keep enough loads in flight.
 __global__ __launch_bounds__(kSB) void k_mdot_partial(const double *V, int cnt, const double *w,
                                                      int64_t n, int norm, const int *gate,
                                                      double *partial) {
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kSB) void k_mdot_partial(const double *V, int cnt, 
       else if (i == cnt && norm) s[u] += wk * wk;
     }
   }
-  // the eight sums of the block: wave shuffles, then the four waves in index order
+  // the block's sums: wave shuffles, then the four waves in index order
 #pragma unroll
   for (int u = 0; u < kMdotVec; u++) {
     double v = s[u];
