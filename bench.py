@@ -10,6 +10,7 @@ already resident in HBM.  Prints one JSON line (see the keys below).
     python bench.py --workload cfg5 [--requests 1000]      # served Poisson trace vs plain FIFO
     python bench.py --workload sweep                      # doubling N, edges, T (Table 1 SBMs)
     python bench.py --workload spectral [--spectral-graph cfg2|cfg3]   # Bethe-Hessian pathway
+    python bench.py --workload long                       # windowed Patent/School-shaped runs
     python bench.py --copy-calibration                     # 3 plain 1 GiB device copies
 
 The default workload is config 3 (T=64 x N=1M DC-SBM, omega=1/2), the largest instance that
@@ -453,6 +454,51 @@ def bench_spectral(args):
                          "traffic": None}}
 
 
+def bench_long(args):
+    """Windowed optimisation (Section 4, the School case) of the two long sequences shaped like
+    Table 1's Patent (T = 891) and School (T = 7375), present-only coupling, windows of 64
+    snapshots overlapping by 8, 2 iterations per window.  The windowed entry takes host edge
+    lists, so each window's upload and supra-CSR build are inside the timed region."""
+    import hashlib
+
+    import numpy as np
+    from paper_2608_03695_amd import gen
+    spec = gen.LONG_SOLVE
+    w, o = gen.LONG_WINDOW
+    graphs = {name: gen.long_graph(name) for name in gen.LONG_SHAPES}
+    import torch
+    from paper_2608_03695_amd import mslm
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    stream = torch.cuda.current_stream()
+    kw = dict(gamma=spec.gamma, max_levels=spec.max_levels, max_iterations=spec.max_iterations,
+              seed=spec.seed, present_only=True, stream=stream)
+    rows = {}
+    for name, tg in graphs.items():
+        for _ in range(args.warmup):
+            mslm.leiden_windowed(tg, spec.omega, w, o, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            memb, res = mslm.leiden_windowed(tg, spec.omega, w, o, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        sha = hashlib.sha256(np.ascontiguousarray(memb, dtype=np.int32).tobytes()).hexdigest()
+        rows[name] = dict(N=tg.n_nodes, T=tg.n_slices, edges=int(tg.n_edges),
+                          windows=res["windows"], ms=ms, ms_per_window=ms / res["windows"],
+                          n_communities=res["n_communities"], sha256=sha)
+        log(f"{name}: {rows[name]}")
+    return {"metric": "windowed solve time of the long sequences (Table 1 shapes)",
+            "value": rows["patent"]["ms"], "unit": "ms per solve (Patent shape)", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": "long_sequences_patent_school_windowed",
+                       "gamma": str(spec.gamma), "omega": str(spec.omega), "window": w,
+                       "overlap": o, "present_only": True,
+                       "iterations": spec.max_iterations},
+            "shapes": rows}
+
+
 def copy_calibration():
     """Three plain 1 GiB device-to-device copies (2^30 bytes read and 2^30 written each): the
     run that calibrates the FETCH_SIZE / WRITE_SIZE counters under rocprofv3 --pmc."""
@@ -507,9 +553,9 @@ def main():
         copy_calibration()
         return
 
-    if args.workload in ("cfg4", "cfg5", "sweep", "spectral"):
+    if args.workload in ("cfg4", "cfg5", "sweep", "spectral", "long"):
         out = {"cfg4": bench_batched, "cfg5": bench_served, "sweep": bench_sweep,
-               "spectral": bench_spectral}[args.workload](args)
+               "spectral": bench_spectral, "long": bench_long}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     # inputs are drawn before anything touches the GPU (the generator may use child processes)

@@ -6,7 +6,6 @@
 #include <cstring>
 #include <memory>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/mslm.h"
@@ -55,7 +54,7 @@ mslm_status mslm_create(const mslm_graph_desc *desc, void *hip_stream, mslm_grap
   *out = nullptr;
   mslm_status s = api_check_desc(desc);
   if (s != MSLM_OK) return s;
-  std::unique_ptr<mslm_graph> h(new mslm_graph());
+  std::unique_ptr<mslm_graph, void (*)(mslm_graph *)> h(new mslm_graph(), mslm_destroy);
   h->st = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&h->device) != hipSuccess) return fail(MSLM_EHIP, "no HIP device");
   try {
@@ -199,10 +198,23 @@ mslm_status mslm_leiden_windowed(const mslm_graph_desc *desc, const mslm_params 
       return fail(MSLM_EINVAL, "slice_offsets must be non-decreasing");
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = (int64_t)N * T;
+  // global labels are dense ids 0..fresh-1 (at most n); window labels are canonical ids
+  // below the window's size: the stitching maps are plain arrays, reset after each window
   std::vector<int64_t> glob(n, -1);
+  std::vector<int32_t> first_copy(n, -1);   // global label -> first overlap copy of a window
   int64_t fresh = 0;
   int windows = 0;
   int32_t prev_end = 0;
+  // one handle for every window: its graph is rebuilt in place and its workspace kept, so
+  // device buffers are allocated once for the largest window rather than once per window
+  std::unique_ptr<mslm_graph, void (*)(mslm_graph *)> h(new mslm_graph(), mslm_destroy);
+  h->st = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&h->device) != hipSuccess) return fail(MSLM_EHIP, "no HIP device");
+  try {
+    h->ws = workspace_new();
+  } catch (const std::exception &e) {
+    return fail(MSLM_ENOMEM, e.what());
+  }
   for (int32_t s0 = 0;;) {
     const int32_t s1 = std::min(T, s0 + window);
     const int32_t ov = windows == 0 ? 0 : prev_end - s0;   // overlapping snapshots
@@ -220,47 +232,58 @@ mslm_status mslm_leiden_windowed(const mslm_graph_desc *desc, const mslm_params 
     if (ov > 0) {   // the overlapping copies' labels so far, as labels of this window
       init.resize(nw);
       for (int64_t v = 0; v < nw; v++) init[v] = (int32_t)v;
-      std::unordered_map<int64_t, int32_t> seen;
+      const int64_t *gl = glob.data() + (int64_t)s0 * N;
       for (int64_t v = 0; v < (int64_t)ov * N; v++) {
-        const int64_t lab = glob[(int64_t)s0 * N + v];
-        auto it = seen.find(lab);
-        if (it == seen.end()) it = seen.emplace(lab, (int32_t)v).first;
-        init[v] = it->second;
+        int32_t &f = first_copy[gl[v]];
+        if (f < 0) f = (int32_t)v;
+        init[v] = f;
       }
+      for (int64_t v = 0; v < (int64_t)ov * N; v++) first_copy[gl[v]] = -1;
     }
     mslm_params p = *params;
     p.gamma_slices = params->gamma_slices ? params->gamma_slices + 2 * (int64_t)s0 : nullptr;
     p.initial_membership = ov > 0 ? init.data() : nullptr;
     p.flags &= ~(uint32_t)(MSLM_OUTPUT_ON_DEVICE | MSLM_PROFILE | MSLM_COUNT);
-    mslm_graph *g = nullptr;
-    mslm_status st = mslm_create(&sub, hip_stream, &g);
+    mslm_status st = api_check_desc(&sub);
     if (st != MSLM_OK) return st;
+    try {
+      h->g.omega_num = sub.omega_num;
+      h->g.omega_den = sub.omega_den;
+      build_graph(h->g, sub, h->st, h->ws);
+      MSLM_HIP(hipStreamSynchronize(h->st));
+    } catch (const Error &e) {
+      return fail(e.status, e.what());
+    } catch (const std::exception &e) {
+      return fail(MSLM_ENOMEM, e.what());
+    }
     std::vector<int32_t> m(nw);
-    st = mslm_leiden(g, &p, m.data(), nullptr);
-    mslm_destroy(g);
+    st = mslm_leiden(h.get(), &p, m.data(), nullptr);
     if (st != MSLM_OK) return st;
-    std::unordered_map<int32_t, int64_t> label_of;
-    for (int64_t v = 0; v < (int64_t)ov * N; v++)   // communities holding overlapping copies
-      label_of.emplace(m[v], glob[(int64_t)s0 * N + v]);
+    std::vector<int64_t> label_of(nw, -1);   // window label -> global label
+    for (int64_t v = 0; v < (int64_t)ov * N; v++) {   // communities holding overlapping copies
+      int64_t &l = label_of[m[v]];
+      if (l < 0) l = glob[(int64_t)s0 * N + v];
+    }
     for (int64_t v = (int64_t)ov * N; v < nw; v++) {
-      auto it = label_of.find(m[v]);
-      if (it == label_of.end()) it = label_of.emplace(m[v], fresh++).first;
-      glob[(int64_t)s0 * N + v] = it->second;
+      int64_t &l = label_of[m[v]];
+      if (l < 0) l = fresh++;
+      glob[(int64_t)s0 * N + v] = l;
     }
     windows++;
     prev_end = s1;
     if (s1 == T) break;
     s0 = s1 - overlap;
   }
-  std::unordered_map<int64_t, int32_t> first;   // labels by first appearance
+  std::vector<int32_t> first(fresh, -1);   // labels by first appearance
+  int32_t ncomm = 0;
   for (int64_t v = 0; v < n; v++) {
-    auto it = first.find(glob[v]);
-    if (it == first.end()) it = first.emplace(glob[v], (int32_t)first.size()).first;
-    membership[v] = it->second;
+    int32_t &f = first[glob[v]];
+    if (f < 0) f = ncomm++;
+    membership[v] = f;
   }
   if (res) {
     res->windows = windows;
-    res->n_communities = (int32_t)first.size();
+    res->n_communities = ncomm;
     res->ms_total =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -4,14 +4,15 @@ Runs only the oracle (oracle/), never the HIP library: for each workload it reco
 sha256 of the oracle's int32 membership, its Q components and schedule statistics.  The
 GPU parity tests compare the HIP path's output against these files.
 
-    python tests/golden/make_expected.py [cfg2] [cfg3] [cfg4] [sweep]
+    python tests/golden/make_expected.py [cfg2] [cfg3] [cfg4] [sweep] [long]
 
 Config 3 needs about 45 GB of host memory and tens of minutes on 8 threads.  cfg4 records the
 oracle's digest (sha256 of the int32 membership and the int64 Q components) and statistics of
 every solve of the batched workload's grid (gamma in {1/2, 1, 2} x omega in {1/10, 1, 10}) on
 every 8th of its 512 graphs: 576 solves, run in parallel processes.  sweep records the same
 digests for the four SBM shapes of the doubling study (Table 1) under the multislice and the
-global null model.
+global null model.  long records the windowed solves of the two long sequences shaped like
+Table 1's Patent and School (present-only coupling): the sha256 of the int32 labels.
 """
 import hashlib
 import json
@@ -25,6 +26,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
+from oracle import windows  # noqa: E402
 from paper_2608_03695_amd import gen  # noqa: E402
 
 WORKLOADS = {
@@ -97,6 +99,31 @@ def make_sweep():
         json.dump(out, f, indent=1)
 
 
+def make_long():
+    spec = gen.LONG_SOLVE
+    w, o = gen.LONG_WINDOW
+    out = dict(workload="long sequences shaped like Table 1's Patent and School",
+               gamma=str(spec.gamma), omega=str(spec.omega), max_levels=spec.max_levels,
+               max_iterations=spec.max_iterations, seed=spec.seed, window=w, overlap=o,
+               present_only=True, solves=[])
+    for name in gen.LONG_SHAPES:
+        tg = gen.long_graph(name)
+        t0 = time.time()
+        memb, nw = windows.leiden_windowed(tg, spec.omega, w, o, gamma=spec.gamma,
+                                           max_levels=spec.max_levels,
+                                           max_iterations=spec.max_iterations, seed=spec.seed,
+                                           present_only=True)
+        sha = hashlib.sha256(np.ascontiguousarray(memb, dtype=np.int32).tobytes()).hexdigest()
+        out["solves"].append(dict(shape=name, graph=tg.name, n_nodes=tg.n_nodes,
+                                  n_slices=tg.n_slices, n_edges=int(tg.n_edges), windows=nw,
+                                  n_communities=int(memb.max()) + 1, sha256=sha,
+                                  oracle_s=round(time.time() - t0, 1)))
+        print(name, out["solves"][-1]["oracle_s"], "s", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "long_expected.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+
+
 def main(names):
     for name in names:
         if name == "cfg4":
@@ -104,6 +131,9 @@ def main(names):
             continue
         if name == "sweep":
             make_sweep()
+            continue
+        if name == "long":
+            make_long()
             continue
         make, spec = WORKLOADS[name]
         t0 = time.time()

@@ -68,3 +68,33 @@ def test_windowed_refusals():
         with pytest.raises(mslm.MslmError) as e:
             mslm.leiden_windowed(tg, 1, W, o)
         assert e.value.status == mslm.MSLM_EINVAL
+
+
+def _long_record():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "long_expected.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("shape", list(gen.LONG_SHAPES))
+def test_long_sequences_equal_oracle_record(shape):
+    """The two long sequences shaped like Table 1's Patent (T = 891) and School (T = 7375),
+    windowed with present-only coupling, against the oracle's record
+    (tests/golden/make_expected.py long)."""
+    import hashlib
+    mslm = _mslm()
+    rec = _long_record()
+    want = next(s for s in rec["solves"] if s["shape"] == shape)
+    spec = gen.LONG_SOLVE
+    tg = gen.long_graph(shape)
+    assert tg.name == want["graph"] and int(tg.n_edges) == want["n_edges"]
+    gm, res = mslm.leiden_windowed(tg, spec.omega, rec["window"], rec["overlap"],
+                                   gamma=spec.gamma, max_levels=spec.max_levels,
+                                   max_iterations=spec.max_iterations, seed=spec.seed,
+                                   present_only=True)
+    assert res["windows"] == want["windows"]
+    assert res["n_communities"] == want["n_communities"]
+    assert hashlib.sha256(np.ascontiguousarray(gm, dtype=np.int32).tobytes()).hexdigest() == \
+        want["sha256"]
