@@ -148,3 +148,22 @@ def test_invalid_spectral_arguments():
     with pytest.raises(mslm.MslmError):
         mslm.kmeans(np.zeros((3, 2)), 4)
     g.close()
+
+
+@pytest.mark.parametrize("T,N,omega", [(1, 200, F(0)), (2, 100, F(1, 100))])
+def test_path_laplacian_closed_form(T, N, omega):
+    """H(1) = D - A of a path of N nodes has the eigenvalues 2 - 2 cos(pi k / N), k = 0..N-1;
+    two copies of the path coupled node to node with weight omega add the coupling Laplacian's
+    eigenvalues {0, 2 omega}.  With the Krylov space run to the whole space, the smallest eight
+    must equal these closed forms (a pin of the operator, the Lanczos recurrence and the
+    tridiagonal eigensolver that does not go through another eigensolver)."""
+    path = [(i, i + 1) for i in range(N - 1)]
+    tg = gen.from_edge_lists(N, [path] * T)
+    g = _handle(tg, omega, None, False)
+    n = N * T
+    ev, _, _, res = g.bethe_hessian(8, r=1.0, lanczos_steps=n, labels=False)
+    g.close()
+    lam = 2.0 - 2.0 * np.cos(np.pi * np.arange(N) / N)
+    want = np.sort(np.concatenate([lam + 2.0 * float(omega) * c for c in range(T)]))[:8]
+    assert res["lanczos_steps"] <= n
+    assert np.max(np.abs(ev - want)) < 1e-10, (ev, want)
