@@ -467,10 +467,23 @@ __global__ void k_km_assign(const double *P, int64_t n, int dim, const double *C
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool ch = false;
   if (v < n) {
+    // the point's coordinates are loaded once (registers), then compared with every centroid;
+    // the distance is the same sum in the same order as sqdist
+    double p[kMaxK];
+#pragma unroll
+    for (int j = 0; j < kMaxK; j++) p[j] = j < dim ? P[v * dim + j] : 0.0;
     double best = INFINITY;
     int lab = 0;
     for (int c = 0; c < k; c++) {
-      const double d = sqdist(P + v * dim, C + c * dim, dim);
+      const double *cc = C + c * dim;
+      double d = 0.0;
+#pragma unroll
+      for (int j = 0; j < kMaxK; j++) {
+        if (j < dim) {
+          const double t = p[j] - cc[j];
+          d = d + t * t;
+        }
+      }
       if (d < best) {
         best = d;
         lab = c;
@@ -496,8 +509,10 @@ __global__ void k_km_accum(const int64_t *Q, const int32_t *labels, int64_t n, i
   }
   for (int i = threadIdx.x; i < k; i += blockDim.x) lc[i] = 0ull;
   __syncthreads();
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) {
+  // a grid-stride share per block (a few hundred blocks), so the global atomics below stay
+  // few per address
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
     const int c = labels[v];
     atomicAdd(&lc[c], 1ull);
     for (int j = 0; j < dim; j++) {
@@ -587,7 +602,8 @@ int kmeans_dev(const double *P, int64_t n, int dim, int k, int max_iter, int32_t
   for (it = 1; it <= max_iter; it++) {
     MSLM_HIP(hipMemsetAsync(acc, 0, sizeof(unsigned long long) * (2 * k * dim + k + 1), st));
     k_km_assign<<<blocks(n), kSB, 0, st>>>(P, n, dim, C, k, labels, changed);
-    k_km_accum<<<blocks(n), kSB, 0, st>>>(Q, labels, n, dim, k, Sh, Sl, cnt);
+    k_km_accum<<<std::min<unsigned>(blocks(n), kDotBlocks), kSB, 0, st>>>(Q, labels, n, dim, k,
+                                                                         Sh, Sl, cnt);
     k_km_centroids<<<blocks(k * dim), kSB, 0, st>>>(Sh, Sl, cnt, k, dim, C);
     unsigned long long h = 0;
     d2h_raw(&h, changed, sizeof(h), st);
