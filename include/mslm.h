@@ -310,8 +310,11 @@ mslm_status mslm_leiden_windowed(const mslm_graph_desc *desc, const mslm_params 
 /* The Bethe-Hessian pathway of Section 3.1 (the paragraphs after Eq. 4) on a resident graph:
  * H(r) = (r^2 - 1) I - r A + D with A the supra-adjacency of Eq. 3 (intra weights, coupling
  * omega * c_sr) and D its weighted degrees; the k algebraically smallest eigenpairs of H (its
- * informative, negative end) by Lanczos with full reorthogonalisation in float64; k-means of
- * the n = N*T rows of the eigenvector embedding into k clusters.
+ * informative, negative end) by Lanczos with full reorthogonalisation in float64 (classical
+ * Gram-Schmidt against every Lanczos vector, a second pass when the first removed more than half
+ * of the vector's squared norm), the small tridiagonal matrix's eigenpairs by implicit QR steps
+ * with the Wilkinson shift, Ritz vectors; k-means of the n = N*T rows of the eigenvector
+ * embedding into k clusters.
  *   k                  eigenvectors and clusters, 1..32 and below n
  *   lanczos_steps      Krylov dimension m, k..min(256, n) (0: min(n, 256, max(4k, k + 152));
  *                      without restarts the returned pairs converge only when m is large enough
