@@ -5,7 +5,7 @@ refinement round, aggregation, split and the Q components) on a supra-graph that
 already resident in HBM.  Prints one JSON line (see the keys below).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3|cfg2|cfg1]
-                    [--no-cpu-baseline]
+                    [--null-model multislice|global] [--no-cpu-baseline]
     python bench.py --workload cfg4 [--graphs 512]         # batched grid vs plain calls
     python bench.py --workload cfg5 [--requests 1000]      # served Poisson trace vs plain FIFO
     python bench.py --workload sweep                      # doubling N, edges, T (Table 1 SBMs)
@@ -91,10 +91,15 @@ def host_cpu():
     return model, len(os.sched_getaffinity(0))
 
 
-def full_size_oracle(workload):
+NULL_MODELS = {"multislice": 0, "global": 1}
+
+
+def full_size_oracle(workload, null_model="multislice"):
     """The oracle's full-size solve time recorded with the committed expected result of this
     workload (taken once on a build host, not on the benchmark host), or None."""
-    path = os.path.join(ROOT, "tests", "golden", f"{workload.split('_')[0]}_expected.json")
+    suffix = "_global" if null_model == "global" else ""
+    path = os.path.join(ROOT, "tests", "golden",
+                        f"{workload.split('_')[0]}{suffix}_expected.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -124,15 +129,16 @@ def cpu_baseline(args):
     rp, col, w, raw, twom = og.csr()
     m_supra = int(rp[-1]) // 2
     t0 = time.perf_counter()
-    og.leiden(gamma, max_levels=32, max_iterations=2, seed=0)
+    og.leiden(gamma, max_levels=32, max_iterations=2, seed=0,
+              null_model=NULL_MODELS[args.null_model])
     dt = time.perf_counter() - t0
     model, avail = host_cpu()
     out = {"value": m_supra / dt, "unit": "supra-edges/s", "cores": oracle.num_threads(),
            "kind": "oracle",
            "sample": f"{tg.name}: {what}; {m_supra} supra-edges, one full solve "
-                     f"(2 iterations) in {dt:.1f} s",
+                     f"(2 iterations, {args.null_model} null model) in {dt:.1f} s",
            "host_cpu": model, "host_threads_available": avail}
-    full = full_size_oracle(args.workload)
+    full = full_size_oracle(args.workload, args.null_model)
     if full is not None:
         out["full_size_oracle"] = full
     return out
@@ -171,7 +177,7 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload, launches):
+def measured_traffic(workload, launches, null_model="multislice"):
     """HBM bytes per launch of the level-0 decision kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy), or None when the
     summary is for another workload or the kernel sources changed since it was taken."""
@@ -181,6 +187,8 @@ def measured_traffic(workload, launches):
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("workload") != workload or rec.get("sources_sha256") != kernel_sources_sha():
+        return None
+    if null_model != "multislice":   # the record is of the multislice solve
         return None
     if rec.get("launches") != launches:
         return None
@@ -519,6 +527,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--null-model", choices=sorted(NULL_MODELS), default="multislice",
+                    help="cfg1/cfg2/cfg3: the objective (multislice: Eq. 6; global: Eq. 5 over "
+                         "the supra-graph, the objective of the paper's GPU path)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true",
                     help="skip the profiled and the counting solve (keeps profiler traces to "
@@ -579,7 +590,7 @@ def main():
     info = g.info()
     m_supra = info["nnz"] // 2
     kw = dict(gamma=spec.gamma, max_levels=spec.max_levels, max_iterations=spec.max_iterations,
-              seed=spec.seed)
+              seed=spec.seed, null_model=NULL_MODELS[args.null_model])
     tuning = None
     if args.autotune:
         # result-invariant execution choices picked by timing solves (not part of a step)
@@ -624,7 +635,8 @@ def main():
         return (rc[pre + "_units"] * BYTES_UNIT
                 + rc[pre + "_entries"] * (BYTES_ENTRY + (BYTES_WEIGHT if weighted else 0))
                 + rc[pre + "_candidates"] * BYTES_CAND)
-    q = mslm.q_exact(results[-1]["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
+    qf = mslm.q_exact_global if args.null_model == "global" else mslm.q_exact
+    q = qf(results[-1]["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
     out = {
         "tuning": tuning,
         "metric": METRIC,
@@ -637,6 +649,7 @@ def main():
         "config": {"workload": tg.name, "n_nodes": tg.n_nodes, "n_slices": tg.n_slices,
                    "supra_nodes": info["n_supra"], "supra_edges": m_supra,
                    "gamma": str(spec.gamma), "omega": str(spec.omega),
+                   "null_model": args.null_model,
                    "max_levels": spec.max_levels, "max_iterations": spec.max_iterations},
         # the HBM-bound loop: level-0 local-moving decisions (every sweep of every iteration)
         "roofline": roofline(nbytes("lm0"), rp["lm0_kernel_ms"], rp["lm0_launches"],
@@ -662,7 +675,7 @@ def main():
     rl["copy_gbs"] = copy_gbs                 # a plain device copy on this GPU, same clock
     rl["frac_of_copy"] = rl["achieved"] / copy_gbs if copy_gbs else None
     rl["bytes_per_launch"] = rl["bytes_per_step"] / max(rl["launches_per_step"], 1)
-    t = measured_traffic(tg.name, rl["launches_per_step"])
+    t = measured_traffic(tg.name, rl["launches_per_step"], args.null_model)
     if t is not None:
         rl["traffic"] = t
         rl["traffic_gbs"] = t * rl["launches_per_step"] / (rl["kernel_ms_per_step"] * 1e-3) / 1e9

@@ -4,7 +4,8 @@ Runs only the oracle (oracle/), never the HIP library: for each workload it reco
 sha256 of the oracle's int32 membership, its Q components and schedule statistics.  The
 GPU parity tests compare the HIP path's output against these files.
 
-    python tests/golden/make_expected.py [cfg2] [cfg3] [cfg4] [sweep] [long]
+    python tests/golden/make_expected.py [cfg2] [cfg3] [cfg2_global] [cfg3_global] [cfg4]
+                                         [sweep] [long]
 
 Config 3 needs about 45 GB of host memory and tens of minutes on 8 threads.  cfg4 records the
 oracle's digest (sha256 of the int32 membership and the int64 Q components) and statistics of
@@ -33,6 +34,9 @@ WORKLOADS = {
     "cfg2": (lambda: gen.config2(8), gen.CONFIG_SOLVE[2]),
     "cfg3": (lambda: gen.config3(8), gen.CONFIG_SOLVE[3]),
 }
+# the same graphs and constants under the global null model (Eq. 5, the objective of the
+# paper's GPU path): records cfg2_global_expected.json, cfg3_global_expected.json
+GLOBAL = {"cfg2_global": "cfg2", "cfg3_global": "cfg3"}
 
 
 CFG4_GRAPHS = range(0, 512, 8)
@@ -135,7 +139,8 @@ def main(names):
         if name == "long":
             make_long()
             continue
-        make, spec = WORKLOADS[name]
+        nm = 1 if name in GLOBAL else 0
+        make, spec = WORKLOADS[GLOBAL.get(name, name)]
         t0 = time.time()
         tg = make()
         t1 = time.time()
@@ -147,11 +152,13 @@ def main(names):
         og._keep = None
         t2 = time.time()
         memb, comps, st = og.leiden(spec.gamma, max_levels=spec.max_levels,
-                                    max_iterations=spec.max_iterations, seed=spec.seed)
+                                    max_iterations=spec.max_iterations, seed=spec.seed,
+                                    null_model=nm)
         t3 = time.time()
-        q = oracle.q_from_components(comps, meta["n_nodes"], meta["n_slices"], spec.gamma,
-                                     spec.omega)
-        out = dict(workload=meta["name"], n_nodes=meta["n_nodes"], n_slices=meta["n_slices"],
+        qf = oracle.q_global_from_components if nm == 1 else oracle.q_from_components
+        q = qf(comps, meta["n_nodes"], meta["n_slices"], spec.gamma, spec.omega)
+        out = dict(workload=meta["name"], null_model=nm, n_nodes=meta["n_nodes"],
+                   n_slices=meta["n_slices"],
                    n_edges=int(meta["n_edges"]), gamma=str(spec.gamma), omega=str(spec.omega),
                    max_levels=spec.max_levels, max_iterations=spec.max_iterations, seed=spec.seed,
                    membership_sha256=hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest(),

@@ -2,7 +2,8 @@
 calls only the oracle):
 
 * config 3 (T=64 x N=1M DC-SBM, exponent 2.1, mu 0.4, omega 1/2): membership sha256, the 193 Q
-  components, Q as a reduced fraction and every schedule statistic;
+  components, Q as a reduced fraction and every schedule statistic, under the multislice
+  objective (Eq. 6) and under the global null model (Eq. 5);
 * the batched workload: every (gamma, omega) of the 3x3 grid on every 8th of its 512 graphs
   (576 solves) run as batched calls, each solve's membership and Q components against the
   oracle's digest and statistics;
@@ -54,6 +55,28 @@ def test_config3_full_size_matches_oracle_record():
     assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == exp["membership_sha256"]
     assert [int(x) for x in r["q_components"]] == exp["q_components"]
     q = mslm.q_exact(r["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
+    assert f"{q.numerator}/{q.denominator}" == exp["q"]
+    for k in STAT_KEYS:
+        assert r[k] == exp["stats"][k], k
+
+
+def test_config3_global_null_model_matches_oracle_record():
+    """Config 3 under the global null model (Eq. 5, the objective of the paper's GPU path)
+    against the oracle's record (cfg3_global_expected.json)."""
+    from paper_2608_03695_amd import mslm
+    exp = _golden("cfg3_global")
+    assert exp["null_model"] == 1
+    tg = fsi.load(fsi.cfg3_path())
+    assert tg.name == exp["workload"] and tg.n_edges == exp["n_edges"]
+    spec = gen.CONFIG_SOLVE[3]
+    g = mslm.Graph(tg, spec.omega)
+    memb, r = g.leiden(spec.gamma, max_levels=spec.max_levels,
+                       max_iterations=spec.max_iterations, seed=spec.seed,
+                       null_model=mslm.MSLM_NULL_GLOBAL)
+    g.close()
+    assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == exp["membership_sha256"]
+    assert [int(x) for x in r["q_components"]] == exp["q_components"]
+    q = mslm.q_exact_global(r["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
     assert f"{q.numerator}/{q.denominator}" == exp["q"]
     for k in STAT_KEYS:
         assert r[k] == exp["stats"][k], k

@@ -135,6 +135,31 @@ def test_config2_full_size_matches_oracle_record():
         assert r[k] == exp["stats"][k], k
 
 
+def test_config2_global_null_model_matches_oracle_record():
+    """Full-size config 2 under the global null model (Eq. 5, the objective of the paper's GPU
+    path) against the oracle's stored result (tests/golden/cfg2_global_expected.json)."""
+    import hashlib
+    import json
+    import os
+    mslm = _mslm()
+    path = os.path.join(os.path.dirname(__file__), "golden", "cfg2_global_expected.json")
+    exp = json.load(open(path))
+    assert exp["null_model"] == 1
+    tg = gen.config2()
+    spec = gen.CONFIG_SOLVE[2]
+    g = mslm.Graph(tg, spec.omega)
+    memb, r = g.leiden(spec.gamma, max_levels=spec.max_levels,
+                       max_iterations=spec.max_iterations, seed=spec.seed,
+                       null_model=mslm.MSLM_NULL_GLOBAL)
+    g.close()
+    assert hashlib.sha256(memb.astype(np.int32).tobytes()).hexdigest() == exp["membership_sha256"]
+    assert [int(x) for x in r["q_components"]] == exp["q_components"]
+    q = mslm.q_exact_global(r["q_components"], tg.n_slices, tg.n_nodes, spec.gamma, spec.omega)
+    assert f"{q.numerator}/{q.denominator}" == exp["q"]
+    for k in STAT_KEYS:
+        assert r[k] == exp["stats"][k], k
+
+
 def test_exact_comparisons_match_oracle():
     """The batched workload's graph 44 (N=214, T=26): its solves meet many pairs of targets
     whose double estimates cannot be told apart, settled by the 2304-bit evaluation.  The
