@@ -11,6 +11,7 @@ already resident in HBM.  Prints one JSON line (see the keys below).
     python bench.py --workload sweep                      # doubling N, edges, T (Table 1 SBMs)
     python bench.py --workload spectral [--spectral-graph cfg2|cfg3]   # Bethe-Hessian pathway
     python bench.py --workload long                       # windowed Patent/School-shaped runs
+    python bench.py --workload variants                   # objective/input variants, config 2
     python bench.py --copy-calibration                     # 3 plain 1 GiB device copies
 
 The default workload is config 3 (T=64 x N=1M DC-SBM, omega=1/2), the largest instance that
@@ -507,6 +508,62 @@ def bench_long(args):
             "shapes": rows}
 
 
+def bench_variants(args):
+    """The objective and input variants on config 2's graph (inputs resident, 1 warm-up and
+    --steps timed solves each): per-slice resolutions, the multislice CPM, a warm start from
+    the default solve's labels, categorical (all-to-all) coupling, and present-only coupling
+    on the graph with 20 % of the node copies absent."""
+    from paper_2608_03695_amd import gen
+    tg, spec = workload("cfg2", args.gen_workers, args.graph_cache)
+    tga = gen.with_absences(tg, 0.2, seed=1)
+    T = tg.n_slices
+    cat = [[0 if s == r else 1 for r in range(T)] for s in range(T)]
+    import torch
+    from paper_2608_03695_amd import mslm
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    stream = torch.cuda.current_stream()
+    base = dict(gamma=spec.gamma, max_levels=spec.max_levels,
+                max_iterations=spec.max_iterations, seed=spec.seed)
+    g = mslm.Graph(tg, spec.omega, stream=stream)
+    m0, _ = g.leiden(**base)
+    cases = [
+        ("multislice", g, base),
+        ("per_slice_gamma", g, dict(base, gamma_slices=[Fraction(1, 2), Fraction(1), Fraction(2)]
+                                    * (T // 3) + [Fraction(1)] * (T % 3))),
+        ("cpm", g, dict(base, gamma=Fraction(1, 1000), null_model=mslm.MSLM_NULL_CPM)),
+        ("warm_start", g, dict(base, initial=m0)),
+    ]
+    gc = mslm.Graph(tg, spec.omega, coupling=cat, stream=stream)
+    cases.append(("categorical_coupling", gc, base))
+    ga = mslm.Graph(tga, spec.omega, present_only=True, stream=stream)
+    cases.append(("present_only_20pct_absent", ga, base))
+    rows = {}
+    for name, h, kw in cases:
+        for _ in range(args.warmup):
+            h.leiden(**kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, r = h.leiden(**kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        m_supra = h.info()["nnz"] // 2
+        rows[name] = dict(ms=ms, supra_edges=m_supra, supra_edges_per_s=m_supra / (ms * 1e-3),
+                          n_communities=r["n_communities"], sweeps=r["sweeps"],
+                          levels=r["levels_run"])
+        log(f"{name}: {rows[name]}")
+    for h in (g, gc, ga):
+        h.close()
+    return {"metric": "supra-edge TEPS of the objective and input variants (config 2 graph)",
+            "value": rows["multislice"]["supra_edges_per_s"], "unit": "supra-edges/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": "variants_" + tg.name, "gamma": str(spec.gamma),
+                       "omega": str(spec.omega)},
+            "variants": rows}
+
+
 def copy_calibration():
     """Three plain 1 GiB device-to-device copies (2^30 bytes read and 2^30 written each): the
     run that calibrates the FETCH_SIZE / WRITE_SIZE counters under rocprofv3 --pmc."""
@@ -564,9 +621,10 @@ def main():
         copy_calibration()
         return
 
-    if args.workload in ("cfg4", "cfg5", "sweep", "spectral", "long"):
+    if args.workload in ("cfg4", "cfg5", "sweep", "spectral", "long", "variants"):
         out = {"cfg4": bench_batched, "cfg5": bench_served, "sweep": bench_sweep,
-               "spectral": bench_spectral, "long": bench_long}[args.workload](args)
+               "spectral": bench_spectral, "long": bench_long,
+               "variants": bench_variants}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     # inputs are drawn before anything touches the GPU (the generator may use child processes)
